@@ -1,0 +1,625 @@
+// SGP4 near-Earth oracle -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+//
+// A plain, serial, double-precision CPU implementation of what the GPU library
+// computes.  Only the test suite, the smoke check and the CPU-baseline leg of
+// the benchmark may load it; the product library never links, calls or falls
+// back to it, and the two share no source, header, table or helper.
+//
+// What it computes.  The paper (jaxsgp4, section 2.1 "Architecture and
+// Refactoring") re-implements the SGP4 general-perturbation model of Hoots &
+// Roehrich (Spacetrack Report No. 3, 1980) as revised by Hoots et al. (2004)
+// and Vallado et al. (2006, AIAA 2006-6753), with the WGS72 geopotential
+// constants, mapping a satellite's mean elements s and a time t to a TEME
+// state f(s, t) -> (r, v) (section 2.2, "Vectorisation").  The paper prints
+// none of the model's equations; the steps below restate the published
+// near-Earth model in the order it is defined (initialisation I1-I8, then
+// propagation P1-P9), written here from the mathematics, not from any listing.
+//
+// Readings where the paper is silent (each is listed in the design notes):
+//  * WGS72: mu = 398600.8 km^3/s^2, R = 6378.135 km, J2 = 0.001082616,
+//    J3 = -0.00000253881, J4 = -0.00000165597; ke = 60/sqrt(R^3/mu) 1/min.
+//  * Un-Kozai'd semi-major axis a0'' = (ke/n0'')^(2/3) (Vallado 2006 form).
+//  * Kepler: Newton on the generalised equation, start psi = U, step clamped to
+//    [-0.95, 0.95], stop after the first step with |step| < 1e-12 or after 10
+//    steps; sin/cos are then taken at the final iterate (the root).
+//  * Error codes (section 2.2 "Control Flow": anomalous states are computed and
+//    flagged, not exited): 1 mean eccentricity outside [-0.001, 1) (or e0
+//    outside [0, 1) at epoch), 2 mean motion n0'' not > 0, 4 semi-latus rectum
+//    p_L < 0, 6 decayed (r_k < 1 earth radius; state still written), 7 deep-space
+//    element set (period >= 225 min, section 6: near-Earth only).  Checks run
+//    in the order 1(epoch) -> 2 -> 7 -> 1 -> 4 -> 6; the first failing one
+//    wins.  Codes 1, 2, 4, 7 write NaN to r and v.
+//  * Checks are written so that NaN fails them (NaN never passes as valid).
+//  * Angles are reduced with floor to [0, 2*pi).
+//  * pow(x, 2/3) is cbrt(x)^2 and x^1.5 is x*sqrt(x).
+//  * J3/J2 is taken as 0 when J3 == 0 (two-body configuration); J3 != 0 with
+//    J2 == 0 is rejected.
+//
+// Agreement of these coefficients with the published model is parity
+// unpinned: no verification vectors are available.  The structure is pinned by
+// the CPU tests (two-body closed form, node equivariance, Kepler residual,
+// finite differences, radius bounds, first-order J2 rates, numerical
+// integration of the J2 field over one orbit, term-group toggles, crafted
+// error codes).
+//
+// The scalar type is a template parameter: double for values, Dual (seven
+// forward-mode tangents) for the derivative oracle, OpCount to count the
+// arithmetic the definition performs.  Build: g++ -O2 -std=c++17
+// -ffp-contract=off (no fast-math, no fused multiply-add contraction).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+constexpr int kNElem = 7;  // differentiated elements: n0, e0, i0, node0, argp0, M0, bstar
+
+// ---------------------------------------------------------------- scalars --
+inline double val(double x) { return x; }
+
+// Forward-mode dual number carrying derivatives w.r.t. the seven elements.
+struct Dual {
+  double v;
+  double d[kNElem];
+  Dual() : v(0) { std::memset(d, 0, sizeof d); }
+  Dual(double x) : v(x) { std::memset(d, 0, sizeof d); }  // NOLINT: implicit by design
+};
+inline double val(const Dual& x) { return x.v; }
+inline Dual operator+(const Dual& a, const Dual& b) { Dual r(a.v + b.v); for (int k = 0; k < kNElem; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+inline Dual operator-(const Dual& a, const Dual& b) { Dual r(a.v - b.v); for (int k = 0; k < kNElem; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+inline Dual operator-(const Dual& a) { Dual r(-a.v); for (int k = 0; k < kNElem; ++k) r.d[k] = -a.d[k]; return r; }
+inline Dual operator*(const Dual& a, const Dual& b) { Dual r(a.v * b.v); for (int k = 0; k < kNElem; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+inline Dual operator/(const Dual& a, const Dual& b) {
+  Dual r(a.v / b.v);
+  for (int k = 0; k < kNElem; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+  return r;
+}
+inline Dual operator+(const Dual& a, double b) { return a + Dual(b); }
+inline Dual operator+(double a, const Dual& b) { return Dual(a) + b; }
+inline Dual operator-(const Dual& a, double b) { return a - Dual(b); }
+inline Dual operator-(double a, const Dual& b) { return Dual(a) - b; }
+inline Dual operator*(const Dual& a, double b) { Dual r(a.v * b); for (int k = 0; k < kNElem; ++k) r.d[k] = a.d[k] * b; return r; }
+inline Dual operator*(double a, const Dual& b) { return b * a; }
+inline Dual operator/(const Dual& a, double b) { Dual r(a.v / b); for (int k = 0; k < kNElem; ++k) r.d[k] = a.d[k] / b; return r; }
+inline Dual operator/(double a, const Dual& b) { return Dual(a) / b; }
+inline Dual chain(const Dual& x, double fx, double dfx) { Dual r(fx); for (int k = 0; k < kNElem; ++k) r.d[k] = dfx * x.d[k]; return r; }
+inline Dual sin(const Dual& x) { return chain(x, std::sin(x.v), std::cos(x.v)); }
+inline Dual cos(const Dual& x) { return chain(x, std::cos(x.v), -std::sin(x.v)); }
+inline Dual sqrt(const Dual& x) { double s = std::sqrt(x.v); return chain(x, s, 0.5 / s); }
+inline Dual cbrt(const Dual& x) { double c = std::cbrt(x.v); return chain(x, c, 1.0 / (3.0 * c * c)); }
+inline Dual fabs(const Dual& x) { return x.v < 0 ? -x : x; }
+inline Dual atan2(const Dual& y, const Dual& x) {
+  double den = x.v * x.v + y.v * y.v;
+  Dual r(std::atan2(y.v, x.v));
+  for (int k = 0; k < kNElem; ++k) r.d[k] = (x.v * y.d[k] - y.v * x.d[k]) / den;
+  return r;
+}
+// x - 2*pi*floor(x / 2*pi): the floor is locally constant, so d/dx = 1.
+inline Dual mod2pi(const Dual& x) { Dual r = x; r.v = x.v - kTwoPi * std::floor(x.v / kTwoPi); return r; }
+
+// Operation-counting scalar: value in double, every arithmetic operation and
+// elementary function call counted once, by kind.
+struct OpTally { uint64_t add = 0, mul = 0, div = 0, sqrt = 0, cbrt = 0, trig = 0, atan2 = 0, floor = 0; };
+OpTally g_tally;
+struct OpCount {
+  double v;
+  OpCount() : v(0) {}
+  OpCount(double x) : v(x) {}  // NOLINT
+};
+inline double val(const OpCount& x) { return x.v; }
+inline OpCount operator+(const OpCount& a, const OpCount& b) { ++g_tally.add; return OpCount(a.v + b.v); }
+inline OpCount operator-(const OpCount& a, const OpCount& b) { ++g_tally.add; return OpCount(a.v - b.v); }
+inline OpCount operator-(const OpCount& a) { return OpCount(-a.v); }
+inline OpCount operator*(const OpCount& a, const OpCount& b) { ++g_tally.mul; return OpCount(a.v * b.v); }
+inline OpCount operator/(const OpCount& a, const OpCount& b) { ++g_tally.div; return OpCount(a.v / b.v); }
+inline OpCount operator+(const OpCount& a, double b) { return a + OpCount(b); }
+inline OpCount operator+(double a, const OpCount& b) { return OpCount(a) + b; }
+inline OpCount operator-(const OpCount& a, double b) { return a - OpCount(b); }
+inline OpCount operator-(double a, const OpCount& b) { return OpCount(a) - b; }
+inline OpCount operator*(const OpCount& a, double b) { return a * OpCount(b); }
+inline OpCount operator*(double a, const OpCount& b) { return OpCount(a) * b; }
+inline OpCount operator/(const OpCount& a, double b) { return a / OpCount(b); }
+inline OpCount operator/(double a, const OpCount& b) { return OpCount(a) / b; }
+inline OpCount sin(const OpCount& x) { ++g_tally.trig; return OpCount(std::sin(x.v)); }
+inline OpCount cos(const OpCount& x) { ++g_tally.trig; return OpCount(std::cos(x.v)); }
+inline OpCount sqrt(const OpCount& x) { ++g_tally.sqrt; return OpCount(std::sqrt(x.v)); }
+inline OpCount cbrt(const OpCount& x) { ++g_tally.cbrt; return OpCount(std::cbrt(x.v)); }
+inline OpCount fabs(const OpCount& x) { return OpCount(std::fabs(x.v)); }
+inline OpCount atan2(const OpCount& y, const OpCount& x) { ++g_tally.atan2; return OpCount(std::atan2(y.v, x.v)); }
+inline OpCount mod2pi(const OpCount& x) { ++g_tally.floor; g_tally.mul += 2; ++g_tally.add; return OpCount(x.v - kTwoPi * std::floor(x.v / kTwoPi)); }
+
+inline double mod2pi(double x) { return x - kTwoPi * std::floor(x / kTwoPi); }
+using std::atan2;
+using std::cbrt;
+using std::cos;
+using std::fabs;
+using std::sin;
+using std::sqrt;
+
+template <class S> inline S sq(const S& x) { return x * x; }
+template <class S> inline S cube(const S& x) { return x * x * x; }
+template <class S> inline S pow4(const S& x) { S x2 = x * x; return x2 * x2; }
+
+// ---------------------------------------------------------------- gravity --
+struct Gravity {
+  double mu, radius, j2, j3, j4;  // km^3/s^2, km, dimensionless zonals
+  double ke;                      // sqrt(mu/R^3) in 1/min: 60/sqrt(R^3/mu)
+  double j3oj2;                   // J3/J2, 0 when J3 == 0
+  double vkms;                    // earth radii per minute -> km/s: R*ke/60
+};
+
+// WGS72 geopotential constants (section 2.1: the paper uses WGS72).
+constexpr double kWgs72[5] = {398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597};
+
+int make_gravity(const double* g5, Gravity* g) {
+  const double* src = g5 ? g5 : kWgs72;
+  g->mu = src[0]; g->radius = src[1]; g->j2 = src[2]; g->j3 = src[3]; g->j4 = src[4];
+  if (!(g->mu > 0) || !(g->radius > 0)) return -6;
+  if (g->j2 == 0 && g->j3 != 0) return -6;
+  g->ke = 60.0 / std::sqrt(g->radius * g->radius * g->radius / g->mu);
+  g->j3oj2 = (g->j3 == 0) ? 0.0 : g->j3 / g->j2;
+  g->vkms = g->radius * g->ke / 60.0;
+  return 0;
+}
+
+// --------------------------------------------------------- initialisation --
+// Per-satellite constants of the near-Earth model (steps I1-I8).
+template <class S>
+struct Sat {
+  S n0, e0, i0, node0, argp0, M0, bstar;
+  double epoch;  // days relative to the caller's reference instant
+  S cosi, sini, beta0sq, beta0, c41, x1, x7;
+  S n0pp, a0pp, rp, hp, s, q4;
+  S xi, eta, C1, C2, C3, C4, C5;
+  S Mdot, argpdot, nodedot, nodedot1;
+  S argpcof, Mcof, nodecf, t2cof, aycof, Lcof, dM0, sinM0;
+  S D2, D3, D4, t3cof, t4cof, t5cof;
+  bool isimp = false, deep = false;
+  int epoch_code = 0;  // 1 when e0 is outside [0, 1)
+};
+
+template <class S>
+Sat<S> sgp4_init(const Gravity& g, const S el[kNElem], double epoch) {
+  Sat<S> c;
+  c.n0 = el[0]; c.e0 = el[1]; c.i0 = el[2]; c.node0 = el[3]; c.argp0 = el[4]; c.M0 = el[5]; c.bstar = el[6];
+  c.epoch = epoch;
+  const double R = g.radius, J2 = g.j2, J4 = g.j4, ke = g.ke, j3oj2 = g.j3oj2;
+  const S& n0 = c.n0; const S& e0 = c.e0;
+  if (!(val(e0) >= 0.0 && val(e0) < 1.0)) c.epoch_code = 1;
+
+  // I1: inclination and eccentricity functions.
+  c.cosi = cos(c.i0);
+  c.sini = sin(c.i0);
+  S th2 = c.cosi * c.cosi;
+  c.beta0sq = 1.0 - e0 * e0;
+  c.beta0 = sqrt(c.beta0sq);
+  c.c41 = 3.0 * th2 - 1.0;
+  c.x1 = 1.0 - th2;
+  c.x7 = 7.0 * th2 - 1.0;
+
+  // I2: recover the original (Brouwer) mean motion and semi-major axis from
+  // the Kozai mean motion of the element set.
+  S a1 = sq(cbrt(ke / n0));
+  S d1 = 0.75 * J2 * c.c41 / (c.beta0 * c.beta0sq);
+  S del1 = d1 / (a1 * a1);
+  S adel = a1 * (1.0 - del1 / 3.0 - del1 * del1 - (134.0 / 81.0) * del1 * del1 * del1);
+  S del0 = d1 / (adel * adel);
+  c.n0pp = n0 / (1.0 + del0);
+  c.a0pp = sq(cbrt(ke / c.n0pp));
+
+  // I3: perigee height selects the atmospheric density parameter s and q0-s.
+  c.rp = c.a0pp * (1.0 - e0);
+  c.hp = (c.rp - 1.0) * R;
+  c.s = S(1.0 + 78.0 / R);
+  c.q4 = S(pow4((120.0 - 78.0) / R));
+  if (val(c.hp) < 156.0) {
+    S sstar = c.hp - 78.0;
+    if (val(c.hp) < 98.0) sstar = S(20.0);
+    c.q4 = pow4((120.0 - sstar) / R);
+    c.s = 1.0 + sstar / R;
+  }
+
+  // I4: flags.  Deep space: period 2*pi/n0'' of 225 min or more.  Simplified
+  // drag: perigee below 220 km.
+  c.deep = (val(c.n0pp) > 0.0) && (kTwoPi / val(c.n0pp) >= 225.0);
+  c.isimp = val(c.rp) < 1.0 + 220.0 / R;
+
+  // I5: drag coefficients.
+  c.xi = 1.0 / (c.a0pp - c.s);
+  c.eta = c.a0pp * e0 * c.xi;
+  S eta2 = c.eta * c.eta;
+  S e0eta = e0 * c.eta;
+  S q = fabs(1.0 - eta2);
+  S coef = c.q4 * pow4(c.xi);
+  S coef1 = coef / (q * q * q * sqrt(q));
+  c.C2 = coef1 * c.n0pp *
+         (c.a0pp * (1.0 + 1.5 * eta2 + e0eta * (4.0 + eta2)) +
+          0.375 * J2 * c.xi / q * c.c41 * (8.0 + 3.0 * eta2 * (8.0 + eta2)));
+  c.C1 = c.bstar * c.C2;
+  c.C3 = S(0.0);
+  if (val(e0) > 1.0e-4) c.C3 = -2.0 * coef * c.xi * j3oj2 * c.n0pp * c.sini / e0;
+  c.C4 = 2.0 * c.n0pp * coef1 * c.a0pp * c.beta0sq *
+         (c.eta * (2.0 + 0.5 * eta2) + e0 * (0.5 + 2.0 * eta2) -
+          J2 * c.xi / (c.a0pp * q) *
+              (-3.0 * c.c41 * (1.0 - 2.0 * e0eta + eta2 * (1.5 - 0.5 * e0eta)) +
+               0.75 * c.x1 * (2.0 * eta2 - e0eta * (1.0 + eta2)) * cos(2.0 * c.argp0)));
+  c.C5 = 2.0 * coef1 * c.a0pp * c.beta0sq * (1.0 + 2.75 * (eta2 + e0eta) + e0eta * eta2);
+
+  // I6: secular rates of M, argument of perigee and node (J2, J2^2, J4).
+  S p0 = c.a0pp * c.beta0sq;
+  S p0sq = p0 * p0;
+  S T1 = 1.5 * J2 * c.n0pp / p0sq;
+  S T2 = 0.5 * T1 * J2 / p0sq;
+  S T3 = -(15.0 / 32.0) * J4 * c.n0pp / (p0sq * p0sq);
+  S th4 = th2 * th2;
+  c.Mdot = c.n0pp + 0.5 * T1 * c.beta0 * c.c41 + (1.0 / 16.0) * T2 * c.beta0 * (13.0 - 78.0 * th2 + 137.0 * th4);
+  c.argpdot = -0.5 * T1 * (1.0 - 5.0 * th2) + (1.0 / 16.0) * T2 * (7.0 - 114.0 * th2 + 395.0 * th4) +
+              T3 * (3.0 - 36.0 * th2 + 49.0 * th4);
+  c.nodedot1 = -T1 * c.cosi;
+  c.nodedot = c.nodedot1 + (0.5 * T2 * (4.0 - 19.0 * th2) + 2.0 * T3 * (3.0 - 7.0 * th2)) * c.cosi;
+
+  // I7: drag-on-angles and long-period (J3) coefficients.
+  c.argpcof = c.bstar * c.C3 * cos(c.argp0);
+  c.Mcof = S(0.0);
+  if (val(e0) > 1.0e-4) c.Mcof = -(2.0 / 3.0) * coef * c.bstar / e0eta;
+  c.nodecf = 3.5 * c.beta0sq * c.nodedot1 * c.C1;
+  c.t2cof = 1.5 * c.C1;
+  c.aycof = -0.5 * j3oj2 * c.sini;
+  S den = 1.0 + c.cosi;
+  if (std::fabs(val(den)) <= 1.5e-12) den = S(1.5e-12);
+  c.Lcof = -0.25 * j3oj2 * c.sini * (3.0 + 5.0 * c.cosi) / den;
+  c.dM0 = cube(1.0 + c.eta * cos(c.M0));
+  c.sinM0 = sin(c.M0);
+
+  // I8: higher-order drag terms (only when the simplified model is off).
+  c.D2 = c.D3 = c.D4 = c.t3cof = c.t4cof = c.t5cof = S(0.0);
+  if (!c.isimp) {
+    S C1sq = c.C1 * c.C1;
+    c.D2 = 4.0 * c.a0pp * c.xi * C1sq;
+    c.D3 = (4.0 / 3.0) * c.a0pp * c.xi * c.xi * (17.0 * c.a0pp + c.s) * C1sq * c.C1;
+    c.D4 = (2.0 / 3.0) * c.a0pp * c.a0pp * c.xi * c.xi * c.xi * (221.0 * c.a0pp + 31.0 * c.s) * C1sq * C1sq;
+    c.t3cof = c.D2 + 2.0 * C1sq;
+    c.t4cof = 0.25 * (3.0 * c.D3 + c.C1 * (12.0 * c.D2 + 10.0 * C1sq));
+    c.t5cof = 0.2 * (3.0 * c.D4 + 12.0 * c.C1 * c.D3 + 6.0 * c.D2 * c.D2 + 15.0 * C1sq * (2.0 * c.D2 + C1sq));
+  }
+  return c;
+}
+
+// ------------------------------------------------------------ propagation --
+// Intermediate values of one point, exposed for the structural pins.
+enum DetailIdx {
+  kD_M, kD_argp, kD_node, kD_a, kD_n, kD_e, kD_L, kD_axn, kD_ayn, kD_LT, kD_U, kD_psi, kD_iters, kD_resid,
+  kD_ecE, kD_esE, kD_eL2, kD_pL, kD_r, kD_rdot, kD_rfdot, kD_betaL, kD_sinu, kD_cosu, kD_u,
+  kD_k1, kD_k2, kD_rk, kD_uk, kD_nodek, kD_ik, kD_rdotk, kD_rfdotk, kD_code, kD_emargin, kD_COUNT
+};
+
+inline double wrap_pi(double x) { return x - kTwoPi * std::floor((x + kPi) / kTwoPi); }
+
+template <class S>
+int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3], double* det) {
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  auto fail = [&](int code) {
+    for (int k = 0; k < 3; ++k) { r[k] = S(nan); v[k] = S(nan); }
+    if (det) det[kD_code] = code;
+    return code;
+  };
+  if (det) for (int k = 0; k < kD_COUNT; ++k) det[k] = nan;
+  if (c.epoch_code) return fail(1);
+  if (!(val(c.n0pp) > 0.0)) return fail(2);
+  if (c.deep) return fail(7);
+
+  const double t = tsince;
+  const double t2 = t * t;
+  // P1: secular gravity.
+  S M_df = c.M0 + c.Mdot * t;
+  S argp_df = c.argp0 + c.argpdot * t;
+  S node_df = c.node0 + c.nodedot * t;
+  S node = node_df + c.nodecf * t2;
+  // P2: secular drag.
+  S A = 1.0 - c.C1 * t;
+  S Ed = c.bstar * c.C4 * t;
+  S Ld = c.t2cof * t2;
+  S M, argp;
+  if (!c.isimp) {
+    S dargp = c.argpcof * t;
+    S dM = c.Mcof * (cube(1.0 + c.eta * cos(M_df)) - c.dM0);
+    M = M_df + dargp + dM;
+    argp = argp_df - dargp - dM;
+    const double t3 = t2 * t, t4 = t3 * t;
+    A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
+    Ed = Ed + c.bstar * c.C5 * (sin(M) - c.sinM0);
+    Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
+  } else {
+    M = M_df;
+    argp = argp_df;
+  }
+  // P3: drag-decayed semi-major axis, mean motion and eccentricity.
+  S a = c.a0pp * A * A;
+  S n = g.ke / (a * sqrt(a));
+  S e = c.e0 - Ed;
+  if (det) det[kD_emargin] = std::min(val(e) + 0.001, 1.0 - val(e));
+  if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);
+  if (val(e) < 1.0e-6) e = S(1.0e-6);
+  // P4: mean longitude; angles reduced to [0, 2*pi).
+  M = M + c.n0pp * Ld;
+  S L = M + argp + node;
+  node = mod2pi(node);
+  argp = mod2pi(argp);
+  L = mod2pi(L);
+  // P5: long-period periodics (J3).
+  S axn = e * cos(argp);
+  S tau = 1.0 / (a * (1.0 - e * e));
+  S ayn = e * sin(argp) + tau * c.aycof;
+  S LT = L + tau * c.Lcof * axn;
+  // P6: Kepler's equation for psi = E + argp:  psi - axn sin psi + ayn cos psi = U.
+  S U = mod2pi(LT - node);
+  S psi = U;
+  int iters = 0;
+  for (int k = 0; k < 10; ++k) {
+    S sp = sin(psi), cp = cos(psi);
+    S step = (U - ayn * cp + axn * sp - psi) / (1.0 - axn * cp - ayn * sp);
+    if (val(step) > 0.95) step = S(0.95);
+    if (val(step) < -0.95) step = S(-0.95);
+    psi = psi + step;
+    ++iters;
+    if (std::fabs(val(step)) < 1.0e-12) break;
+  }
+  S sinpsi = sin(psi), cospsi = cos(psi);
+  // P7: short-period preliminaries.
+  S ecE = axn * cospsi + ayn * sinpsi;
+  S esE = axn * sinpsi - ayn * cospsi;
+  S eL2 = axn * axn + ayn * ayn;
+  S pL = a * (1.0 - eL2);
+  if (det) {
+    det[kD_M] = val(M); det[kD_argp] = val(argp); det[kD_node] = val(node); det[kD_a] = val(a);
+    det[kD_n] = val(n); det[kD_e] = val(e); det[kD_L] = val(L); det[kD_axn] = val(axn); det[kD_ayn] = val(ayn);
+    det[kD_LT] = val(LT); det[kD_U] = val(U); det[kD_psi] = val(psi); det[kD_iters] = iters;
+    det[kD_resid] = wrap_pi(val(psi) - val(axn) * std::sin(val(psi)) + val(ayn) * std::cos(val(psi)) - val(U));
+    det[kD_ecE] = val(ecE); det[kD_esE] = val(esE); det[kD_eL2] = val(eL2); det[kD_pL] = val(pL);
+  }
+  if (!(val(pL) >= 0.0)) return fail(4);
+  S rr = a * (1.0 - ecE);
+  S rdot = sqrt(a) * esE / rr;
+  S rfdot = sqrt(pL) / rr;
+  S betaL = sqrt(1.0 - eL2);
+  S w = esE / (1.0 + betaL);
+  S sinu = a / rr * (sinpsi - ayn - axn * w);
+  S cosu = a / rr * (cospsi - axn + ayn * w);
+  S u = atan2(sinu, cosu);
+  S sin2u = 2.0 * sinu * cosu;
+  S cos2u = 1.0 - 2.0 * sinu * sinu;
+  // P8: short-period periodics (J2).
+  S k1 = 0.5 * g.j2 / pL;
+  S k2 = k1 / pL;
+  S rk = rr * (1.0 - 1.5 * k2 * betaL * c.c41) + 0.5 * k1 * c.x1 * cos2u;
+  S uk = u - 0.25 * k2 * c.x7 * sin2u;
+  S nodek = node + 1.5 * k2 * c.cosi * sin2u;
+  S ik = c.i0 + 1.5 * k2 * c.cosi * c.sini * cos2u;
+  S rdotk = rdot - n / g.ke * k1 * c.x1 * sin2u;
+  S rfdotk = rfdot + n / g.ke * k1 * (c.x1 * cos2u + 1.5 * c.c41);
+  // P9: orientation vectors and the TEME state.
+  S su = sin(uk), cu = cos(uk), sn = sin(nodek), cn = cos(nodek), si = sin(ik), ci = cos(ik);
+  S mx = -sn * ci, my = cn * ci, mz = si;
+  S ux = mx * su + cn * cu, uy = my * su + sn * cu, uz = mz * su;
+  S vx = mx * cu - cn * su, vy = my * cu - sn * su, vz = mz * cu;
+  r[0] = g.radius * rk * ux; r[1] = g.radius * rk * uy; r[2] = g.radius * rk * uz;
+  v[0] = g.vkms * (rdotk * ux + rfdotk * vx);
+  v[1] = g.vkms * (rdotk * uy + rfdotk * vy);
+  v[2] = g.vkms * (rdotk * uz + rfdotk * vz);
+  int code = (val(rk) < 1.0) ? 6 : 0;
+  if (det) {
+    det[kD_r] = val(rr); det[kD_rdot] = val(rdot); det[kD_rfdot] = val(rfdot); det[kD_betaL] = val(betaL);
+    det[kD_sinu] = val(sinu); det[kD_cosu] = val(cosu); det[kD_u] = val(u); det[kD_k1] = val(k1); det[kD_k2] = val(k2);
+    det[kD_rk] = val(rk); det[kD_uk] = val(uk); det[kD_nodek] = val(nodek); det[kD_ik] = val(ik);
+    det[kD_rdotk] = val(rdotk); det[kD_rfdotk] = val(rfdotk); det[kD_code] = code;
+  }
+  return code;
+}
+
+// ------------------------------------------------------------ batch glue --
+template <class F>
+void parallel_for(int64_t n, int nthreads, F&& body) {
+  if (nthreads <= 1 || n < 2) { body(int64_t(0), n); return; }
+  nthreads = int(std::min<int64_t>(nthreads, n));
+  std::vector<std::thread> pool;
+  for (int k = 0; k < nthreads; ++k) {
+    int64_t lo = n * k / nthreads, hi = n * (k + 1) / nthreads;
+    pool.emplace_back([&body, lo, hi] { body(lo, hi); });
+  }
+  for (auto& th : pool) th.join();
+}
+
+template <class S>
+void load_elements(const double* elem, int64_t n, int64_t i, S el[kNElem], double* epoch) {
+  for (int k = 0; k < kNElem; ++k) el[k] = S(elem[k * n + i]);
+  *epoch = elem[7 * n + i];
+}
+
+void store_point(const double r[3], const double v[3], int code, int64_t P, int64_t p, double* ro, double* vo, uint8_t* err) {
+  for (int k = 0; k < 3; ++k) { ro[k * P + p] = r[k]; vo[k * P + p] = v[k]; }
+  err[p] = uint8_t(code);
+}
+
+}  // namespace
+
+// ================================================================== C ABI ==
+// Layouts: elem is [8][n] row-major (rows: no_kozai rad/min, ecco, inclo rad,
+// nodeo rad, argpo rad, mo rad, bstar 1/earth-radii, epoch days relative to
+// the caller's reference).  Times are minutes after that reference; the time
+// since epoch is t - 1440*epoch.  r, v are [3][P] in km and km/s; err is [P].
+// grav is NULL (WGS72) or {mu, R, J2, J3, J4}.  Returns 0 or a negative code.
+extern "C" {
+
+int oracle_abi_version(void) { return 1; }
+
+void oracle_wgs72(double* out5) { for (int k = 0; k < 5; ++k) out5[k] = kWgs72[k]; }
+
+double oracle_ke(const double* grav) { Gravity g; if (make_gravity(grav, &g)) return -1; return g.ke; }
+
+int oracle_propagate(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
+                     double* r, double* v, uint8_t* err, int nthreads) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  if (n < 0 || T < 0) return -2;
+  const int64_t P = n * T;
+  parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      double el[kNElem], epoch;
+      load_elements(elem, n, i, el, &epoch);
+      Sat<double> c = sgp4_init<double>(g, el, epoch);
+      for (int64_t j = 0; j < T; ++j) {
+        double rr[3], vv[3];
+        int code = sgp4_point(g, c, t[j] - 1440.0 * epoch, rr, vv, nullptr);
+        store_point(rr, vv, code, P, i * T + j, r, v, err);
+      }
+    }
+  });
+  return 0;
+}
+
+int oracle_propagate_ragged(const double* grav, int64_t n, const double* elem, const int64_t* offsets,
+                            const double* t, int64_t nnz, double* r, double* v, uint8_t* err, int nthreads) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  if (n < 0 || nnz < 0 || offsets[0] != 0 || offsets[n] != nnz) return -3;
+  for (int64_t i = 0; i < n; ++i) if (offsets[i + 1] < offsets[i]) return -3;
+  parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      double el[kNElem], epoch;
+      load_elements(elem, n, i, el, &epoch);
+      Sat<double> c = sgp4_init<double>(g, el, epoch);
+      for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p) {
+        double rr[3], vv[3];
+        int code = sgp4_point(g, c, t[p] - 1440.0 * epoch, rr, vv, nullptr);
+        store_point(rr, vv, code, nnz, p, r, v, err);
+      }
+    }
+  });
+  return 0;
+}
+
+// Individual (satellite, time) points: sat[k] indexes the n element sets, t[k]
+// is minutes after the reference.  Optional detail[k][kD_COUNT] intermediates.
+int oracle_propagate_points(const double* grav, int64_t n, const double* elem, int64_t npts, const int64_t* sat,
+                            const double* t, double* r, double* v, uint8_t* err, double* detail) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  for (int64_t k = 0; k < npts; ++k) {
+    if (sat[k] < 0 || sat[k] >= n) return -1;
+    double el[kNElem], epoch;
+    load_elements(elem, n, sat[k], el, &epoch);
+    Sat<double> c = sgp4_init<double>(g, el, epoch);
+    double rr[3], vv[3];
+    int code = sgp4_point(g, c, t[k] - 1440.0 * epoch, rr, vv, detail ? detail + k * kD_COUNT : nullptr);
+    store_point(rr, vv, code, npts, k, r, v, err);
+  }
+  return 0;
+}
+
+int oracle_detail_count(void) { return kD_COUNT; }
+
+// Initialisation constants per satellite, [n][44] in this order.
+enum { kI_COUNT = 44 };
+int oracle_init_count(void) { return kI_COUNT; }
+int oracle_init(const double* grav, int64_t n, const double* elem, double* rec) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  for (int64_t i = 0; i < n; ++i) {
+    double el[kNElem], epoch;
+    load_elements(elem, n, i, el, &epoch);
+    Sat<double> c = sgp4_init<double>(g, el, epoch);
+    double out[kI_COUNT] = {
+        c.cosi, c.sini, c.beta0sq, c.beta0, c.c41, c.x1, c.x7, c.n0pp, c.a0pp, c.rp, c.hp, c.s, c.q4,
+        c.xi, c.eta, c.C1, c.C2, c.C3, c.C4, c.C5, c.Mdot, c.argpdot, c.nodedot, c.nodedot1,
+        c.argpcof, c.Mcof, c.nodecf, c.t2cof, c.aycof, c.Lcof, c.dM0, c.sinM0,
+        c.D2, c.D3, c.D4, c.t3cof, c.t4cof, c.t5cof, double(c.isimp), double(c.deep), double(c.epoch_code),
+        g.ke, g.j3oj2, g.vkms};
+    std::memcpy(rec + i * kI_COUNT, out, sizeof out);
+  }
+  return 0;
+}
+
+// Forward-mode Jacobian d(r, v)/d(n0, e0, i0, node0, argp0, M0, bstar) at
+// individual points: J[k][6][7] (rows rx ry rz vx vy vz).
+int oracle_jacobian_points(const double* grav, int64_t n, const double* elem, int64_t npts, const int64_t* sat,
+                           const double* t, double* J, double* r, double* v, uint8_t* err) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  for (int64_t k = 0; k < npts; ++k) {
+    if (sat[k] < 0 || sat[k] >= n) return -1;
+    Dual el[kNElem];
+    double epoch;
+    load_elements(elem, n, sat[k], el, &epoch);
+    for (int q = 0; q < kNElem; ++q) el[q].d[q] = 1.0;
+    Sat<Dual> c = sgp4_init<Dual>(g, el, epoch);
+    Dual rr[3], vv[3];
+    int code = sgp4_point(g, c, t[k] - 1440.0 * epoch, rr, vv, nullptr);
+    for (int q = 0; q < 3; ++q) {
+      r[q * npts + k] = rr[q].v; v[q * npts + k] = vv[q].v;
+      for (int m = 0; m < kNElem; ++m) {
+        J[(k * 6 + q) * kNElem + m] = rr[q].d[m];
+        J[(k * 6 + 3 + q) * kNElem + m] = vv[q].d[m];
+      }
+    }
+    err[k] = uint8_t(code);
+  }
+  return 0;
+}
+
+// Vector-Jacobian product over a dense n x T grid: gelem[7][n] =
+// sum_j sum_c gr[c][i*T+j] dr_c/dtheta + gv[c][i*T+j] dv_c/dtheta, with gv
+// nullable (zero).  Points with codes 1, 2, 4, 7 contribute nothing.
+int oracle_vjp(const double* grav, int64_t n, const double* elem, const double* t, int64_t T, const double* gr,
+               const double* gv, double* gelem, int nthreads) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  const int64_t P = n * T;
+  parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      Dual el[kNElem];
+      double epoch;
+      load_elements(elem, n, i, el, &epoch);
+      for (int q = 0; q < kNElem; ++q) el[q].d[q] = 1.0;
+      Sat<Dual> c = sgp4_init<Dual>(g, el, epoch);
+      double acc[kNElem] = {0};
+      for (int64_t j = 0; j < T; ++j) {
+        Dual rr[3], vv[3];
+        int code = sgp4_point(g, c, t[j] - 1440.0 * epoch, rr, vv, nullptr);
+        if (code != 0 && code != 6) continue;
+        const int64_t p = i * T + j;
+        for (int q = 0; q < 3; ++q)
+          for (int m = 0; m < kNElem; ++m) {
+            acc[m] += gr[q * P + p] * rr[q].d[m];
+            if (gv) acc[m] += gv[q * P + p] * vv[q].d[m];
+          }
+      }
+      for (int m = 0; m < kNElem; ++m) gelem[m * n + i] = acc[m];
+    }
+  });
+  return 0;
+}
+
+// Arithmetic the definition performs for one point (initialisation excluded):
+// out[8] = {add/sub, mul, div, sqrt, cbrt, sin/cos, atan2, floor}.
+int oracle_count_ops(const double* grav, const double* elem1 /*[8]*/, double tmin, uint64_t* out8) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  OpCount el[kNElem];
+  for (int k = 0; k < kNElem; ++k) el[k] = OpCount(elem1[k]);
+  Sat<OpCount> c = sgp4_init<OpCount>(g, el, elem1[7]);
+  g_tally = OpTally();
+  OpCount rr[3], vv[3];
+  int code = sgp4_point(g, c, tmin - 1440.0 * elem1[7], rr, vv, nullptr);
+  uint64_t o[8] = {g_tally.add, g_tally.mul, g_tally.div, g_tally.sqrt, g_tally.cbrt, g_tally.trig, g_tally.atan2, g_tally.floor};
+  std::memcpy(out8, o, sizeof o);
+  return code;
+}
+
+}  // extern "C"

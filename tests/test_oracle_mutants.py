@@ -1,0 +1,76 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each mutant is the oracle source with one planted mistake (a dropped term, a
+flipped sign, a wrong coefficient or power), built on the CPU into a temporary
+library and run against the pin tests; at least one pin must fail.  Mistakes
+that no available pin can see are listed in the design notes as weakly pinned
+(J3 long-period mean-longitude term, the eccentricity-dependent drag
+coefficients, the J4 perigee rate, the low-perigee density parameter).
+"""
+import concurrent.futures
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "sgp4_oracle.cpp")
+
+MUTANTS = [
+    ("short-period radius coefficient", "0.5 * k1 * c.x1 * cos2u", "0.25 * k1 * c.x1 * cos2u"),
+    ("short-period argument of latitude sign", "u - 0.25 * k2 * c.x7 * sin2u", "u + 0.25 * k2 * c.x7 * sin2u"),
+    ("short-period node sign", "node + 1.5 * k2 * c.cosi * sin2u", "node - 1.5 * k2 * c.cosi * sin2u"),
+    ("short-period inclination dropped", "c.i0 + 1.5 * k2 * c.cosi * c.sini * cos2u", "c.i0 + 0.0 * k2"),
+    ("short-period radial rate dropped", "rdot - n / g.ke * k1 * c.x1 * sin2u", "rdot - 0.0 * k1"),
+    ("short-period transverse rate coefficient", "(c.x1 * cos2u + 1.5 * c.c41)", "(c.x1 * cos2u + 0.5 * c.c41)"),
+    ("D3 coefficient", "(17.0 * c.a0pp + c.s)", "(16.0 * c.a0pp + c.s)"),
+    ("D4 power of a0", "(2.0 / 3.0) * c.a0pp * c.a0pp * c.xi", "(2.0 / 3.0) * c.a0pp * c.xi"),
+    ("t4cof coefficient", "12.0 * c.D2 + 10.0 * C1sq", "12.0 * c.D2 + 8.0 * C1sq"),
+    ("Kepler residual sign", "(U - ayn * cp + axn * sp - psi)", "(U + ayn * cp + axn * sp - psi)"),
+    ("velocity unit", "g->vkms = g->radius * g->ke / 60.0", "g->vkms = g->radius * g->ke / 61.0"),
+    ("first-order node rate", "c.nodedot1 = -T1 * c.cosi", "c.nodedot1 = -0.9 * T1 * c.cosi"),
+    ("un-Kozai coefficient", "0.75 * J2 * c.c41", "1.5 * J2 * c.c41"),
+    ("J3 long-period eccentricity sign", "ayn = e * sin(argp) + tau * c.aycof", "ayn = e * sin(argp) - tau * c.aycof"),
+    ("first-order mean-anomaly rate", "0.5 * T1 * c.beta0 * c.c41", "0.6 * T1 * c.beta0 * c.c41"),
+    ("eccentricity floor of code 1", "if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);",
+     "if (!(val(e) >= -0.01 && val(e) < 1.0)) return fail(1);"),
+]
+
+
+def _run(mutant, workdir):
+    name, old, new = mutant
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    cpp = os.path.join(workdir, "m.cpp")
+    lib = os.path.join(workdir, "m.so")
+    open(cpp, "w").write(src.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-pthread", "-o", lib, cpp],
+                   check=True)
+    env = dict(os.environ, SGP4_ORACLE_LIB=lib)
+    p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    return name, p.returncode
+
+
+def test_every_planted_mistake_fails_a_pin():
+    with tempfile.TemporaryDirectory() as tmp:
+        dirs = []
+        for k in range(len(MUTANTS)):
+            d = os.path.join(tmp, str(k))
+            os.makedirs(d)
+            dirs.append(d)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+            results = list(ex.map(_run, MUTANTS, dirs))
+    survived = [name for name, rc in results if rc == 0]
+    assert not survived, f"mutants not caught by any pin: {survived}"
+
+
+def test_unmutated_source_passes():
+    # guard: the harness itself must not report a failure for the real oracle
+    with tempfile.TemporaryDirectory() as tmp:
+        name, rc = _run(("identity", "int oracle_abi_version(void) { return 1; }",
+                         "int oracle_abi_version(void) { return 1; }"), tmp)
+    assert rc == 0
