@@ -1,0 +1,154 @@
+/* sgp4mi: SGP4 near-Earth propagation of N satellites x T times on MI355X.
+ *
+ * The operation is the batched map f(s, t) -> (r, v) of the paper's section
+ * 2.2 ("Vectorisation"): for every satellite s (a set of mean elements) and
+ * every time t, the SGP4 general-perturbation model (section 2.1: Hoots &
+ * Roehrich 1980 as revised by Hoots et al. 2004 and Vallado et al. 2006, with
+ * WGS72 constants) gives the TEME position in km and velocity in km/s.
+ * Validity problems do not abort the batch: each point carries an error code
+ * (section 2.2, "Control Flow").  Only near-Earth element sets (period under
+ * 225 minutes, section 6) are propagated; deep-space sets are flagged.
+ *
+ * Conventions for every call
+ *   - Pointers are DEVICE pointers owned by the caller unless marked "host".
+ *   - Calls validate their arguments on the host, enqueue work on `stream`
+ *     (a hipStream_t; NULL is the default stream) and return without
+ *     synchronising, except sgp4_plan_create, which may synchronise.
+ *   - A negative return value is an SGP4_E_* error: nothing was enqueued and
+ *     nothing was written.  SGP4_E_HIP reports a failed HIP call or launch.
+ *   - The library allocates device memory only inside sgp4_plan objects.
+ *   - Element array elem is float64 [8][n] row-major (row k at elem + k*n):
+ *       0 no_kozai  mean motion (Kozai), rad/min      1 ecco   eccentricity
+ *       2 inclo     inclination, rad                  3 nodeo  RAAN, rad
+ *       4 argpo     argument of perigee, rad          5 mo     mean anomaly, rad
+ *       6 bstar     drag term, 1/earth radii
+ *       7 epoch     days after the caller's reference instant (float64; the
+ *                   time since epoch is t - 1440*epoch minutes, formed in
+ *                   float64, which avoids the float32 epoch error of section 6)
+ *   - Times t are float64 minutes after the same reference instant.
+ *   - Outputs are component-major SoA: r[c*P + p], v[c*P + p] for c = x, y, z,
+ *     err[p], with P points; p = i*T + j on a dense grid, the CSR position on a
+ *     ragged one.  r and v are double for SGP4_FP64 and float otherwise.
+ *   - Point codes: 0 ok; 1 mean eccentricity outside [-0.001, 1) (or outside
+ *     [0, 1) at epoch); 2 recovered mean motion not positive; 4 semi-latus
+ *     rectum negative; 6 decayed (radius below one earth radius; the state is
+ *     still written); 7 deep-space element set, not propagated.  Codes 1, 2, 4
+ *     and 7 write NaN to r and v.
+ */
+#ifndef SGP4MI_H
+#define SGP4MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of the per-point path.  Section 4 of the paper compares 32- and
+ * 64-bit propagation; FP32_MIXED keeps the time since epoch, the secular
+ * (n*t and drag) accumulation and the angle reductions in float64 and runs
+ * the periodic terms, Kepler solve and state assembly in float32. */
+typedef enum { SGP4_FP64 = 0, SGP4_FP32 = 1, SGP4_FP32_MIXED = 2 } sgp4_precision;
+
+enum {
+  SGP4_OK = 0,
+  SGP4_E_ARG = -1,       /* null pointer or inconsistent argument */
+  SGP4_E_SIZE = -2,      /* negative or too large n, T, nnz */
+  SGP4_E_OFFSETS = -3,   /* CSR offsets not 0 = o[0] <= ... <= o[n] = nnz */
+  SGP4_E_PRECISION = -4, /* unknown precision */
+  SGP4_E_HIP = -5,       /* HIP runtime or launch failure */
+  SGP4_E_GRAVITY = -6,   /* gravity model rejected */
+  SGP4_E_PLAN = -7       /* plan does not match the call's buffers */
+};
+
+/* Library version (integer, increases with ABI changes). */
+int sgp4_version(void);
+
+/* Human-readable text for a return code (static storage). */
+const char* sgp4_strerror(int code);
+
+/* Bytes of the opaque per-satellite constant record for n satellites.  The
+ * record layout is internal; allocate at least this much, 256-byte aligned. */
+size_t sgp4_consts_bytes(int64_t n);
+
+/* Initialisation (section 3.1: the constants computed from the elements before
+ * propagation).  grav (host, nullable) is {mu km^3/s^2, R km, J2, J3, J4};
+ * NULL selects WGS72 (section 2.1).  J3 != 0 with J2 == 0 is rejected.
+ * elem: device float64 [8][n].  consts: device, sgp4_consts_bytes(n) bytes,
+ * written.  sat_flags: device uint8 [n] or NULL; written with bit0 deep-space,
+ * bit1 simplified drag (perigee below 220 km), bit2 invalid elements.
+ * 0 <= n < 2^31. */
+int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, uint8_t* sat_flags, void* stream);
+
+/* Dense N x T propagation (section 2.2: f applied over satellites x times).
+ * t: device float64 [T].  r, v: device [3][n*T] of double (FP64) or float;
+ * err: device uint8 [n*T].  consts must come from sgp4_init with the same n. */
+int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
+                   uint8_t* err, void* stream);
+
+/* As sgp4_propagate with an explicit workgroup size (64, 128, 256 or 512). */
+int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
+                      uint8_t* err, int block, void* stream);
+
+/* Opaque ragged-propagation plan (host object owning device tile tables and
+ * a captured HIP graph). */
+typedef struct sgp4_plan sgp4_plan;
+
+enum { SGP4_PLAN_AUTOTUNE = 1, SGP4_PLAN_GRAPH = 2 };
+
+/* Ragged propagation: satellite i has times t[offsets[i] .. offsets[i+1]).
+ * offsets: device int64 [n+1] with offsets[0] = 0, non-decreasing,
+ * offsets[n] = nnz.  t: device float64 [nnz].  r, v: [3][nnz]; err: [nnz].
+ * plan: NULL (one persistent launch whose wavefronts locate their satellites
+ * by binary search of the offsets; the offsets are not checked on the host) or
+ * a plan created for exactly these buffers (launches its tuned kernel
+ * directly, without the graph). */
+int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,
+                          int precision, void* r, void* v, uint8_t* err, const sgp4_plan* plan, void* stream);
+
+/* Build a plan for one ragged batch: copies and checks the offsets (returns
+ * SGP4_E_OFFSETS when malformed), builds the tile tables, optionally times
+ * the candidate mappings (tiles of one satellite per wavefront or flat runs,
+ * workgroup size, persistent grid size) and keeps the fastest
+ * (SGP4_PLAN_AUTOTUNE), and optionally captures the launch in a HIP graph
+ * (SGP4_PLAN_GRAPH).  Synchronises `stream`.  Autotuning writes r, v, err. */
+int sgp4_plan_create(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
+                     int64_t nnz, int precision, void* r, void* v, uint8_t* err, unsigned flags, void* stream);
+
+/* As sgp4_plan_create with a fixed configuration instead of autotuning:
+ * mode 0 = tiles of one satellite per wavefront, 1 = flat runs of 64 points;
+ * block = workgroup size (64, 128, 256, 512); waves_per_cu scales the
+ * persistent grid (workgroups = min(needed, compute units * waves_per_cu)).
+ * SGP4_PLAN_AUTOTUNE in flags is ignored; SGP4_PLAN_GRAPH is honoured. */
+int sgp4_plan_create_config(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
+                            int64_t nnz, int precision, void* r, void* v, uint8_t* err, int mode, int block,
+                            int waves_per_cu, unsigned flags, void* stream);
+
+/* Enqueue the plan's launch on `stream` (graph launch when captured). */
+int sgp4_plan_launch(const sgp4_plan* plan, void* stream);
+
+/* Describe the plan's chosen configuration into buf (host, NUL-terminated). */
+int sgp4_plan_describe(const sgp4_plan* plan, char* buf, size_t len);
+
+/* Free a plan and its device tables.  NULL is accepted. */
+void sgp4_plan_destroy(sgp4_plan* plan);
+
+/* Vector-Jacobian product (section 5: gradients of the state with respect to
+ * the elements): for a dense n x T batch, gelem[m][i] = sum over j and
+ * components c of gr[c][i*T+j] * d r_c/d theta_m + gv[c][i*T+j] * d v_c/d theta_m,
+ * theta = (no_kozai, ecco, inclo, nodeo, argpo, mo, bstar) of satellite i.
+ * The forward pass is recomputed, not stored.  elem: the device float64
+ * [8][n] elements consts was initialised from (the gravity model is read from
+ * consts); gr and gv device [3][n*T] of double
+ * (FP64) or float (FP32_MIXED), gv nullable (zero).  Points with codes 1, 2,
+ * 4, 7 contribute nothing.  gelem: device float64 [7][n].  FP32 is rejected
+ * (SGP4_E_PRECISION). */
+int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
+             const void* gr, const void* gv, double* gelem, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGP4MI_H */

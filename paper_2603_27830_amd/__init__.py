@@ -1,0 +1,228 @@
+"""SGP4 near-Earth propagation on MI355X: thin torch front end of libsgp4mi.
+
+PyTorch supplies device memory and streams; every step of the computation runs
+in the library's HIP kernels (see include/sgp4mi.h for the C ABI).
+
+    rec = init(elem)                      # elem: float64 [8, n] on the GPU
+    r, v, err = propagate(rec, t, "mixed")  # r, v: [3, n, T]; err: uint8 [n, T]
+
+Element rows: no_kozai (rad/min), ecco, inclo, nodeo, argpo, mo (rad), bstar
+(1/earth radii), epoch (days after the reference instant); times are minutes
+after the reference instant.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native
+from ._native import SGP4Error, PLAN_AUTOTUNE, PLAN_GRAPH
+
+__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "SGP4Function", "PRECISIONS",
+           "SGP4Error", "consts_bytes"]
+
+PRECISIONS = {"fp64": _native.SGP4_FP64, "fp32": _native.SGP4_FP32, "mixed": _native.SGP4_FP32_MIXED}
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        if p not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _out_dtype(p: int) -> torch.dtype:
+    return torch.float64 if p == _native.SGP4_FP64 else torch.float32
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, name, device=None):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA/HIP tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def consts_bytes(n: int) -> int:
+    return int(_native.lib().sgp4_consts_bytes(int(n)))
+
+
+class Record:
+    """Per-satellite constant record produced by :func:`init` (opaque bytes)."""
+
+    def __init__(self, consts: torch.Tensor, n: int, flags: torch.Tensor, elem: torch.Tensor):
+        self.consts, self.n, self.flags, self.elem = consts, n, flags, elem
+
+    @property
+    def device(self):
+        return self.consts.device
+
+
+def init(elem: torch.Tensor, grav: Optional[Sequence[float]] = None) -> Record:
+    """Initialisation: elements float64 [8, n] (device) -> constant record."""
+    _need(elem, torch.float64, "elem")
+    if elem.dim() != 2 or elem.shape[0] != 8:
+        raise ValueError("elem must have shape [8, n]")
+    n = int(elem.shape[1])
+    consts = torch.empty(max(consts_bytes(n), 1), dtype=torch.uint8, device=elem.device)
+    flags = torch.empty(max(n, 1), dtype=torch.uint8, device=elem.device)
+    g = None
+    if grav is not None:
+        g = (ctypes.c_double * 5)(*[float(x) for x in grav])
+    with torch.cuda.device(elem.device):
+        _native.check(_native.lib().sgp4_init(g, n, _ptr(elem), _ptr(consts), _ptr(flags), _stream(elem.device)),
+                      "sgp4_init")
+    return Record(consts, n, flags[:n], elem)
+
+
+def propagate(rec: Record, t: torch.Tensor, precision="fp64", out=None, block: int = 256):
+    """Dense grid: returns r [3, n, T], v [3, n, T] (km, km/s, TEME) and err uint8 [n, T]."""
+    p = _prec(precision)
+    _need(t, torch.float64, "t", rec.device)
+    n, T = rec.n, int(t.numel())
+    if out is None:
+        dt = _out_dtype(p)
+        r = torch.empty((3, n, T), dtype=dt, device=rec.device)
+        v = torch.empty((3, n, T), dtype=dt, device=rec.device)
+        err = torch.empty((n, T), dtype=torch.uint8, device=rec.device)
+    else:
+        r, v, err = out
+    with torch.cuda.device(rec.device):
+        _native.check(_native.lib().sgp4_propagate_ex(_ptr(rec.consts), n, _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err),
+                                                      int(block), _stream(rec.device)), "sgp4_propagate")
+    return r, v, err
+
+
+def _ragged_out(p, nnz, device):
+    dt = _out_dtype(p)
+    return (torch.empty((3, nnz), dtype=dt, device=device), torch.empty((3, nnz), dtype=dt, device=device),
+            torch.empty(nnz, dtype=torch.uint8, device=device))
+
+
+class RaggedPlan:
+    """A tuned (and optionally graph-captured) launch for one ragged batch."""
+
+    def __init__(self, rec: Record, offsets: torch.Tensor, t: torch.Tensor, precision="fp64", out=None,
+                 autotune: bool = True, graph: bool = True, config=None):
+        """config: None (default or autotuned choice) or (mode, block, waves_per_cu)
+        with mode 0 = tiles, 1 = flat."""
+        self.p = _prec(precision)
+        _need(offsets, torch.int64, "offsets", rec.device)
+        _need(t, torch.float64, "t", rec.device)
+        self.rec, self.offsets, self.t = rec, offsets, t
+        self.nnz = int(t.numel())
+        self.out = out if out is not None else _ragged_out(self.p, self.nnz, rec.device)
+        r, v, err = self.out
+        h = ctypes.c_void_p()
+        flags = (PLAN_AUTOTUNE if autotune else 0) | (PLAN_GRAPH if graph else 0)
+        with torch.cuda.device(rec.device):
+            if config is None:
+                rc = _native.lib().sgp4_plan_create(ctypes.byref(h), _ptr(rec.consts), rec.n, _ptr(offsets), _ptr(t),
+                                                    self.nnz, self.p, _ptr(r), _ptr(v), _ptr(err), flags,
+                                                    _stream(rec.device))
+            else:
+                mode, block, per_cu = (int(x) for x in config)
+                rc = _native.lib().sgp4_plan_create_config(ctypes.byref(h), _ptr(rec.consts), rec.n, _ptr(offsets),
+                                                           _ptr(t), self.nnz, self.p, _ptr(r), _ptr(v), _ptr(err),
+                                                           mode, block, per_cu, flags, _stream(rec.device))
+            _native.check(rc, "sgp4_plan_create")
+        self.handle = h
+
+    def launch(self):
+        with torch.cuda.device(self.rec.device):
+            _native.check(_native.lib().sgp4_plan_launch(self.handle, _stream(self.rec.device)), "sgp4_plan_launch")
+        return self.out
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _native.check(_native.lib().sgp4_plan_describe(self.handle, buf, 512), "sgp4_plan_describe")
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _native.lib().sgp4_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def propagate_ragged(rec: Record, offsets: torch.Tensor, t: torch.Tensor, precision="fp64",
+                     plan: Optional[RaggedPlan] = None, out=None):
+    """CSR lists: returns r [3, nnz], v [3, nnz], err [nnz]."""
+    p = _prec(precision)
+    _need(offsets, torch.int64, "offsets", rec.device)
+    _need(t, torch.float64, "t", rec.device)
+    if offsets.numel() != rec.n + 1:
+        raise ValueError("offsets must have n + 1 entries")
+    nnz = int(t.numel())
+    if plan is not None:
+        r, v, err = plan.out
+        handle = plan.handle
+    else:
+        r, v, err = out if out is not None else _ragged_out(p, nnz, rec.device)
+        handle = None
+    with torch.cuda.device(rec.device):
+        _native.check(_native.lib().sgp4_propagate_ragged(_ptr(rec.consts), rec.n, _ptr(offsets), _ptr(t), nnz, p,
+                                                          _ptr(r), _ptr(v), _ptr(err), handle, _stream(rec.device)),
+                      "sgp4_propagate_ragged")
+    return r, v, err
+
+
+def vjp(rec: Record, t: torch.Tensor, gr: torch.Tensor, gv: Optional[torch.Tensor] = None, precision="fp64"):
+    """Vector-Jacobian product of the dense propagation: float64 [7, n]."""
+    p = _prec(precision)
+    _need(t, torch.float64, "t", rec.device)
+    dt = _out_dtype(p)
+    n, T = rec.n, int(t.numel())
+    gr = gr.contiguous()
+    _need(gr, dt, "gr", rec.device)
+    if gr.numel() != 3 * n * T:
+        raise ValueError("gr must have 3*n*T elements")
+    if gv is not None:
+        gv = gv.contiguous()
+        _need(gv, dt, "gv", rec.device)
+        if gv.numel() != 3 * n * T:
+            raise ValueError("gv must have 3*n*T elements")
+    out = torch.empty((7, n), dtype=torch.float64, device=rec.device)
+    with torch.cuda.device(rec.device):
+        _native.check(_native.lib().sgp4_vjp(n, _ptr(rec.elem), _ptr(rec.consts), _ptr(t), T, p, _ptr(gr), _ptr(gv),
+                                             _ptr(out), _stream(rec.device)), "sgp4_vjp")
+    return out
+
+
+class SGP4Function(torch.autograd.Function):
+    """(elem [8, n], t [T]) -> (r [3, n, T], v [3, n, T]); backward through the
+    hand-written VJP kernel (no gradient for the epoch row or the times)."""
+
+    @staticmethod
+    def forward(ctx, elem, t, precision="fp64", grav=None):
+        rec = init(elem.detach().contiguous(), grav)
+        r, v, err = propagate(rec, t, precision)
+        ctx.rec, ctx.t, ctx.precision = rec, t, precision
+        ctx.mark_non_differentiable(err)
+        return r, v, err
+
+    @staticmethod
+    def backward(ctx, gr, gv, _gerr):
+        p = ctx.precision
+        dt = _out_dtype(_prec(p))
+        if gr is None:
+            gr = torch.zeros((3, ctx.rec.n, ctx.t.numel()), dtype=dt, device=ctx.rec.device)
+        g7 = vjp(ctx.rec, ctx.t, gr.to(dt), None if gv is None else gv.to(dt), p)
+        g = torch.zeros((8, ctx.rec.n), dtype=torch.float64, device=ctx.rec.device)
+        g[:7] = g7
+        return g, None, None, None

@@ -1,0 +1,399 @@
+// C ABI of the library: argument validation, launch selection, ragged plans
+// (tile tables, autotuner, HIP graph capture).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+
+#include "sgp4mi.h"
+#include "sgp4mi_common.h"
+
+namespace sgp4mi {
+hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
+                       hipStream_t s);
+hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
+                        uint8_t* err, int block, hipStream_t s);
+hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
+                         const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
+                         int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
+hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* consts, const double* t, int64_t T,
+                      const void* gr, const void* gv, double* gelem, hipStream_t s);
+}  // namespace sgp4mi
+
+using namespace sgp4mi;
+
+namespace {
+
+constexpr double kWgs72[5] = {398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597};
+constexpr int64_t kMaxSats = 2147483647LL;
+
+int check_gravity(const double* g) {
+  for (int k = 0; k < 5; ++k)
+    if (!std::isfinite(g[k])) return SGP4_E_GRAVITY;
+  if (!(g[0] > 0) || !(g[1] > 0)) return SGP4_E_GRAVITY;
+  if (g[2] == 0.0 && g[3] != 0.0) return SGP4_E_GRAVITY;
+  return SGP4_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SGP4_OK : SGP4_E_HIP; }
+
+bool mul_overflows(int64_t a, int64_t b) { return a != 0 && b > INT64_MAX / a; }
+
+int compute_units() {
+  static int cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  });
+  return cus;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plans --
+struct sgp4_plan {
+  int precision = 0;
+  int mode = 1;      // 0 tiles, 1 flat
+  int block = 256;
+  unsigned grid = 0;
+  const void* consts = nullptr;
+  int64_t n = 0, nnz = 0;
+  const int64_t* offsets = nullptr;
+  const double* t = nullptr;
+  void* r = nullptr;
+  void* v = nullptr;
+  uint8_t* err = nullptr;
+  int64_t* tile_start = nullptr;  // device, tiles mode
+  int32_t* tile_sat = nullptr;    // device, tiles mode
+  int64_t ntiles = 0;
+  int32_t* chunk_sat = nullptr;   // device, flat mode
+  int64_t nchunks = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double best_us = -1.0;
+  int ncandidates = 0;
+  bool from_cache = false;
+};
+
+namespace {
+
+hipError_t plan_launch_direct(const sgp4_plan* p, hipStream_t s) {
+  if (p->mode == 0)
+    return launch_ragged(p->precision, 0, p->consts, p->n, p->offsets, p->t, p->nnz, p->tile_start, p->tile_sat,
+                         p->ntiles, p->r, p->v, p->err, p->block, p->grid, s);
+  return launch_ragged(p->precision, 1, p->consts, p->n, p->offsets, p->t, p->nnz, nullptr, p->chunk_sat, p->nchunks,
+                       p->r, p->v, p->err, p->block, p->grid, s);
+}
+
+void plan_free(sgp4_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->tile_start) (void)hipFree(p->tile_start);
+  if (p->tile_sat) (void)hipFree(p->tile_sat);
+  if (p->chunk_sat) (void)hipFree(p->chunk_sat);
+  delete p;
+}
+
+// Tuning cache: one line per key, "key mode block grid us".
+std::string cache_path() {
+  const char* e = std::getenv("SGP4MI_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/sgp4mi_tune.txt";
+}
+
+std::string tune_key(const sgp4_plan* p) {
+  // Keyed by device, precision and the batch's size class (powers of two of n
+  // and nnz): a plan for a similar batch reuses the choice.
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (auto& ch : arch) if (ch == ' ' || ch == ':') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s/p%d/n%d/z%d", arch.c_str(), p->precision, int(std::log2(double(p->n) + 1)),
+                int(std::log2(double(p->nnz) + 1)));
+  return buf;
+}
+
+bool cache_lookup(const std::string& key, int* mode, int* block, unsigned* grid, double* us) {
+  FILE* f = std::fopen(cache_path().c_str(), "r");
+  if (!f) return false;
+  char k[200];
+  int m, b;
+  unsigned g;
+  double u;
+  bool found = false;
+  while (std::fscanf(f, "%199s %d %d %u %lf", k, &m, &b, &g, &u) == 5) {
+    if (key == k) { *mode = m; *block = b; *grid = g; *us = u; found = true; }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& key, int mode, int block, unsigned grid, double us) {
+  std::string path = cache_path();
+  const size_t slash = path.find_last_of('/');
+  if (slash != std::string::npos && slash > 0) mkdir(path.substr(0, slash).c_str(), 0755);
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;  // caching is best effort
+  std::fprintf(f, "%s %d %d %u %.3f\n", key.c_str(), mode, block, grid, us);
+  std::fclose(f);
+}
+
+}  // namespace
+
+// ================================================================== C ABI ==
+extern "C" {
+
+int sgp4_version(void) { return 1; }
+
+const char* sgp4_strerror(int code) {
+  switch (code) {
+    case SGP4_OK: return "ok";
+    case SGP4_E_ARG: return "invalid argument (null pointer or inconsistent argument)";
+    case SGP4_E_SIZE: return "invalid size (negative or too large n, T or nnz)";
+    case SGP4_E_OFFSETS: return "malformed CSR offsets";
+    case SGP4_E_PRECISION: return "unknown or unsupported precision";
+    case SGP4_E_HIP: return "HIP runtime or launch failure";
+    case SGP4_E_GRAVITY: return "gravity model rejected";
+    case SGP4_E_PLAN: return "plan does not match the call";
+  }
+  return "unknown error code";
+}
+
+size_t sgp4_consts_bytes(int64_t n) { return n < 0 ? 0 : record_bytes(n); }
+
+int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, uint8_t* sat_flags, void* stream) {
+  if (n < 0 || n > kMaxSats) return SGP4_E_SIZE;
+  if (!consts || (n > 0 && !elem)) return SGP4_E_ARG;
+  const double* g = grav ? grav : kWgs72;
+  if (int rc = check_gravity(g)) return rc;
+  return hip_status(launch_init(g, n, elem, consts, sat_flags, static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
+                      uint8_t* err, int block, void* stream) {
+  if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
+  if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
+  if (block != 64 && block != 128 && block != 256 && block != 512) return SGP4_E_ARG;
+  if (n == 0 || T == 0) return SGP4_OK;
+  if (!consts || !t || !r || !v || !err) return SGP4_E_ARG;
+  return hip_status(launch_dense(precision, consts, n, t, T, r, v, err, block, static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
+                   uint8_t* err, void* stream) {
+  return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, 256, stream);
+}
+
+int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,
+                          int precision, void* r, void* v, uint8_t* err, const sgp4_plan* plan, void* stream) {
+  if (n < 0 || nnz < 0 || n > kMaxSats || mul_overflows(nnz, 3)) return SGP4_E_SIZE;
+  if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
+  if (nnz == 0) return SGP4_OK;
+  if (n == 0) return SGP4_E_OFFSETS;  // nnz > 0 points cannot belong to no satellite
+  if (!consts || !offsets || !t || !r || !v || !err) return SGP4_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan) {
+    if (plan->consts != consts || plan->n != n || plan->offsets != offsets || plan->t != t || plan->nnz != nnz ||
+        plan->precision != precision || plan->r != r || plan->v != v || plan->err != err)
+      return SGP4_E_PLAN;
+    return hip_status(plan_launch_direct(plan, s));
+  }
+  const int64_t nchunks = (nnz + 63) / 64;
+  const unsigned grid = unsigned(std::min<int64_t>((nchunks + 3) / 4, int64_t(compute_units()) * 8));
+  return hip_status(launch_ragged(precision, 1, consts, n, offsets, t, nnz, nullptr, nullptr, nchunks, r, v, err, 256,
+                                  std::max(grid, 1u), s));
+}
+
+static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
+                      int64_t nnz, int precision, void* r, void* v, uint8_t* err, unsigned flags, int force_mode,
+                      int force_block, int force_per_cu, void* stream) {
+  if (!out) return SGP4_E_ARG;
+  *out = nullptr;
+  if (n <= 0 || nnz <= 0 || n > kMaxSats || mul_overflows(nnz, 3)) return SGP4_E_SIZE;
+  if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
+  if (!consts || !offsets || !t || !r || !v || !err) return SGP4_E_ARG;
+  if (force_mode >= 0 && (force_mode > 1 || (force_block != 64 && force_block != 128 && force_block != 256 &&
+                                             force_block != 512) || force_per_cu <= 0))
+    return SGP4_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int64_t> off(size_t(n) + 1);
+  if (hipMemcpyAsync(off.data(), offsets, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SGP4_E_HIP;
+  if (off[0] != 0 || off[size_t(n)] != nnz) return SGP4_E_OFFSETS;
+  for (int64_t i = 0; i < n; ++i)
+    if (off[size_t(i) + 1] < off[size_t(i)]) return SGP4_E_OFFSETS;
+
+  sgp4_plan* p = new sgp4_plan;
+  p->precision = precision; p->consts = consts; p->n = n; p->nnz = nnz; p->offsets = offsets; p->t = t;
+  p->r = r; p->v = v; p->err = err;
+
+  // Tile tables: tiles of <= 64 points of one satellite; chunk owners for the
+  // flat mapping (satellite whose list holds point 64*k).
+  std::vector<int64_t> ts;
+  std::vector<int32_t> tsat;
+  ts.reserve(size_t(nnz / 64 + n));
+  tsat.reserve(size_t(nnz / 64 + n));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t q = off[size_t(i)]; q < off[size_t(i) + 1]; q += 64) {
+      ts.push_back(q);
+      tsat.push_back(int32_t(i));
+    }
+  p->ntiles = int64_t(ts.size());
+  p->nchunks = (nnz + 63) / 64;
+  std::vector<int32_t> csat(size_t(p->nchunks));
+  {
+    int64_t i = 0;
+    for (int64_t k = 0; k < p->nchunks; ++k) {
+      const int64_t q = k * 64;
+      while (off[size_t(i) + 1] <= q) ++i;
+      csat[size_t(k)] = int32_t(i);
+    }
+  }
+  bool ok = hipMalloc(&p->tile_start, ts.size() * sizeof(int64_t)) == hipSuccess &&
+            hipMalloc(&p->tile_sat, tsat.size() * sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&p->chunk_sat, csat.size() * sizeof(int32_t)) == hipSuccess &&
+            hipMemcpyAsync(p->tile_start, ts.data(), ts.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) ==
+                hipSuccess &&
+            hipMemcpyAsync(p->tile_sat, tsat.data(), tsat.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) ==
+                hipSuccess &&
+            hipMemcpyAsync(p->chunk_sat, csat.data(), csat.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) ==
+                hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) { plan_free(p); return SGP4_E_HIP; }
+
+  const int cus = compute_units();
+  auto grid_for = [&](int mode, int block, int per_cu) {
+    const int64_t work = mode == 0 ? p->ntiles : p->nchunks;
+    const int64_t waves_needed = work;
+    const int64_t blocks_needed = (waves_needed + block / 64 - 1) / (block / 64);
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>(blocks_needed, int64_t(cus) * per_cu)));
+  };
+  // default choice (or the caller's fixed configuration)
+  p->mode = 0;
+  p->block = 256;
+  p->grid = grid_for(0, 256, 8);
+  if (force_mode >= 0) {
+    p->mode = force_mode;
+    p->block = force_block;
+    p->grid = grid_for(force_mode, force_block, force_per_cu);
+    flags &= ~unsigned(SGP4_PLAN_AUTOTUNE);
+  }
+
+  if (flags & SGP4_PLAN_AUTOTUNE) {
+    const std::string key = tune_key(p);
+    int m, b;
+    unsigned g;
+    double us;
+    if (cache_lookup(key, &m, &b, &g, &us)) {
+      p->mode = m; p->block = b; p->grid = std::min(g, grid_for(m, b, 1 << 20)); p->best_us = us;
+      p->from_cache = true;
+    } else {
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { plan_free(p); return SGP4_E_HIP; }
+      const int blocks[] = {128, 256, 512};
+      const int per_cu[] = {2, 4, 8, 16};
+      double best = 1e300;
+      for (int mode = 0; mode < 2; ++mode)
+        for (int b : blocks)
+          for (int pc : per_cu) {
+            sgp4_plan c = *p;
+            c.mode = mode; c.block = b; c.grid = grid_for(mode, b, pc);
+            c.graph = nullptr; c.exec = nullptr;
+            if (plan_launch_direct(&c, s) != hipSuccess) continue;  // warm-up
+            (void)hipEventRecord(e0, s);
+            const int reps = 3;
+            bool fine = true;
+            for (int k = 0; k < reps; ++k) fine = fine && plan_launch_direct(&c, s) == hipSuccess;
+            (void)hipEventRecord(e1, s);
+            if (!fine || hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double us_c = 1000.0 * ms / reps;
+            ++p->ncandidates;
+            if (us_c < best) { best = us_c; p->mode = mode; p->block = b; p->grid = c.grid; }
+          }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      // nothing of the candidates must stay owned by the copies
+      if (p->ncandidates == 0) { plan_free(p); return SGP4_E_HIP; }
+      p->best_us = best;
+      cache_store(key, p->mode, p->block, p->grid, best);
+    }
+  }
+
+  if (flags & SGP4_PLAN_GRAPH) {
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { plan_free(p); return SGP4_E_HIP; }
+    bool gok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (gok) {
+      const hipError_t le = plan_launch_direct(p, cs);
+      const hipError_t ce = hipStreamEndCapture(cs, &p->graph);
+      gok = le == hipSuccess && ce == hipSuccess &&
+            hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+    (void)hipStreamDestroy(cs);
+    if (!gok) { plan_free(p); return SGP4_E_HIP; }
+  }
+  *out = p;
+  return SGP4_OK;
+}
+
+int sgp4_plan_create(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
+                     int64_t nnz, int precision, void* r, void* v, uint8_t* err, unsigned flags, void* stream) {
+  return plan_build(out, consts, n, offsets, t, nnz, precision, r, v, err, flags, -1, 0, 0, stream);
+}
+
+int sgp4_plan_create_config(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
+                            int64_t nnz, int precision, void* r, void* v, uint8_t* err, int mode, int block,
+                            int waves_per_cu, unsigned flags, void* stream) {
+  if (mode < 0) return SGP4_E_ARG;
+  return plan_build(out, consts, n, offsets, t, nnz, precision, r, v, err, flags, mode, block, waves_per_cu, stream);
+}
+
+int sgp4_plan_launch(const sgp4_plan* plan, void* stream) {
+  if (!plan) return SGP4_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->exec) return hip_status(hipGraphLaunch(plan->exec, s));
+  return hip_status(plan_launch_direct(plan, s));
+}
+
+int sgp4_plan_describe(const sgp4_plan* plan, char* buf, size_t len) {
+  if (!plan || !buf || len == 0) return SGP4_E_ARG;
+  std::snprintf(buf, len,
+                "{\"mode\": \"%s\", \"block\": %d, \"grid\": %u, \"tiles\": %lld, \"chunks\": %lld, "
+                "\"tuned_us\": %.3f, \"candidates\": %d, \"from_cache\": %s, \"graph\": %s}",
+                plan->mode == 0 ? "tiles" : "flat", plan->block, plan->grid, (long long)plan->ntiles,
+                (long long)plan->nchunks, plan->best_us, plan->ncandidates, plan->from_cache ? "true" : "false",
+                plan->exec ? "true" : "false");
+  return SGP4_OK;
+}
+
+void sgp4_plan_destroy(sgp4_plan* plan) { plan_free(plan); }
+
+int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
+             const void* gr, const void* gv, double* gelem, void* stream) {
+  if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
+  if (precision != SGP4_FP64 && precision != SGP4_FP32_MIXED) return SGP4_E_PRECISION;
+  if (n == 0) return SGP4_OK;
+  if (!elem || !consts || !gelem || (T > 0 && (!t || !gr))) return SGP4_E_ARG;
+  return hip_status(launch_vjp(precision, n, elem, consts, t, T, gr, gv, gelem, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

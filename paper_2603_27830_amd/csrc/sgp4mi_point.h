@@ -1,0 +1,203 @@
+// Per-point SGP4 near-Earth propagation, templated on precision.
+//
+// One lane evaluates f(s, t) -> (r, v) for one (satellite, time) point, all in
+// registers (paper section 2.2: the whole routine fused, with validity checks
+// turned into per-point codes instead of early exits of the batch).  The
+// steps follow the published near-Earth model: secular gravity and drag,
+// long-period (J3) periodics, Kepler's equation for the eccentric longitude,
+// short-period (J2) periodics, orientation and the TEME state in km, km/s.
+//
+// Precision policy (TS = secular type, TP = periodic type):
+//   FP64        TS = double, TP = double
+//   FP32 plain  TS = float,  TP = float   (time since epoch rounded to float:
+//               the paper's 32-bit mode, section 4)
+//   FP32 mixed  TS = double, TP = float   (time since epoch, the n*t and drag
+//               polynomials, the angle sums and their reduction mod 2*pi in
+//               double; everything after the reduction in float)
+#pragma once
+
+#include "sgp4mi_common.h"
+
+namespace sgp4mi {
+
+template <class TS, class TP>
+struct SatC {
+  // secular (TS)
+  TS M0, Mdot, argp0, argpdot, node0, nodedot, nodecf, C1, bC4, t2cof, argpcof, Mcof, D2, D3, D4, bC5;
+  TS t3cof, t4cof, t5cof, n0pp, a0pp, e0;
+  double epoch_min;
+  // periodic (TP)
+  TP eta, dM0, sinM0, aycof, Lcof, c41, x1, x7, cosi, sini, i0;
+  uint32_t info;
+};
+
+template <class T> __device__ __forceinline__ const T* rows_of(const RecordView& rv);
+template <> __device__ __forceinline__ const double* rows_of<double>(const RecordView& rv) { return rv.f64; }
+template <> __device__ __forceinline__ const float* rows_of<float>(const RecordView& rv) { return rv.f32; }
+
+template <class TS, class TP>
+__device__ __forceinline__ SatC<TS, TP> load_sat(const RecordView& rv, int64_t i) {
+  const TS* s = rows_of<TS>(rv);
+  const TP* p = rows_of<TP>(rv);
+  const int64_t np = rv.npad;
+  SatC<TS, TP> c;
+  c.M0 = s[kM0 * np + i]; c.Mdot = s[kMdot * np + i]; c.argp0 = s[kArgp0 * np + i];
+  c.argpdot = s[kArgpdot * np + i]; c.node0 = s[kNode0 * np + i]; c.nodedot = s[kNodedot * np + i];
+  c.nodecf = s[kNodecf * np + i]; c.C1 = s[kC1 * np + i]; c.bC4 = s[kBC4 * np + i]; c.t2cof = s[kT2cof * np + i];
+  c.argpcof = s[kArgpcof * np + i]; c.Mcof = s[kMcof * np + i]; c.D2 = s[kD2 * np + i]; c.D3 = s[kD3 * np + i];
+  c.D4 = s[kD4 * np + i]; c.bC5 = s[kBC5 * np + i]; c.t3cof = s[kT3cof * np + i]; c.t4cof = s[kT4cof * np + i];
+  c.t5cof = s[kT5cof * np + i]; c.n0pp = s[kN0pp * np + i]; c.a0pp = s[kA0pp * np + i]; c.e0 = s[kE0 * np + i];
+  c.epoch_min = rv.f64[kEpochMin * np + i];
+  c.eta = p[kEta * np + i]; c.dM0 = p[kDM0 * np + i]; c.sinM0 = p[kSinM0 * np + i]; c.aycof = p[kAycof * np + i];
+  c.Lcof = p[kLcof * np + i]; c.c41 = p[kC41 * np + i]; c.x1 = p[kX1 * np + i]; c.x7 = p[kX7 * np + i];
+  c.cosi = p[kCosi * np + i]; c.sini = p[kSini * np + i]; c.i0 = p[kI0 * np + i];
+  c.info = rv.info[i];
+  return c;
+}
+
+__device__ __forceinline__ Grav load_grav(const RecordView& rv) {
+  Grav g;
+  g.ke = rv.hdr[kHKe];
+  g.radius = rv.hdr[kHRadius];
+  g.vkms = rv.hdr[kHVkms];
+  g.k2 = rv.hdr[kHK2];
+  return g;
+}
+
+// ------------------------------------------------------- typed primitives --
+__device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ double wrap(double x) { return wrap_pi(x); }
+__device__ __forceinline__ float wrap(float x) {
+  return fmaf(-6.28318530717958647692f, rintf(x * 0.15915494309189533577f), x);
+}
+__device__ __forceinline__ double sq_root(double x) { return sqrt(x); }
+__device__ __forceinline__ float sq_root(float x) { return sqrtf(x); }
+__device__ __forceinline__ double vabs(double x) { return fabs(x); }
+__device__ __forceinline__ float vabs(float x) { return fabsf(x); }
+template <class T> __device__ __forceinline__ T kepler_tol();
+template <> __device__ __forceinline__ double kepler_tol<double>() { return 1.0e-12; }
+template <> __device__ __forceinline__ float kepler_tol<float>() { return 1.0e-12f; }
+
+template <class TP>
+struct PointState {
+  TP r[3], v[3];
+};
+
+// Returns the point's code (0, 1, 2, 4, 6 or 7).  r and v are written for
+// codes 0 and 6 only.
+template <class TS, class TP, bool kMixedTol = false>
+__device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav& g, double t_abs, PointState<TP>& out) {
+  const uint32_t scode = c.info & kInfoCodeMask;
+  if (scode) return scode;
+
+  // Secular gravity.
+  const TS t = TS(t_abs - c.epoch_min);
+  const TS t2 = t * t;
+  const TS Mdf = c.M0 + c.Mdot * t;
+  const TS argpdf = c.argp0 + c.argpdot * t;
+  TS node = c.node0 + c.nodedot * t + c.nodecf * t2;
+  // Secular drag.
+  TS A = TS(1) - c.C1 * t;
+  TS Ed = c.bC4 * t;
+  TS Ld = c.t2cof * t2;
+  TS M = Mdf, argp = argpdf;
+  if (!(c.info & kInfoIsimp)) {
+    TP sMdf, cMdf;
+    sc(TP(wrap(Mdf)), &sMdf, &cMdf);
+    const TP x = TP(1) + c.eta * cMdf;
+    const TS dM = c.Mcof * TS(x * x * x - c.dM0);
+    const TS dargp = c.argpcof * t;
+    M = Mdf + dargp + dM;
+    argp = argpdf - dargp - dM;
+    const TS t3 = t2 * t, t4 = t3 * t;
+    A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
+    TP sM, cM;
+    sc(TP(wrap(M)), &sM, &cM);
+    Ed = Ed + c.bC5 * TS(sM - c.sinM0);
+    Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
+  }
+  const TS a_s = c.a0pp * A * A;
+  TS e_s = c.e0 - Ed;
+  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
+  if (e_s < TS(1.0e-6)) e_s = TS(1.0e-6);
+  M = M + c.n0pp * Ld;
+  const TS L = wrap(M + argp + node);
+  node = wrap(node);
+  argp = wrap(argp);
+
+  // Long-period periodics (J3).
+  const TP a = TP(a_s), e = TP(e_s);
+  const TP n = TP(g.ke) / (a * sq_root(a));
+  TP sw, cw;
+  sc(TP(argp), &sw, &cw);
+  const TP axn = e * cw;
+  const TP tau = TP(1) / (a * (TP(1) - e * e));
+  const TP ayn = e * sw + tau * c.aycof;
+  const TS LT = L + TS(tau * c.Lcof * axn);
+
+  // Kepler: psi - axn sin psi + ayn cos psi = U, Newton from psi = U with the
+  // step clamped to +-0.95; the loop ends when every lane of the wavefront has
+  // taken a step below the tolerance (at most 10 steps).
+  const TP U = TP(wrap(LT - node));
+  TP psi = U;
+  const TP tol = kMixedTol ? TP(1.0e-6) : kepler_tol<TP>();
+  TP sp, cp;
+  for (int k = 0; k < 10; ++k) {
+    sc(psi, &sp, &cp);
+    TP step = (U - ayn * cp + axn * sp - psi) / (TP(1) - axn * cp - ayn * sp);
+    step = step > TP(0.95) ? TP(0.95) : step;
+    step = step < TP(-0.95) ? TP(-0.95) : step;
+    psi = psi + step;
+    if (__all(vabs(step) < tol)) break;
+  }
+  sc(psi, &sp, &cp);
+
+  // Short-period preliminaries.
+  const TP ecE = axn * cp + ayn * sp;
+  const TP esE = axn * sp - ayn * cp;
+  const TP eL2 = axn * axn + ayn * ayn;
+  const TP pL = a * (TP(1) - eL2);
+  if (!(pL >= TP(0))) return 4;
+  const TP rl = a * (TP(1) - ecE);
+  const TP inv_rl = TP(1) / rl;
+  const TP rdotl = sq_root(a) * esE * inv_rl;
+  const TP rvdotl = sq_root(pL) * inv_rl;
+  const TP betal = sq_root(TP(1) - eL2);
+  const TP w = esE / (TP(1) + betal);
+  const TP sinu = a * inv_rl * (sp - ayn - axn * w);
+  const TP cosu = a * inv_rl * (cp - axn + ayn * w);
+  const TP u = atan2(sinu, cosu);
+  const TP sin2u = TP(2) * sinu * cosu;
+  const TP cos2u = TP(1) - TP(2) * sinu * sinu;
+
+  // Short-period periodics (J2).
+  const TP inv_pl = TP(1) / pL;
+  const TP k1 = TP(g.k2) * inv_pl;
+  const TP k2 = k1 * inv_pl;
+  const TP nk = n / TP(g.ke);
+  const TP mrt = rl * (TP(1) - TP(1.5) * k2 * betal * c.c41) + TP(0.5) * k1 * c.x1 * cos2u;
+  const TP su = u - TP(0.25) * k2 * c.x7 * sin2u;
+  const TP xnode = TP(node) + TP(1.5) * k2 * c.cosi * sin2u;
+  const TP xinc = c.i0 + TP(1.5) * k2 * c.cosi * c.sini * cos2u;
+  const TP mvt = rdotl - nk * k1 * c.x1 * sin2u;
+  const TP rvdot = rvdotl + nk * k1 * (c.x1 * cos2u + TP(1.5) * c.c41);
+
+  // Orientation and state.
+  TP ssu, csu, snod, cnod, sinc, cinc;
+  sc(su, &ssu, &csu);
+  sc(xnode, &snod, &cnod);
+  sc(xinc, &sinc, &cinc);
+  const TP xmx = -snod * cinc, xmy = cnod * cinc;
+  const TP ux = xmx * ssu + cnod * csu, uy = xmy * ssu + snod * csu, uz = sinc * ssu;
+  const TP vx = xmx * csu - cnod * ssu, vy = xmy * csu - snod * ssu, vz = sinc * csu;
+  const TP rk = mrt * TP(g.radius);
+  const TP vk = TP(g.vkms);
+  out.r[0] = rk * ux; out.r[1] = rk * uy; out.r[2] = rk * uz;
+  out.v[0] = vk * (mvt * ux + rvdot * vx);
+  out.v[1] = vk * (mvt * uy + rvdot * vy);
+  out.v[2] = vk * (mvt * uz + rvdot * vz);
+  return (mrt < TP(1)) ? 6u : 0u;
+}
+
+}  // namespace sgp4mi

@@ -1,0 +1,84 @@
+"""The C-ABI library loads, exports every symbol its header declares, and its
+host-side argument checks reject bad calls before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2603_27830_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgp4mi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgp4_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _native.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert {s[0] for s in _native.SIGNATURES} == set(names)
+
+
+def test_version_strerror_and_sizes():
+    L = _native.lib()
+    assert L.sgp4_version() == 1
+    for code in range(-7, 1):
+        assert _native.strerror(code)
+    assert L.sgp4_consts_bytes(-1) == 0
+    assert L.sgp4_consts_bytes(1000) > L.sgp4_consts_bytes(10) > 0
+
+
+def test_argument_errors_need_no_gpu():
+    L = _native.lib()
+    E = {v: k for k, v in _native.ERRORS.items()}
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    # negative sizes
+    assert L.sgp4_propagate(fake, -1, fake, 10, 0, fake, fake, fake, None) == E["SGP4_E_SIZE"]
+    assert L.sgp4_propagate(fake, 10, fake, -1, 0, fake, fake, fake, None) == E["SGP4_E_SIZE"]
+    # n * T overflow
+    assert L.sgp4_propagate(fake, 2**31 - 1, fake, 2**40, 0, fake, fake, fake, None) == E["SGP4_E_SIZE"]
+    # precision
+    assert L.sgp4_propagate(fake, 10, fake, 10, 3, fake, fake, fake, None) == E["SGP4_E_PRECISION"]
+    assert L.sgp4_vjp(10, fake, fake, fake, 10, 1, fake, None, fake, None) == E["SGP4_E_PRECISION"]
+    # null pointers
+    assert L.sgp4_propagate(None, 10, fake, 10, 0, fake, fake, fake, None) == E["SGP4_E_ARG"]
+    assert L.sgp4_propagate(fake, 10, fake, 10, 0, fake, None, fake, None) == E["SGP4_E_ARG"]
+    # block size
+    assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 96, None) == E["SGP4_E_ARG"]
+    # empty batches are valid no-ops
+    assert L.sgp4_propagate(fake, 0, fake, 10, 0, fake, fake, fake, None) == 0
+    assert L.sgp4_propagate(fake, 10, fake, 0, 0, fake, fake, fake, None) == 0
+    assert L.sgp4_propagate_ragged(fake, 10, fake, fake, 0, 0, fake, fake, fake, None, None) == 0
+    # points with no satellite
+    assert L.sgp4_propagate_ragged(fake, 0, fake, fake, 5, 0, fake, fake, fake, None, None) == E["SGP4_E_OFFSETS"]
+    # gravity: J3 without J2, non-positive mu
+    g = (ctypes.c_double * 5)(398600.8, 6378.135, 0.0, -2.5e-6, 0.0)
+    assert L.sgp4_init(g, 10, fake, fake, None, None) == E["SGP4_E_GRAVITY"]
+    g = (ctypes.c_double * 5)(0.0, 6378.135, 1e-3, 0.0, 0.0)
+    assert L.sgp4_init(g, 10, fake, fake, None, None) == E["SGP4_E_GRAVITY"]
+    assert L.sgp4_init(None, -5, fake, fake, None, None) == E["SGP4_E_SIZE"]
+    assert L.sgp4_init(None, 5, None, fake, None, None) == E["SGP4_E_ARG"]
+    # plan creation
+    out = ctypes.c_void_p()
+    assert L.sgp4_plan_create(None, fake, 10, fake, fake, 10, 0, fake, fake, fake, 0, None) == E["SGP4_E_ARG"]
+    assert L.sgp4_plan_create(ctypes.byref(out), fake, 10, fake, fake, 10, 7, fake, fake, fake, 0,
+                              None) == E["SGP4_E_PRECISION"]
+    assert L.sgp4_plan_launch(None, None) == E["SGP4_E_ARG"]
+    L.sgp4_plan_destroy(None)
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2603_27830_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f
