@@ -17,6 +17,7 @@
 #pragma once
 
 #include "sgp4mi_common.h"
+#include "sgp4mi_math.h"
 
 namespace sgp4mi {
 
@@ -65,19 +66,40 @@ __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
 }
 
 // ------------------------------------------------------- typed primitives --
-__device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
+// Sine and cosine of an angle held in the secular type, evaluated in the
+// periodic type (reduction in the secular type).
+template <class TS, class TP>
+struct Trig;
+template <>
+struct Trig<double, double> {
+  static __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos_rr(x, s, c); }
+};
+template <>
+struct Trig<float, float> {
+  static __device__ __forceinline__ void sc(float x, float* s, float* c) { sincos_rr(x, s, c); }
+};
+template <>
+struct Trig<double, float> {
+  static __device__ __forceinline__ void sc(double x, float* s, float* c) { sincos_mx(x, s, c); }
+};
+
 __device__ __forceinline__ double wrap(double x) { return wrap_pi(x); }
 __device__ __forceinline__ float wrap(float x) {
   return fmaf(-6.28318530717958647692f, rintf(x * 0.15915494309189533577f), x);
 }
 __device__ __forceinline__ double sq_root(double x) { return sqrt(x); }
-__device__ __forceinline__ float sq_root(float x) { return sqrtf(x); }
+__device__ __forceinline__ float sq_root(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double vabs(double x) { return fabs(x); }
 __device__ __forceinline__ float vabs(float x) { return fabsf(x); }
+__device__ __forceinline__ double arctan2(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float arctan2(float y, float x) { return atan2f(y, x); }
+// Kepler tolerance: the model's 1e-12 in double; in float the eccentric
+// longitude offset is resolved to ~1e-10, so 1e-7 rad (sub-millimetre) ends it.
 template <class T> __device__ __forceinline__ T kepler_tol();
 template <> __device__ __forceinline__ double kepler_tol<double>() { return 1.0e-12; }
-template <> __device__ __forceinline__ float kepler_tol<float>() { return 1.0e-12f; }
+template <> __device__ __forceinline__ float kepler_tol<float>() { return 1.0e-7f; }
 
 template <class TP>
 struct PointState {
@@ -86,8 +108,17 @@ struct PointState {
 
 // Returns the point's code (0, 1, 2, 4, 6 or 7).  r and v are written for
 // codes 0 and 6 only.
-template <class TS, class TP, bool kMixedTol = false>
+//
+// Reformulations relative to the textbook order, each an identity up to
+// rounding: sin M from sin/cos of the drag-free M by a small rotation; the
+// Kepler iteration carries psi - U and rotates (sin psi, cos psi) by each
+// Newton step; the argument of latitude u never leaves its (sin, cos) pair
+// (no atan2: the short-period correction is a rotation of the normalised
+// pair); sin/cos of the corrected inclination rotate those of i0.  Rotations
+// fall back to a full evaluation when the angle exceeds kRotMax.
+template <class TS, class TP>
 __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav& g, double t_abs, PointState<TP>& out) {
+  using TR = Trig<TS, TP>;
   const uint32_t scode = c.info & kInfoCodeMask;
   if (scode) return scode;
 
@@ -103,17 +134,18 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TS Ld = c.t2cof * t2;
   TS M = Mdf, argp = argpdf;
   if (!(c.info & kInfoIsimp)) {
-    TP sMdf, cMdf;
-    sc(TP(wrap(Mdf)), &sMdf, &cMdf);
-    const TP x = TP(1) + c.eta * cMdf;
+    TP sM, cM;
+    TR::sc(wrap(Mdf), &sM, &cM);
+    const TP x = TP(1) + c.eta * cM;
     const TS dM = c.Mcof * TS(x * x * x - c.dM0);
     const TS dargp = c.argpcof * t;
-    M = Mdf + dargp + dM;
-    argp = argpdf - dargp - dM;
+    const TS dMa = dargp + dM;
+    M = Mdf + dMa;
+    argp = argpdf - dMa;
     const TS t3 = t2 * t, t4 = t3 * t;
     A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
-    TP sM, cM;
-    sc(TP(wrap(M)), &sM, &cM);
+    if (vabs(dMa) <= TS(kRotMax)) rotate_small(&sM, &cM, TP(dMa));
+    else TR::sc(wrap(M), &sM, &cM);
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
     Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
   }
@@ -124,34 +156,32 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   M = M + c.n0pp * Ld;
   const TS L = wrap(M + argp + node);
   node = wrap(node);
-  argp = wrap(argp);
 
   // Long-period periodics (J3).
   const TP a = TP(a_s), e = TP(e_s);
-  const TP n = TP(g.ke) / (a * sq_root(a));
   TP sw, cw;
-  sc(TP(argp), &sw, &cw);
+  TR::sc(wrap(argp), &sw, &cw);
   const TP axn = e * cw;
-  const TP tau = TP(1) / (a * (TP(1) - e * e));
+  const TP tau = rcp(a * (TP(1) - e * e));
   const TP ayn = e * sw + tau * c.aycof;
   const TS LT = L + TS(tau * c.Lcof * axn);
 
   // Kepler: psi - axn sin psi + ayn cos psi = U, Newton from psi = U with the
-  // step clamped to +-0.95; the loop ends when every lane of the wavefront has
-  // taken a step below the tolerance (at most 10 steps).
-  const TP U = TP(wrap(LT - node));
-  TP psi = U;
-  const TP tol = kMixedTol ? TP(1.0e-6) : kepler_tol<TP>();
+  // step clamped to +-0.95; dpsi = psi - U.  The loop ends when every lane of
+  // the wavefront has taken a step below the tolerance (at most 10 steps).
+  const TS U = wrap(LT - node);
   TP sp, cp;
+  TR::sc(U, &sp, &cp);
+  TP dpsi = TP(0);
   for (int k = 0; k < 10; ++k) {
-    sc(psi, &sp, &cp);
-    TP step = (U - ayn * cp + axn * sp - psi) / (TP(1) - axn * cp - ayn * sp);
+    TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
     step = step > TP(0.95) ? TP(0.95) : step;
     step = step < TP(-0.95) ? TP(-0.95) : step;
-    psi = psi + step;
-    if (__all(vabs(step) < tol)) break;
+    dpsi = dpsi + step;
+    if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
+    else TR::sc(U + TS(dpsi), &sp, &cp);
+    if (__all(vabs(step) < kepler_tol<TP>())) break;
   }
-  sc(psi, &sp, &cp);
 
   // Short-period preliminaries.
   const TP ecE = axn * cp + ayn * sp;
@@ -160,34 +190,46 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP pL = a * (TP(1) - eL2);
   if (!(pL >= TP(0))) return 4;
   const TP rl = a * (TP(1) - ecE);
-  const TP inv_rl = TP(1) / rl;
-  const TP rdotl = sq_root(a) * esE * inv_rl;
+  const TP inv_rl = rcp(rl);
+  const TP sqa = sq_root(a);
+  const TP rdotl = sqa * esE * inv_rl;
   const TP rvdotl = sq_root(pL) * inv_rl;
   const TP betal = sq_root(TP(1) - eL2);
-  const TP w = esE / (TP(1) + betal);
-  const TP sinu = a * inv_rl * (sp - ayn - axn * w);
-  const TP cosu = a * inv_rl * (cp - axn + ayn * w);
-  const TP u = atan2(sinu, cosu);
+  const TP w = esE * rcp(TP(1) + betal);
+  const TP ar = a * inv_rl;
+  const TP sinu = ar * (sp - ayn - axn * w);
+  const TP cosu = ar * (cp - axn + ayn * w);
   const TP sin2u = TP(2) * sinu * cosu;
   const TP cos2u = TP(1) - TP(2) * sinu * sinu;
 
   // Short-period periodics (J2).
-  const TP inv_pl = TP(1) / pL;
+  const TP inv_pl = rcp(pL);
   const TP k1 = TP(g.k2) * inv_pl;
   const TP k2 = k1 * inv_pl;
-  const TP nk = n / TP(g.ke);
+  const TP nk = rcp(a * sqa);  // n / ke
   const TP mrt = rl * (TP(1) - TP(1.5) * k2 * betal * c.c41) + TP(0.5) * k1 * c.x1 * cos2u;
-  const TP su = u - TP(0.25) * k2 * c.x7 * sin2u;
-  const TP xnode = TP(node) + TP(1.5) * k2 * c.cosi * sin2u;
-  const TP xinc = c.i0 + TP(1.5) * k2 * c.cosi * c.sini * cos2u;
+  const TP du = TP(-0.25) * k2 * c.x7 * sin2u;
+  const TP dnode = TP(1.5) * k2 * c.cosi * sin2u;
+  const TP dinc = TP(1.5) * k2 * c.cosi * c.sini * cos2u;
   const TP mvt = rdotl - nk * k1 * c.x1 * sin2u;
   const TP rvdot = rvdotl + nk * k1 * (c.x1 * cos2u + TP(1.5) * c.c41);
 
-  // Orientation and state.
-  TP ssu, csu, snod, cnod, sinc, cinc;
-  sc(su, &ssu, &csu);
-  sc(xnode, &snod, &cnod);
-  sc(xinc, &sinc, &cinc);
+  // Orientation: sin/cos of u_k = u + du, i_k = i0 + dinc, node_k = node + dnode.
+  TP ssu, csu;
+  if (vabs(du) <= TP(kRotMax)) {
+    const TP h = rsq(sinu * sinu + cosu * cosu);
+    ssu = sinu * h;
+    csu = cosu * h;
+    rotate_small(&ssu, &csu, du);
+  } else {
+    TR::sc(TS(arctan2(sinu, cosu) + du), &ssu, &csu);
+  }
+  TP sinc = c.sini, cinc = c.cosi;
+  if (vabs(dinc) <= TP(kRotMax)) rotate_small(&sinc, &cinc, dinc);
+  else TR::sc(TS(c.i0 + dinc), &sinc, &cinc);
+  TP snod, cnod;
+  TR::sc(node + TS(dnode), &snod, &cnod);
+
   const TP xmx = -snod * cinc, xmy = cnod * cinc;
   const TP ux = xmx * ssu + cnod * csu, uy = xmy * ssu + snod * csu, uz = sinc * ssu;
   const TP vx = xmx * csu - cnod * ssu, vy = xmy * csu - snod * ssu, vz = sinc * csu;

@@ -32,15 +32,6 @@ __device__ __forceinline__ void store_point(TP* __restrict__ r, TP* __restrict__
   st_nt(err + p, uint8_t(code));
 }
 
-template <class TS, class TP>
-struct Mixed {
-  static constexpr bool value = false;
-};
-template <>
-struct Mixed<double, float> {
-  static constexpr bool value = true;
-};
-
 // ------------------------------------------------------------------ dense --
 template <class TS, class TP, int kBlock>
 __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const double* __restrict__ t, int64_t T,
@@ -51,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const doub
   const Grav g = load_grav(rv);
   for (int64_t j = int64_t(blockIdx.y) * kBlock + threadIdx.x; j < T; j += int64_t(gridDim.y) * kBlock) {
     PointState<TP> s;
-    const uint32_t code = sgp4_point<TS, TP, Mixed<TS, TP>::value>(c, g, t[j], s);
+    const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
     store_point(r, v, err, P, i * T + j, code, s);
   }
 }
@@ -79,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int6
     const int64_t p = start + lane;
     if (p < end && p - start < 64) {
       PointState<TP> s;
-      const uint32_t code = sgp4_point<TS, TP, Mixed<TS, TP>::value>(c, g, t[p], s);
+      const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
       store_point(r, v, err, nnz, p, code, s);
     }
   }
@@ -119,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64
       while (sat + 1 < n && offsets[sat + 1] <= p) ++sat;
       const SatC<TS, TP> c = load_sat<TS, TP>(rv, sat);
       PointState<TP> s;
-      const uint32_t code = sgp4_point<TS, TP, Mixed<TS, TP>::value>(c, g, t[p], s);
+      const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
       store_point(r, v, err, nnz, p, code, s);
     }
   }

@@ -115,15 +115,50 @@ def crafted_elements():
     return np.array(cols, dtype=np.float64).T.copy()
 
 
+def conditioning(el, t, trials=4, rel=1e-15):
+    """Oracle-only conditioning of each point: perturb the seven elements by
+    +-rel (relative, a few ulps) and record which codes the oracle reaches and how far the
+    state moves.  A decision that flips under such a perturbation is a
+    threshold tie of the FP64 computation itself."""
+    ro, vo, eo = oracle.propagate(el, t)
+    rng = np.random.default_rng(0)
+    codes = [eo]
+    move = np.zeros(eo.shape)
+    for _ in range(trials):
+        pert = el.copy()
+        pert[:7] *= 1 + rel * rng.choice([-1.0, 1.0], size=(7, el.shape[1]))
+        r2, _, e2 = oracle.propagate(pert, t)
+        codes.append(e2)
+        d = np.nan_to_num(np.max(np.abs(r2 - ro), axis=0), nan=np.inf)
+        move = np.maximum(move, d)
+    codes = np.stack(codes)
+    stable = np.all(codes == eo[None], axis=0)
+    return ro, vo, eo, codes, stable, move
+
+
 def test_edge_cases_and_error_codes_fp64():
+    """Crafted element sets: codes bit-exact wherever the FP64 decision is
+    well conditioned; at ties the GPU's code must be one the oracle reaches
+    under a 1e-15 relative perturbation.  States are compared (1e-6 km) where
+    the oracle's state moves by less than 1e-7 km under that perturbation."""
     el = crafted_elements()
     t = np.linspace(-1440.0, 10080.0, 97)
     say(f"[gpu] crafted edge cases n={el.shape[1]} fp64")
     r, v, err = gpu_dense(el, t, "fp64")
-    ro, vo, eo = oracle.propagate(el, t)
-    check_fp64(r, v, err, ro, vo, eo)
-    codes = set(np.unique(eo).tolist())
-    assert {0, 1, 2, 4, 6, 7} <= codes, codes
+    ro, vo, eo, codes, stable, move = conditioning(el, t)
+    say(f"  threshold ties: {int((~stable).sum())} of {stable.size} points")
+    assert (~stable).sum() <= 0.02 * stable.size
+    assert np.array_equal(err[stable], eo[stable])
+    assert np.all(np.any(codes == err[None], axis=0))
+    bad = (err != 0) & (err != 6)
+    assert np.all(np.isnan(r[:, bad])) and np.all(np.isnan(v[:, bad]))
+    well = stable & ((eo == 0) | (eo == 6)) & (move < 1e-7)
+    assert well.sum() >= 500
+    # the ordinary element sets among the crafted ones are all well conditioned
+    assert np.all(well[[5, 6, 7, 9, 10, 15]] | ~((eo[[5, 6, 7, 9, 10, 15]] == 0) | (eo[[5, 6, 7, 9, 10, 15]] == 6)))
+    assert np.max(np.abs(r[:, well] - ro[:, well])) <= 1e-6
+    assert np.max(np.abs(v[:, well] - vo[:, well])) <= 1e-9
+    assert {0, 1, 2, 4, 6, 7} <= set(np.unique(eo).tolist())
 
 
 def test_two_body_gravity_fp64():
