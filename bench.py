@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--ragged", action="store_true", help="also time the 1M-satellite ragged catalogue")
     ap.add_argument("--vjp", action="store_true", help="also time the VJP on the 9341 x 1000 grid")
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (3 launches), the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -144,6 +146,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4, "launches": 3}))
+        return
     cat = synth.config1()
     elem = torch.from_numpy(cat.elem).to(dev)
     t = torch.from_numpy(cat.t).to(dev)
@@ -164,8 +174,9 @@ def main():
             sg.propagate(rec, t, name, out=out)
 
         s = time_steps(step, args.steps, args.warmup, torch)
-        k = kernel_time(prop_only, torch)
-        pp = paper_protocol(step, torch)
+        # --only is the profiling mode: a handful of launches, no adaptive repeats
+        k = kernel_time(prop_only, torch, reps=2 if args.only else 20)
+        pp = paper_protocol(step, torch) if not args.only else float("nan")
         paths[name] = {
             "points_per_s": P / s, "ms_per_step": s * 1e3, "propagate_kernel_us": k * 1e6,
             "propagate_only_points_per_s": P / k, "paper_protocol_min_ms": pp * 1e3,
