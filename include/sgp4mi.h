@@ -87,9 +87,13 @@ int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, u
 int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                    uint8_t* err, void* stream);
 
-/* As sgp4_propagate with an explicit workgroup size (64, 128, 256 or 512). */
+/* As sgp4_propagate with an explicit launch configuration: config is the
+ * workgroup size (64, 128, 256 or 512), optionally OR'd with
+ * SGP4_CFG_SCALAR_CONSTS to hold each satellite's constants in scalar
+ * registers instead of vector registers.  Output is identical. */
+enum { SGP4_CFG_SCALAR_CONSTS = 0x10000 };
 int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
-                      uint8_t* err, int block, void* stream);
+                      uint8_t* err, int config, void* stream);
 
 /* Opaque ragged-propagation plan (host object owning device tile tables and
  * a captured HIP graph). */

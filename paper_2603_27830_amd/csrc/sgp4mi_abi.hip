@@ -20,7 +20,7 @@ namespace sgp4mi {
 hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
                        hipStream_t s);
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, hipStream_t s);
+                        uint8_t* err, int block, bool vec, hipStream_t s);
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
@@ -186,13 +186,17 @@ int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, u
 }
 
 int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
-                      uint8_t* err, int block, void* stream) {
+                      uint8_t* err, int config, void* stream) {
   if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
   if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
+  const int block = config & 0xffff;
+  const bool scalar = (config & SGP4_CFG_SCALAR_CONSTS) != 0;
+  if ((config & ~(0xffff | SGP4_CFG_SCALAR_CONSTS)) != 0) return SGP4_E_ARG;
   if (block != 64 && block != 128 && block != 256 && block != 512) return SGP4_E_ARG;
   if (n == 0 || T == 0) return SGP4_OK;
   if (!consts || !t || !r || !v || !err) return SGP4_E_ARG;
-  return hip_status(launch_dense(precision, consts, n, t, T, r, v, err, block, static_cast<hipStream_t>(stream)));
+  return hip_status(
+      launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, static_cast<hipStream_t>(stream)));
 }
 
 int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,

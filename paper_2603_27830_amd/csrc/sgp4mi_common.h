@@ -11,11 +11,14 @@ namespace sgp4mi {
 // The record produced by initialisation (the model's per-satellite constants,
 // computed once and reused for every time; paper section 3.1 notes that the
 // C++ baseline keeps initialisation separate while jaxsgp4 fuses it).
-// Layout in device memory, all SoA with a row stride of npad = round_up(n, 64):
+// Layout in device memory:
 //   [header: 64 doubles]
-//   [f64 rows: kNRec x npad doubles]   full-precision constants
-//   [f32 rows: kNRec x npad floats]    the same constants rounded to float
-//   [info:     npad uint32]            bits 0-7 satellite code, bit 8 isimp
+//   [n slots of kSlotBytes = 512 bytes, one per satellite]:
+//       bytes   0..271  kNRec doubles (full-precision constants)
+//       bytes 272..407  kNRec floats  (the same constants rounded to float)
+//       bytes 408..411  uint32 info: bits 0-7 satellite code, bit 8 isimp
+// One contiguous slot per satellite: a wavefront working on one satellite
+// fetches its constants with a few wide loads from one base address.
 enum Rec : int {
   kM0, kMdot, kArgp0, kArgpdot, kNode0, kNodedot, kNodecf, kC1, kBC4, kT2cof,
   kArgpcof, kEta, kMcof, kDM0, kD2, kD3, kD4, kBC5, kSinM0, kT3cof, kT4cof, kT5cof,
@@ -30,29 +33,33 @@ constexpr double kMagic = 20260331.0;
 constexpr uint32_t kInfoCodeMask = 0xffu;
 constexpr uint32_t kInfoIsimp = 0x100u;
 
+constexpr int kSlotBytes = 512;
+constexpr int kSlotF32 = kNRec * 8;            // byte offset of the float copies
+constexpr int kSlotInfo = kSlotF32 + kNRec * 4;  // byte offset of the info word
+static_assert(kSlotInfo + 4 <= kSlotBytes, "record slot overflow");
+
+struct alignas(16) Slot {
+  double d[kNRec];
+  float f[kNRec];
+  uint32_t info;
+  uint32_t pad[(kSlotBytes - kSlotInfo - 4) / 4];
+};
+static_assert(sizeof(Slot) == kSlotBytes, "slot size");
+
 inline int64_t npad_of(int64_t n) { return (n + 63) / 64 * 64; }
-inline size_t record_bytes(int64_t n) {
-  const int64_t np = npad_of(n);
-  return size_t(kHCount) * 8 + size_t(kNRec) * 8 * np + size_t(kNRec) * 4 * np + 4 * np;
-}
+inline size_t record_bytes(int64_t n) { return size_t(kHCount) * 8 + size_t(kSlotBytes) * size_t(n > 0 ? n : 0); }
 
 struct RecordView {
   const double* hdr;
-  const double* f64;   // row k at f64 + k * npad
-  const float* f32;    // row k at f32 + k * npad
-  const uint32_t* info;
-  int64_t npad;
+  const Slot* slots;
 };
 
 inline RecordView view_of(const void* base, int64_t n) {
+  (void)n;
   RecordView v;
-  const int64_t np = npad_of(n);
   const char* b = static_cast<const char*>(base);
   v.hdr = reinterpret_cast<const double*>(b);
-  v.f64 = reinterpret_cast<const double*>(b + kHCount * 8);
-  v.f32 = reinterpret_cast<const float*>(b + kHCount * 8 + size_t(kNRec) * 8 * np);
-  v.info = reinterpret_cast<const uint32_t*>(b + kHCount * 8 + size_t(kNRec) * 12 * np);
-  v.npad = np;
+  v.slots = reinterpret_cast<const Slot*>(b + kHCount * 8);
   return v;
 }
 

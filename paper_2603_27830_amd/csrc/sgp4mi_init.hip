@@ -18,9 +18,7 @@ struct InitArgs {
   int64_t n, npad;
   const double* elem;   // [8][n]
   double* hdr;
-  double* f64;
-  float* f32;
-  uint32_t* info;
+  Slot* slots;
   uint8_t* user_flags;  // nullable
   double mu, radius, j2, j3, j4;
 };
@@ -171,12 +169,13 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs a) {
   rec[kN0pp] = nbar; rec[kA0pp] = abar; rec[kE0] = ecco; rec[kAycof] = aycof; rec[kLcof] = xlcof;
   rec[kC41] = con41; rec[kX1] = x1mth2; rec[kX7] = x7thm1; rec[kCosi] = cos_i; rec[kSini] = sin_i;
   rec[kI0] = inclo; rec[kEpochMin] = 1440.0 * epoch;
+  Slot* slot = a.slots + i;
 #pragma unroll
   for (int k = 0; k < kNRec; ++k) {
-    a.f64[k * a.npad + i] = rec[k];
-    a.f32[k * a.npad + i] = float(rec[k]);
+    slot->d[k] = rec[k];
+    slot->f[k] = float(rec[k]);
   }
-  a.info[i] = code | (isimp ? kInfoIsimp : 0u);
+  slot->info = code | (isimp ? kInfoIsimp : 0u);
   if (a.user_flags) {
     uint8_t f = 0;
     if (code == 7) f |= 1;
@@ -194,9 +193,7 @@ hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* c
   a.elem = elem;
   char* b = static_cast<char*>(consts);
   a.hdr = reinterpret_cast<double*>(b);
-  a.f64 = reinterpret_cast<double*>(b + kHCount * 8);
-  a.f32 = reinterpret_cast<float*>(b + kHCount * 8 + size_t(kNRec) * 8 * a.npad);
-  a.info = reinterpret_cast<uint32_t*>(b + kHCount * 8 + size_t(kNRec) * 12 * a.npad);
+  a.slots = reinterpret_cast<Slot*>(b + kHCount * 8);
   a.user_flags = user_flags;
   a.mu = g[0]; a.radius = g[1]; a.j2 = g[2]; a.j3 = g[3]; a.j4 = g[4];
   const int64_t blocks = (n + 255) / 256;

@@ -33,23 +33,45 @@ __device__ __forceinline__ void quadrant(int q, T sr, T cr, T* s, T* c) {
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// Double-precision coefficients live in constant memory: gfx9 VALU
+// instructions take no 64-bit literals, and scalar-register operands (one per
+// instruction) avoid holding every coefficient in a vector register pair.
+__constant__ double kSinCos64[17] = {
+    -7.6471637318198164759e-13,  // -1/15!
+    1.6059043836821614599e-10,   // 1/13!
+    -2.5052108385441718775e-8,   // -1/11!
+    2.7557319223985890653e-6,    // 1/9!
+    -1.9841269841269841270e-4,   // -1/7!
+    8.3333333333333333333e-3,    // 1/5!
+    -1.6666666666666666667e-1,   // -1/3!
+    4.7794773323873852974e-14,   // 1/16!
+    -1.1470745597729724714e-11,  // -1/14!
+    2.0876756987868098979e-9,    // 1/12!
+    -2.7557319223985890653e-7,   // -1/10!
+    2.4801587301587301587e-5,    // 1/8!
+    -1.3888888888888888889e-3,   // -1/6!
+    4.1666666666666666667e-2,    // 1/4!
+    0.63661977236758134308,      // 2/pi
+    1.5707963267948966192,       // pi/2 (double nearest)
+    6.123233995736766036e-17,    // pi/2 minus the above
+};
+
 __device__ __forceinline__ void series(double r, double* s, double* c) {
+  const double* k = kSinCos64;
   const double r2 = r * r;
-  double ps = -7.6471637318198164759e-13;       // -1/15!
-  ps = fma(ps, r2, 1.6059043836821614599e-10);  // 1/13!
-  ps = fma(ps, r2, -2.5052108385441718775e-8);  // -1/11!
-  ps = fma(ps, r2, 2.7557319223985890653e-6);   // 1/9!
-  ps = fma(ps, r2, -1.9841269841269841270e-4);  // -1/7!
-  ps = fma(ps, r2, 8.3333333333333333333e-3);   // 1/5!
-  ps = fma(ps, r2, -1.6666666666666666667e-1);  // -1/3!
+  double ps = fma(k[0], r2, k[1]);
+  ps = fma(ps, r2, k[2]);
+  ps = fma(ps, r2, k[3]);
+  ps = fma(ps, r2, k[4]);
+  ps = fma(ps, r2, k[5]);
+  ps = fma(ps, r2, k[6]);
   *s = fma(ps * r2, r, r);
-  double pc = 4.7794773323873852974e-14;        // 1/16!
-  pc = fma(pc, r2, -1.1470745597729724714e-11); // -1/14!
-  pc = fma(pc, r2, 2.0876756987868098979e-9);   // 1/12!
-  pc = fma(pc, r2, -2.7557319223985890653e-7);  // -1/10!
-  pc = fma(pc, r2, 2.4801587301587301587e-5);   // 1/8!
-  pc = fma(pc, r2, -1.3888888888888888889e-3);  // -1/6!
-  pc = fma(pc, r2, 4.1666666666666666667e-2);   // 1/4!
+  double pc = fma(k[7], r2, k[8]);
+  pc = fma(pc, r2, k[9]);
+  pc = fma(pc, r2, k[10]);
+  pc = fma(pc, r2, k[11]);
+  pc = fma(pc, r2, k[12]);
+  pc = fma(pc, r2, k[13]);
   pc = fma(pc, r2, -0.5);
   *c = fma(pc, r2, 1.0);
 }
@@ -70,9 +92,9 @@ __device__ __forceinline__ void series(float r, float* s, float* c) {
 }
 
 __device__ __forceinline__ void sincos_rr(double x, double* s, double* c) {
-  const double k = rint(x * kTwoOverPi);
-  double r = fma(-k, kPio2Hi, x);
-  r = fma(-k, kPio2Lo, r);
+  const double k = rint(x * kSinCos64[14]);
+  double r = fma(-k, kSinCos64[15], x);
+  r = fma(-k, kSinCos64[16], r);
   double sr, cr;
   series(r, &sr, &cr);
   quadrant(int(k), sr, cr, s, c);
@@ -88,21 +110,22 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
 }
 
 __device__ __forceinline__ void sincos_mx(double x, float* s, float* c) {
-  const double k = rint(x * kTwoOverPi);
-  double r = fma(-k, kPio2Hi, x);
-  r = fma(-k, kPio2Lo, r);
+  const double k = rint(x * kSinCos64[14]);
+  double r = fma(-k, kSinCos64[15], x);
+  r = fma(-k, kSinCos64[16], r);
   float sr, cr;
   series(float(r), &sr, &cr);
   quadrant(int(k), sr, cr, s, c);
 }
 
 __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
+  const double* k = kSinCos64;
   const double d2 = d * d;
-  double ps = fma(d2, -1.9841269841269841270e-4, 8.3333333333333333333e-3);
-  ps = fma(ps, d2, -1.6666666666666666667e-1);
+  double ps = fma(d2, k[4], k[5]);
+  ps = fma(ps, d2, k[6]);
   *sd = fma(ps * d2, d, d);
-  double pc = fma(d2, 2.4801587301587301587e-5, -1.3888888888888888889e-3);
-  pc = fma(pc, d2, 4.1666666666666666667e-2);
+  double pc = fma(d2, k[11], k[12]);
+  pc = fma(pc, d2, k[13]);
   pc = fma(pc, d2, -0.5);
   *cd = fma(pc, d2, 1.0);
 }

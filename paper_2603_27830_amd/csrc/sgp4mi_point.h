@@ -32,27 +32,40 @@ struct SatC {
   uint32_t info;
 };
 
-template <class T> __device__ __forceinline__ const T* rows_of(const RecordView& rv);
-template <> __device__ __forceinline__ const double* rows_of<double>(const RecordView& rv) { return rv.f64; }
-template <> __device__ __forceinline__ const float* rows_of<float>(const RecordView& rv) { return rv.f32; }
+template <class T> __device__ __forceinline__ const T* rows_of(const Slot* sp);
+template <> __device__ __forceinline__ const double* rows_of<double>(const Slot* sp) { return sp->d; }
+template <> __device__ __forceinline__ const float* rows_of<float>(const Slot* sp) { return sp->f; }
 
-template <class TS, class TP>
+// The same address seen as a per-lane value: loads through it are vector
+// loads into VGPRs (one broadcast fetch per wavefront when every lane holds the
+// same satellite) instead of scalar loads into SGPRs.  With ~34 constants per
+// satellite, SGPR residency overflows the scalar file and every VALU operation
+// reading two of them needs an extra move; VGPR residency has neither cost.
+template <class T>
+__device__ __forceinline__ const T* lane_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
+  asm volatile("v_mov_b32 %0, %0" : "+v"(lo));
+  asm volatile("v_mov_b32 %0, %0" : "+v"(hi));
+  return reinterpret_cast<const T*>((uint64_t(hi) << 32) | lo);
+}
+
+template <class TS, class TP, bool kVec>
 __device__ __forceinline__ SatC<TS, TP> load_sat(const RecordView& rv, int64_t i) {
-  const TS* s = rows_of<TS>(rv);
-  const TP* p = rows_of<TP>(rv);
-  const int64_t np = rv.npad;
+  const Slot* sp = rv.slots + i;
+  if (kVec) sp = lane_ptr(sp);
+  const TS* s = rows_of<TS>(sp);
+  const TP* p = rows_of<TP>(sp);
   SatC<TS, TP> c;
-  c.M0 = s[kM0 * np + i]; c.Mdot = s[kMdot * np + i]; c.argp0 = s[kArgp0 * np + i];
-  c.argpdot = s[kArgpdot * np + i]; c.node0 = s[kNode0 * np + i]; c.nodedot = s[kNodedot * np + i];
-  c.nodecf = s[kNodecf * np + i]; c.C1 = s[kC1 * np + i]; c.bC4 = s[kBC4 * np + i]; c.t2cof = s[kT2cof * np + i];
-  c.argpcof = s[kArgpcof * np + i]; c.Mcof = s[kMcof * np + i]; c.D2 = s[kD2 * np + i]; c.D3 = s[kD3 * np + i];
-  c.D4 = s[kD4 * np + i]; c.bC5 = s[kBC5 * np + i]; c.t3cof = s[kT3cof * np + i]; c.t4cof = s[kT4cof * np + i];
-  c.t5cof = s[kT5cof * np + i]; c.n0pp = s[kN0pp * np + i]; c.a0pp = s[kA0pp * np + i]; c.e0 = s[kE0 * np + i];
-  c.epoch_min = rv.f64[kEpochMin * np + i];
-  c.eta = p[kEta * np + i]; c.dM0 = p[kDM0 * np + i]; c.sinM0 = p[kSinM0 * np + i]; c.aycof = p[kAycof * np + i];
-  c.Lcof = p[kLcof * np + i]; c.c41 = p[kC41 * np + i]; c.x1 = p[kX1 * np + i]; c.x7 = p[kX7 * np + i];
-  c.cosi = p[kCosi * np + i]; c.sini = p[kSini * np + i]; c.i0 = p[kI0 * np + i];
-  c.info = rv.info[i];
+  c.M0 = s[kM0]; c.Mdot = s[kMdot]; c.argp0 = s[kArgp0]; c.argpdot = s[kArgpdot]; c.node0 = s[kNode0];
+  c.nodedot = s[kNodedot]; c.nodecf = s[kNodecf]; c.C1 = s[kC1]; c.bC4 = s[kBC4]; c.t2cof = s[kT2cof];
+  c.argpcof = s[kArgpcof]; c.Mcof = s[kMcof]; c.D2 = s[kD2]; c.D3 = s[kD3]; c.D4 = s[kD4]; c.bC5 = s[kBC5];
+  c.t3cof = s[kT3cof]; c.t4cof = s[kT4cof]; c.t5cof = s[kT5cof]; c.n0pp = s[kN0pp]; c.a0pp = s[kA0pp];
+  c.e0 = s[kE0];
+  c.epoch_min = sp->d[kEpochMin];
+  c.eta = p[kEta]; c.dM0 = p[kDM0]; c.sinM0 = p[kSinM0]; c.aycof = p[kAycof]; c.Lcof = p[kLcof];
+  c.c41 = p[kC41]; c.x1 = p[kX1]; c.x7 = p[kX7]; c.cosi = p[kCosi]; c.sini = p[kSini]; c.i0 = p[kI0];
+  c.info = sp->info;
   return c;
 }
 
@@ -88,7 +101,7 @@ __device__ __forceinline__ float wrap(float x) {
   return fmaf(-6.28318530717958647692f, rintf(x * 0.15915494309189533577f), x);
 }
 __device__ __forceinline__ double sq_root(double x) { return sqrt(x); }
-__device__ __forceinline__ float sq_root(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float sq_root(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double vabs(double x) { return fabs(x); }
@@ -167,12 +180,17 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TS LT = L + TS(tau * c.Lcof * axn);
 
   // Kepler: psi - axn sin psi + ayn cos psi = U, Newton from psi = U with the
-  // step clamped to +-0.95; dpsi = psi - U.  The loop ends when every lane of
-  // the wavefront has taken a step below the tolerance (at most 10 steps).
+  // step clamped to +-0.95; dpsi = psi - U.  A lane is done once its step is
+  // below the tolerance or once the quadratic-convergence bound on the next
+  // step, eL / (2 (1 - eL)) * step^2 with eL <= |axn| + |ayn|, is below it (the
+  // step that would follow changes psi by less than the tolerance).  The loop
+  // ends when every lane of the wavefront is done (at most 10 steps).
   const TS U = wrap(LT - node);
   TP sp, cp;
   TR::sc(U, &sp, &cp);
   TP dpsi = TP(0);
+  const TP eb = vabs(axn) + vabs(ayn);
+  const TP quad = eb < TP(0.5) ? TP(0.5) * eb * rcp(TP(1) - eb) : TP(1.0e30);
   for (int k = 0; k < 10; ++k) {
     TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
     step = step > TP(0.95) ? TP(0.95) : step;
@@ -180,7 +198,8 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
     dpsi = dpsi + step;
     if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
     else TR::sc(U + TS(dpsi), &sp, &cp);
-    if (__all(vabs(step) < kepler_tol<TP>())) break;
+    const TP as = vabs(step);
+    if (__all(as < kepler_tol<TP>() || quad * as * as < kepler_tol<TP>())) break;
   }
 
   // Short-period preliminaries.
@@ -191,7 +210,8 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   if (!(pL >= TP(0))) return 4;
   const TP rl = a * (TP(1) - ecE);
   const TP inv_rl = rcp(rl);
-  const TP sqa = sq_root(a);
+  const TP ra = rsq(a);
+  const TP sqa = a * ra;
   const TP rdotl = sqa * esE * inv_rl;
   const TP rvdotl = sq_root(pL) * inv_rl;
   const TP betal = sq_root(TP(1) - eL2);
@@ -206,7 +226,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP inv_pl = rcp(pL);
   const TP k1 = TP(g.k2) * inv_pl;
   const TP k2 = k1 * inv_pl;
-  const TP nk = rcp(a * sqa);  // n / ke
+  const TP nk = ra * ra * ra;  // n / ke = a^-3/2
   const TP mrt = rl * (TP(1) - TP(1.5) * k2 * betal * c.c41) + TP(0.5) * k1 * c.x1 * cos2u;
   const TP du = TP(-0.25) * k2 * c.x7 * sin2u;
   const TP dnode = TP(1.5) * k2 * c.cosi * sin2u;
@@ -217,7 +237,11 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   // Orientation: sin/cos of u_k = u + du, i_k = i0 + dinc, node_k = node + dnode.
   TP ssu, csu;
   if (vabs(du) <= TP(kRotMax)) {
-    const TP h = rsq(sinu * sinu + cosu * cosu);
+    // (sinu, cosu) is a unit vector up to rounding; one Newton step from 1
+    // normalises it to O(delta^2), delta = |.|^2 - 1
+    const TP n2 = sinu * sinu + cosu * cosu;
+    TP h = TP(1.5) - TP(0.5) * n2;
+    if (vabs(n2 - TP(1)) > TP(1.0e-8)) h = rsq(n2);
     ssu = sinu * h;
     csu = cosu * h;
     rotate_small(&ssu, &csu, du);

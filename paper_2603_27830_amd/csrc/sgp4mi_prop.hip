@@ -15,48 +15,81 @@
 
 namespace sgp4mi {
 
-template <class TP>
-__device__ __forceinline__ void store_point(TP* __restrict__ r, TP* __restrict__ v, uint8_t* __restrict__ err,
-                                            int64_t P, int64_t p, uint32_t code, const PointState<TP>& s) {
-  TP x0 = s.r[0], x1 = s.r[1], x2 = s.r[2], y0 = s.v[0], y1 = s.v[1], y2 = s.v[2];
-  if (code != 0 && code != 6) {
-    const TP q = TP(__builtin_nan(""));
-    x0 = x1 = x2 = y0 = y1 = y2 = q;
+// Output writer: six component arrays and the code array.  With kOff32 the
+// per-lane offset is a 32-bit byte offset from uniform base pointers (valid
+// when each component array is below 4 GiB), so each store takes its base
+// from scalar registers and no 64-bit address arithmetic per store.
+template <class TP, bool kOff32>
+struct Out {
+  TP* r;
+  TP* v;
+  uint8_t* err;
+  int64_t P;
+  __device__ __forceinline__ void put(int64_t p, uint32_t code, const PointState<TP>& s) const {
+    TP x0 = s.r[0], x1 = s.r[1], x2 = s.r[2], y0 = s.v[0], y1 = s.v[1], y2 = s.v[2];
+    if (code != 0 && code != 6) {
+      const TP q = TP(__builtin_nan(""));
+      x0 = x1 = x2 = y0 = y1 = y2 = q;
+    }
+    if (kOff32) {
+      const uint32_t off = uint32_t(p) * uint32_t(sizeof(TP));
+      char* rb = reinterpret_cast<char*>(r);
+      char* vb = reinterpret_cast<char*>(v);
+      const size_t stride = size_t(P) * sizeof(TP);
+      st_nt(reinterpret_cast<TP*>(rb + off), x0);
+      st_nt(reinterpret_cast<TP*>(rb + stride + off), x1);
+      st_nt(reinterpret_cast<TP*>(rb + 2 * stride + off), x2);
+      st_nt(reinterpret_cast<TP*>(vb + off), y0);
+      st_nt(reinterpret_cast<TP*>(vb + stride + off), y1);
+      st_nt(reinterpret_cast<TP*>(vb + 2 * stride + off), y2);
+      st_nt(err + uint32_t(p), uint8_t(code));
+    } else {
+      st_nt(r + p, x0);
+      st_nt(r + P + p, x1);
+      st_nt(r + 2 * P + p, x2);
+      st_nt(v + p, y0);
+      st_nt(v + P + p, y1);
+      st_nt(v + 2 * P + p, y2);
+      st_nt(err + p, uint8_t(code));
+    }
   }
-  st_nt(r + p, x0);
-  st_nt(r + P + p, x1);
-  st_nt(r + 2 * P + p, x2);
-  st_nt(v + p, y0);
-  st_nt(v + P + p, y1);
-  st_nt(v + 2 * P + p, y2);
-  st_nt(err + p, uint8_t(code));
-}
+};
 
 // ------------------------------------------------------------------ dense --
-template <class TS, class TP, int kBlock>
+// Grid (n, ceil(T / kBlock)): one point per lane.  When T needs more than
+// 65535 workgroups in y, kLoop makes each lane stride over the remaining times.
+template <class TS, class TP, int kBlock, bool kVec, bool kOff32, bool kLoop>
 __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const double* __restrict__ t, int64_t T,
-                                                       TP* __restrict__ r, TP* __restrict__ v,
-                                                       uint8_t* __restrict__ err, int64_t P) {
+                                                       Out<TP, kOff32> out) {
   const int64_t i = blockIdx.x;
-  const SatC<TS, TP> c = load_sat<TS, TP>(rv, i);
-  const Grav g = load_grav(rv);
-  for (int64_t j = int64_t(blockIdx.y) * kBlock + threadIdx.x; j < T; j += int64_t(gridDim.y) * kBlock) {
+  int64_t j = int64_t(blockIdx.y) * kBlock + threadIdx.x;
+  if (!kLoop) {
+    if (j >= T) return;
+    const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
+    const Grav g = load_grav(rv);
     PointState<TP> s;
     const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
-    store_point(r, v, err, P, i * T + j, code, s);
+    out.put(i * T + j, code, s);
+    return;
+  }
+  const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
+  const Grav g = load_grav(rv);
+  for (; j < T; j += int64_t(gridDim.y) * kBlock) {
+    PointState<TP> s;
+    const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+    out.put(i * T + j, code, s);
   }
 }
 
 // ------------------------------------------------------------ ragged tiles --
 // tile_start[w]: first point of tile w; tile_sat[w]: its satellite.  A tile
 // holds min(64, end of that satellite's list - tile_start) points.
-template <class TS, class TP, int kBlock>
+template <class TS, class TP, int kBlock, bool kOff32>
 __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int64_t* __restrict__ offsets,
-                                                       const double* __restrict__ t, int64_t nnz,
+                                                       const double* __restrict__ t,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ tile_sat, int64_t ntiles,
-                                                       TP* __restrict__ r, TP* __restrict__ v,
-                                                       uint8_t* __restrict__ err) {
+                                                       Out<TP, kOff32> out) {
   constexpr int kWaves = kBlock / 64;
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = int64_t(blockIdx.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -66,12 +99,12 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int6
     const int64_t start = tile_start[w];
     const int32_t sat = __builtin_amdgcn_readfirstlane(tile_sat[w]);
     const int64_t end = offsets[sat + 1];
-    const SatC<TS, TP> c = load_sat<TS, TP>(rv, sat);
+    const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, sat);
     const int64_t p = start + lane;
-    if (p < end && p - start < 64) {
+    if (p < end) {
       PointState<TP> s;
       const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
-      store_point(r, v, err, nnz, p, code, s);
+      out.put(p, code, s);
     }
   }
 }
@@ -79,12 +112,11 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int6
 // ------------------------------------------------------------- ragged flat --
 // chunk_sat[k]: satellite whose list contains point 64*k.  When chunk_sat is
 // null the wavefront finds it by a uniform binary search of the offsets.
-template <class TS, class TP, int kBlock>
+template <class TS, class TP, int kBlock, bool kOff32>
 __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64_t* __restrict__ offsets, int64_t n,
                                                       const double* __restrict__ t, int64_t nnz,
                                                       const int32_t* __restrict__ chunk_sat, int64_t nchunks,
-                                                      TP* __restrict__ r, TP* __restrict__ v,
-                                                      uint8_t* __restrict__ err) {
+                                                      Out<TP, kOff32> out) {
   constexpr int kWaves = kBlock / 64;
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = int64_t(blockIdx.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -108,84 +140,112 @@ __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64
     if (p < nnz) {
       int64_t sat = first;
       while (sat + 1 < n && offsets[sat + 1] <= p) ++sat;
-      const SatC<TS, TP> c = load_sat<TS, TP>(rv, sat);
+      const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, sat);
       PointState<TP> s;
       const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
-      store_point(r, v, err, nnz, p, code, s);
+      out.put(p, code, s);
     }
   }
 }
 
 // ------------------------------------------------------------- launchers --
+template <class TP>
+static bool fits32(int64_t P) {
+  return P >= 0 && uint64_t(P) * sizeof(TP) < (uint64_t(1) << 32);
+}
+
+template <class TS, class TP, int kBlock, bool kVec, bool kOff32>
+static void dense_go(dim3 grid, hipStream_t s, const RecordView& rv, const double* t, int64_t T, void* r, void* v,
+                     uint8_t* err, int64_t P) {
+  Out<TP, kOff32> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+  if (int64_t(grid.y) * kBlock >= T)
+    hipLaunchKernelGGL((dense_kernel<TS, TP, kBlock, kVec, kOff32, false>), grid, dim3(kBlock), 0, s, rv, t, T, o);
+  else
+    hipLaunchKernelGGL((dense_kernel<TS, TP, kBlock, kVec, kOff32, true>), grid, dim3(kBlock), 0, s, rv, t, T, o);
+}
+
+template <class TS, class TP, int kBlock>
+static void dense_b(dim3 grid, hipStream_t s, bool vec, const RecordView& rv, const double* t, int64_t T, void* r,
+                    void* v, uint8_t* err, int64_t P) {
+  const bool o32 = fits32<TP>(P);
+  if (vec) {
+    if (o32) dense_go<TS, TP, kBlock, true, true>(grid, s, rv, t, T, r, v, err, P);
+    else dense_go<TS, TP, kBlock, true, false>(grid, s, rv, t, T, r, v, err, P);
+  } else {
+    if (o32) dense_go<TS, TP, kBlock, false, true>(grid, s, rv, t, T, r, v, err, P);
+    else dense_go<TS, TP, kBlock, false, false>(grid, s, rv, t, T, r, v, err, P);
+  }
+}
+
 template <class TS, class TP>
 static hipError_t dense_t(const RecordView& rv, int64_t n, const double* t, int64_t T, void* r, void* v,
-                          uint8_t* err, int block, hipStream_t s) {
+                          uint8_t* err, int block, bool vec, hipStream_t s) {
   const int64_t tiles = (T + block - 1) / block;
   const unsigned gy = unsigned(tiles < 65535 ? tiles : 65535);
   const dim3 grid(unsigned(n), gy);
-  TP* rr = static_cast<TP*>(r);
-  TP* vv = static_cast<TP*>(v);
   const int64_t P = n * T;
   switch (block) {
-    case 64: hipLaunchKernelGGL((dense_kernel<TS, TP, 64>), grid, dim3(64), 0, s, rv, t, T, rr, vv, err, P); break;
-    case 128: hipLaunchKernelGGL((dense_kernel<TS, TP, 128>), grid, dim3(128), 0, s, rv, t, T, rr, vv, err, P); break;
-    case 256: hipLaunchKernelGGL((dense_kernel<TS, TP, 256>), grid, dim3(256), 0, s, rv, t, T, rr, vv, err, P); break;
-    case 512: hipLaunchKernelGGL((dense_kernel<TS, TP, 512>), grid, dim3(512), 0, s, rv, t, T, rr, vv, err, P); break;
+    case 64: dense_b<TS, TP, 64>(grid, s, vec, rv, t, T, r, v, err, P); break;
+    case 128: dense_b<TS, TP, 128>(grid, s, vec, rv, t, T, r, v, err, P); break;
+    case 256: dense_b<TS, TP, 256>(grid, s, vec, rv, t, T, r, v, err, P); break;
+    case 512: dense_b<TS, TP, 512>(grid, s, vec, rv, t, T, r, v, err, P); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// block: workgroup size; vec: constants through vector loads (else scalar).
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, hipStream_t s) {
+                        uint8_t* err, int block, bool vec, hipStream_t s) {
   const RecordView rv = view_of(consts, n);
   switch (precision) {
-    case 0: return dense_t<double, double>(rv, n, t, T, r, v, err, block, s);
-    case 1: return dense_t<float, float>(rv, n, t, T, r, v, err, block, s);
-    case 2: return dense_t<double, float>(rv, n, t, T, r, v, err, block, s);
+    case 0: return dense_t<double, double>(rv, n, t, T, r, v, err, block, vec, s);
+    case 1: return dense_t<float, float>(rv, n, t, T, r, v, err, block, vec, s);
+    case 2: return dense_t<double, float>(rv, n, t, T, r, v, err, block, vec, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <class TS, class TP, int kBlock>
-static void tiles_t(const RecordView& rv, const int64_t* offsets, const double* t, int64_t nnz,
-                    const int64_t* tile_start, const int32_t* tile_sat, int64_t ntiles, void* r, void* v,
-                    uint8_t* err, unsigned grid, hipStream_t s) {
-  hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, t, nnz, tile_start,
-                     tile_sat, ntiles, static_cast<TP*>(r), static_cast<TP*>(v), err);
+template <class TS, class TP, int kBlock, bool kOff32>
+static void ragged_go(int mode, unsigned grid, hipStream_t s, const RecordView& rv, const int64_t* offsets,
+                      int64_t n, const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
+                      int64_t ntiles, void* r, void* v, uint8_t* err) {
+  Out<TP, kOff32> o{static_cast<TP*>(r), static_cast<TP*>(v), err, nnz};
+  if (mode == 0)
+    hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, t,
+                       tile_start, tile_sat, ntiles, o);
+  else
+    hipLaunchKernelGGL((flat_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, n, t, nnz,
+                       tile_sat, ntiles, o);
 }
 
 template <class TS, class TP, int kBlock>
-static void flat_t(const RecordView& rv, const int64_t* offsets, int64_t n, const double* t, int64_t nnz,
-                   const int32_t* chunk_sat, int64_t nchunks, void* r, void* v, uint8_t* err, unsigned grid,
-                   hipStream_t s) {
-  hipLaunchKernelGGL((flat_kernel<TS, TP, kBlock>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, n, t, nnz, chunk_sat,
-                     nchunks, static_cast<TP*>(r), static_cast<TP*>(v), err);
+static void ragged_b(int mode, unsigned grid, hipStream_t s, const RecordView& rv, const int64_t* offsets, int64_t n,
+                     const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat, int64_t ntiles,
+                     void* r, void* v, uint8_t* err) {
+  if (fits32<TP>(nnz))
+    ragged_go<TS, TP, kBlock, true>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err);
+  else
+    ragged_go<TS, TP, kBlock, false>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err);
 }
-
-#define SGP4MI_BLOCKS(F, ...)                               \
-  switch (block) {                                          \
-    case 64: F<TS, TP, 64>(__VA_ARGS__); break;             \
-    case 128: F<TS, TP, 128>(__VA_ARGS__); break;           \
-    case 256: F<TS, TP, 256>(__VA_ARGS__); break;           \
-    case 512: F<TS, TP, 512>(__VA_ARGS__); break;           \
-    default: return hipErrorInvalidValue;                   \
-  }
 
 template <class TS, class TP>
 static hipError_t ragged_t(int mode, const RecordView& rv, const int64_t* offsets, int64_t n, const double* t,
                            int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat, int64_t ntiles, void* r,
                            void* v, uint8_t* err, int block, unsigned grid, hipStream_t s) {
-  if (mode == 0) {
-    SGP4MI_BLOCKS(tiles_t, rv, offsets, t, nnz, tile_start, tile_sat, ntiles, r, v, err, grid, s)
-  } else {
-    SGP4MI_BLOCKS(flat_t, rv, offsets, n, t, nnz, tile_sat, ntiles, r, v, err, grid, s)
+  switch (block) {
+    case 64: ragged_b<TS, TP, 64>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 128: ragged_b<TS, TP, 128>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 256: ragged_b<TS, TP, 256>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 512: ragged_b<TS, TP, 512>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 // mode 0: tiles (tile_start/tile_sat of ntiles); mode 1: flat (tile_sat holds
-// the chunk satellites of ntiles = ceil(nnz / 64) chunks, tile_start unused).
+// the chunk satellites of ntiles = ceil(nnz / 64) chunks or is null for the
+// in-kernel search; tile_start unused).
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s) {
