@@ -32,41 +32,52 @@ struct SatC {
   uint32_t info;
 };
 
-template <class T> __device__ __forceinline__ const T* rows_of(const Slot* sp);
-template <> __device__ __forceinline__ const double* rows_of<double>(const Slot* sp) { return sp->d; }
-template <> __device__ __forceinline__ const float* rows_of<float>(const Slot* sp) { return sp->f; }
+// Global-address-space view of a slot, for loads the compiler keeps as
+// global (not flat) vector loads.
+typedef const __attribute__((address_space(1))) Slot* GSlot;
 
-// The same address seen as a per-lane value: loads through it are vector
+// The slot address seen as a per-lane value: loads through it are vector
 // loads into VGPRs (one broadcast fetch per wavefront when every lane holds the
 // same satellite) instead of scalar loads into SGPRs.  With ~34 constants per
 // satellite, SGPR residency overflows the scalar file and every VALU operation
 // reading two of them needs an extra move; VGPR residency has neither cost.
-template <class T>
-__device__ __forceinline__ const T* lane_ptr(const T* p) {
+__device__ __forceinline__ GSlot lane_slot(const Slot* p) {
   const uint64_t v = reinterpret_cast<uint64_t>(p);
   uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
   asm volatile("v_mov_b32 %0, %0" : "+v"(lo));
   asm volatile("v_mov_b32 %0, %0" : "+v"(hi));
-  return reinterpret_cast<const T*>((uint64_t(hi) << 32) | lo);
+  return (GSlot)((uint64_t(hi) << 32) | lo);
+}
+
+template <class T, class P> __device__ __forceinline__ T rec_val(P sp, int k);
+template <> __device__ __forceinline__ double rec_val<double, const Slot*>(const Slot* sp, int k) { return sp->d[k]; }
+template <> __device__ __forceinline__ float rec_val<float, const Slot*>(const Slot* sp, int k) { return sp->f[k]; }
+template <> __device__ __forceinline__ double rec_val<double, GSlot>(GSlot sp, int k) { return sp->d[k]; }
+template <> __device__ __forceinline__ float rec_val<float, GSlot>(GSlot sp, int k) { return sp->f[k]; }
+
+template <class TS, class TP, class P>
+__device__ __forceinline__ SatC<TS, TP> load_from(P sp) {
+  SatC<TS, TP> c;
+#define S_(k) rec_val<TS, P>(sp, k)
+#define P_(k) rec_val<TP, P>(sp, k)
+  c.M0 = S_(kM0); c.Mdot = S_(kMdot); c.argp0 = S_(kArgp0); c.argpdot = S_(kArgpdot); c.node0 = S_(kNode0);
+  c.nodedot = S_(kNodedot); c.nodecf = S_(kNodecf); c.C1 = S_(kC1); c.bC4 = S_(kBC4); c.t2cof = S_(kT2cof);
+  c.argpcof = S_(kArgpcof); c.Mcof = S_(kMcof); c.D2 = S_(kD2); c.D3 = S_(kD3); c.D4 = S_(kD4); c.bC5 = S_(kBC5);
+  c.t3cof = S_(kT3cof); c.t4cof = S_(kT4cof); c.t5cof = S_(kT5cof); c.n0pp = S_(kN0pp); c.a0pp = S_(kA0pp);
+  c.e0 = S_(kE0);
+  c.epoch_min = rec_val<double, P>(sp, kEpochMin);
+  c.eta = P_(kEta); c.dM0 = P_(kDM0); c.sinM0 = P_(kSinM0); c.aycof = P_(kAycof); c.Lcof = P_(kLcof);
+  c.c41 = P_(kC41); c.x1 = P_(kX1); c.x7 = P_(kX7); c.cosi = P_(kCosi); c.sini = P_(kSini); c.i0 = P_(kI0);
+#undef S_
+#undef P_
+  c.info = sp->info;
+  return c;
 }
 
 template <class TS, class TP, bool kVec>
 __device__ __forceinline__ SatC<TS, TP> load_sat(const RecordView& rv, int64_t i) {
-  const Slot* sp = rv.slots + i;
-  if (kVec) sp = lane_ptr(sp);
-  const TS* s = rows_of<TS>(sp);
-  const TP* p = rows_of<TP>(sp);
-  SatC<TS, TP> c;
-  c.M0 = s[kM0]; c.Mdot = s[kMdot]; c.argp0 = s[kArgp0]; c.argpdot = s[kArgpdot]; c.node0 = s[kNode0];
-  c.nodedot = s[kNodedot]; c.nodecf = s[kNodecf]; c.C1 = s[kC1]; c.bC4 = s[kBC4]; c.t2cof = s[kT2cof];
-  c.argpcof = s[kArgpcof]; c.Mcof = s[kMcof]; c.D2 = s[kD2]; c.D3 = s[kD3]; c.D4 = s[kD4]; c.bC5 = s[kBC5];
-  c.t3cof = s[kT3cof]; c.t4cof = s[kT4cof]; c.t5cof = s[kT5cof]; c.n0pp = s[kN0pp]; c.a0pp = s[kA0pp];
-  c.e0 = s[kE0];
-  c.epoch_min = sp->d[kEpochMin];
-  c.eta = p[kEta]; c.dM0 = p[kDM0]; c.sinM0 = p[kSinM0]; c.aycof = p[kAycof]; c.Lcof = p[kLcof];
-  c.c41 = p[kC41]; c.x1 = p[kX1]; c.x7 = p[kX7]; c.cosi = p[kCosi]; c.sini = p[kSini]; c.i0 = p[kI0];
-  c.info = sp->info;
-  return c;
+  if (kVec) return load_from<TS, TP, GSlot>(lane_slot(rv.slots + i));
+  return load_from<TS, TP, const Slot*>(rv.slots + i);
 }
 
 __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
@@ -148,7 +159,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TS M = Mdf, argp = argpdf;
   if (!(c.info & kInfoIsimp)) {
     TP sM, cM;
-    TR::sc(wrap(Mdf), &sM, &cM);
+    TR::sc(Mdf, &sM, &cM);
     const TP x = TP(1) + c.eta * cM;
     const TS dM = c.Mcof * TS(x * x * x - c.dM0);
     const TS dargp = c.argpcof * t;
@@ -158,7 +169,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
     const TS t3 = t2 * t, t4 = t3 * t;
     A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
     if (vabs(dMa) <= TS(kRotMax)) rotate_small(&sM, &cM, TP(dMa));
-    else TR::sc(wrap(M), &sM, &cM);
+    else TR::sc(M, &sM, &cM);
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
     Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
   }
@@ -166,14 +177,15 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TS e_s = c.e0 - Ed;
   if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
   if (e_s < TS(1.0e-6)) e_s = TS(1.0e-6);
+  // Angles stay unreduced: every one of them only enters through sin/cos,
+  // whose own reduction (by multiples of pi/2) handles any size met here.
   M = M + c.n0pp * Ld;
-  const TS L = wrap(M + argp + node);
-  node = wrap(node);
+  const TS L = M + argp + node;
 
   // Long-period periodics (J3).
   const TP a = TP(a_s), e = TP(e_s);
   TP sw, cw;
-  TR::sc(wrap(argp), &sw, &cw);
+  TR::sc(argp, &sw, &cw);
   const TP axn = e * cw;
   const TP tau = rcp(a * (TP(1) - e * e));
   const TP ayn = e * sw + tau * c.aycof;
@@ -185,7 +197,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   // step, eL / (2 (1 - eL)) * step^2 with eL <= |axn| + |ayn|, is below it (the
   // step that would follow changes psi by less than the tolerance).  The loop
   // ends when every lane of the wavefront is done (at most 10 steps).
-  const TS U = wrap(LT - node);
+  const TS U = LT - node;
   TP sp, cp;
   TR::sc(U, &sp, &cp);
   TP dpsi = TP(0);
