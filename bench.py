@@ -122,6 +122,29 @@ def cpu_baseline(cat, prec_name="fp64"):
             "single_core_sample": f"first {k} satellites x {cat.T} times on 1 thread"}
 
 
+def calibrate(torch):
+    """Achievable rates on this GPU: unpacked FP64 and FP32 FMA (8 independent
+    chains per lane) and a non-temporal store stream."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2603_27830_amd", "libsgp4mi_calib.so"))
+    lib.sgp4mi_calib_fma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.sgp4mi_calib_store.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+    blocks, iters = 256 * 64, 4096
+    res = {}
+    for prec, dt in ((0, torch.float64), (1, torch.float32)):
+        out = torch.empty(blocks * 256, dtype=dt, device="cuda")
+        launch = lambda: lib.sgp4mi_calib_fma(prec, ctypes.c_void_p(out.data_ptr()), blocks, iters, stream)
+        sec = kernel_time(launch, torch, reps=5)
+        res["fma_f64_tflops" if prec == 0 else "fma_f32_tflops"] = blocks * 256 * iters * 8 * 2 / sec / 1e12
+    n = 1 << 30  # 8 GiB of doubles
+    buf = torch.empty(n, dtype=torch.float64, device="cuda")
+    launch = lambda: lib.sgp4mi_calib_store(ctypes.c_void_p(buf.data_ptr()), n, 256 * 64, stream)
+    sec = kernel_time(launch, torch, reps=5)
+    res["store_nt_gbs"] = n * 8 / sec / 1e9
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +155,8 @@ def main():
     ap.add_argument("--ragged", action="store_true", help="also time the 1M-satellite ragged catalogue")
     ap.add_argument("--vjp", action="store_true", help="also time the VJP on the 9341 x 1000 grid")
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run only the calibration microbenchmarks (FMA issue rates, non-temporal store bandwidth)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (3 launches), the reference for HBM counters")
     args = ap.parse_args()
@@ -146,6 +171,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate:
+        print(json.dumps(calibrate(torch)), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
