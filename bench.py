@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--ragged", action="store_true", help="also time the 1M-satellite ragged catalogue")
     ap.add_argument("--vjp", action="store_true", help="also time the VJP on the 9341 x 1000 grid")
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every dense launch configuration (workgroup size x constant residency) per precision")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only the calibration microbenchmarks (FMA issue rates, non-temporal store bandwidth)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -186,6 +188,22 @@ def main():
     elem = torch.from_numpy(cat.elem).to(dev)
     t = torch.from_numpy(cat.t).to(dev)
     P = cat.n * cat.T
+    if args.sweep:
+        rec = sg.init(elem)
+        table = {}
+        for name in ("fp64", "fp32", "mixed"):
+            dt = torch.float64 if name == "fp64" else torch.float32
+            out = (torch.empty((3, cat.n, cat.T), dtype=dt, device=dev),
+                   torch.empty((3, cat.n, cat.T), dtype=dt, device=dev),
+                   torch.empty((cat.n, cat.T), dtype=torch.uint8, device=dev))
+            for block in (64, 128, 256, 512):
+                for scalar in (False, True):
+                    cfg = block | (0x10000 if scalar else 0)
+                    us = kernel_time(lambda: sg.propagate(rec, t, name, out=out, block=cfg), torch) * 1e6
+                    table[f"{name}/b{block}/{'scalar' if scalar else 'vector'}"] = round(us, 2)
+                    log(f"[sweep] {name} block {block} {'scalar' if scalar else 'vector'}: {us:.1f} us")
+        print(json.dumps({"dense_sweep_us": table}), flush=True)
+        return
     paths = {}
     names = [args.only] if args.only else ["fp64", "fp32", "mixed"]
     for name in names:

@@ -1,7 +1,9 @@
 // Device math for the per-point path: sine/cosine of reduced arguments,
 // rotation by small angles, and fast reciprocals.
 //
-// sincos_rr: for |x| up to ~1e4.  x = k*pi/2 + r with k = rint(2x/pi) and r by
+// sincos_rr: any |x| whose multiple k of pi/2 is below 2^53 (the error of the
+// reduction grows like k * 2e-33; for the angles of this model, below 1e5 rad
+// in practice, it is negligible).  x = k*pi/2 + r with k = rint(2x/pi) and r by
 // a two-constant Cody-Waite step (the product k*pi/2_hi is exact inside the
 // fused multiply-add), |r| <= pi/4, then the Taylor series of sin and cos
 // (1/n! coefficients): through r^15 / r^16 in double (truncation below
@@ -91,13 +93,18 @@ __device__ __forceinline__ void series(float r, float* s, float* c) {
   *c = fmaf(pc, r2, 1.0f);
 }
 
+// k mod 4 taken in floating point (exact for any integral k below 2^53, or
+// 2^24 in float), so the quadrant stays right when k exceeds the int range.
+__device__ __forceinline__ int quad_of(double k) { return int(fma(-4.0, floor(k * 0.25), k)); }
+__device__ __forceinline__ int quad_of(float k) { return int(fmaf(-4.0f, floorf(k * 0.25f), k)); }
+
 __device__ __forceinline__ void sincos_rr(double x, double* s, double* c) {
   const double k = rint(x * kSinCos64[14]);
   double r = fma(-k, kSinCos64[15], x);
   r = fma(-k, kSinCos64[16], r);
   double sr, cr;
   series(r, &sr, &cr);
-  quadrant(int(k), sr, cr, s, c);
+  quadrant(quad_of(k), sr, cr, s, c);
 }
 
 __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
@@ -106,7 +113,7 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
   r = fmaf(-k, -4.37113900018624283e-8f, r);            // pi/2 minus that
   float sr, cr;
   series(r, &sr, &cr);
-  quadrant(int(k), sr, cr, s, c);
+  quadrant(quad_of(k), sr, cr, s, c);
 }
 
 __device__ __forceinline__ void sincos_mx(double x, float* s, float* c) {
@@ -115,7 +122,7 @@ __device__ __forceinline__ void sincos_mx(double x, float* s, float* c) {
   r = fma(-k, kSinCos64[16], r);
   float sr, cr;
   series(float(r), &sr, &cr);
-  quadrant(int(k), sr, cr, s, c);
+  quadrant(quad_of(k), sr, cr, s, c);
 }
 
 __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
