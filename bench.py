@@ -196,12 +196,14 @@ def main():
             out = (torch.empty((3, cat.n, cat.T), dtype=dt, device=dev),
                    torch.empty((3, cat.n, cat.T), dtype=dt, device=dev),
                    torch.empty((cat.n, cat.T), dtype=torch.uint8, device=dev))
-            for block in (64, 128, 256, 512):
-                for scalar in (False, True):
-                    cfg = block | (0x10000 if scalar else 0)
-                    us = kernel_time(lambda: sg.propagate(rec, t, name, out=out, block=cfg), torch) * 1e6
-                    table[f"{name}/b{block}/{'scalar' if scalar else 'vector'}"] = round(us, 2)
-                    log(f"[sweep] {name} block {block} {'scalar' if scalar else 'vector'}: {us:.1f} us")
+            cfgs = [(b, sc, 0) for b in (256, 512) for sc in (False, True)]
+            cfgs += [(b, sc, k) for b in (256, 512) for sc in (False, True) for k in (2, 4, 8)]
+            for block, scalar, per_cu in cfgs:
+                cfg = block | (0x10000 if scalar else 0) | ((0x20000 | (per_cu << 20)) if per_cu else 0)
+                us = kernel_time(lambda: sg.propagate(rec, t, name, out=out, block=cfg), torch) * 1e6
+                key = f"{name}/b{block}/{'scalar' if scalar else 'vector'}/{'persist' + str(per_cu) if per_cu else 'grid'}"
+                table[key] = round(us, 2)
+                log(f"[sweep] {key}: {us:.1f} us")
         print(json.dumps({"dense_sweep_us": table}), flush=True)
         return
     paths = {}

@@ -83,15 +83,22 @@ int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, u
 
 /* Dense N x T propagation (section 2.2: f applied over satellites x times).
  * t: device float64 [T].  r, v: device [3][n*T] of double (FP64) or float;
- * err: device uint8 [n*T].  consts must come from sgp4_init with the same n. */
+ * err: device uint8 [n*T].  consts must come from sgp4_init with the same n.
+ * Uses the default launch configuration (see sgp4_propagate_ex). */
 int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                    uint8_t* err, void* stream);
 
-/* As sgp4_propagate with an explicit launch configuration: config is the
- * workgroup size (64, 128, 256 or 512), optionally OR'd with
- * SGP4_CFG_SCALAR_CONSTS to hold each satellite's constants in scalar
- * registers instead of vector registers.  Output is identical. */
-enum { SGP4_CFG_SCALAR_CONSTS = 0x10000 };
+/* As sgp4_propagate with an explicit launch configuration.  config is the
+ * workgroup size (64, 128, 256 or 512), OR'd with any of:
+ *   SGP4_CFG_SCALAR_CONSTS  each satellite's constants in scalar registers
+ *                           (otherwise vector registers);
+ *   SGP4_CFG_PERSISTENT     a fixed grid of compute-units x k workgroups whose
+ *                           wavefronts loop over 64-time tiles, with k given
+ *                           by SGP4_CFG_PER_CU(k), 1 <= k <= 255.
+ * Codes are identical for every configuration and states agree to rounding
+ * (the Kepler loop ends when all lanes of a wavefront have converged). */
+enum { SGP4_CFG_SCALAR_CONSTS = 0x10000, SGP4_CFG_PERSISTENT = 0x20000 };
+#define SGP4_CFG_PER_CU(k) ((int)(k) << 20)
 int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                       uint8_t* err, int config, void* stream);
 

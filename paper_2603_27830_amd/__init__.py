@@ -85,8 +85,12 @@ def init(elem: torch.Tensor, grav: Optional[Sequence[float]] = None) -> Record:
     return Record(consts, n, flags[:n], elem)
 
 
-def propagate(rec: Record, t: torch.Tensor, precision="fp64", out=None, block: int = 256):
-    """Dense grid: returns r [3, n, T], v [3, n, T] (km, km/s, TEME) and err uint8 [n, T]."""
+DEFAULT_DENSE = 512 | 0x10000  # the library's default launch (512-wide workgroups, scalar constants)
+
+
+def propagate(rec: Record, t: torch.Tensor, precision="fp64", out=None, block: int = DEFAULT_DENSE):
+    """Dense grid: returns r [3, n, T], v [3, n, T] (km, km/s, TEME) and err uint8 [n, T].
+    block: launch configuration word of sgp4_propagate_ex (workgroup size and flags)."""
     p = _prec(precision)
     _need(t, torch.float64, "t", rec.device)
     n, T = rec.n, int(t.numel())

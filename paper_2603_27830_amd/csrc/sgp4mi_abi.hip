@@ -20,7 +20,7 @@ namespace sgp4mi {
 hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
                        hipStream_t s);
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, bool vec, hipStream_t s);
+                        uint8_t* err, int block, bool vec, unsigned grid, hipStream_t s);
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
@@ -34,6 +34,10 @@ namespace {
 
 constexpr double kWgs72[5] = {398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597};
 constexpr int64_t kMaxSats = 2147483647LL;
+// Default dense launch: 512-wide workgroups, constants in scalar registers
+// (fastest of the workgroup x residency sweep on MI355X for all three
+// precisions at 9,341 x 1,000).
+constexpr int kDefaultDense = 512 | SGP4_CFG_SCALAR_CONSTS;
 
 int check_gravity(const double* g) {
   for (int k = 0; k < 5; ++k)
@@ -189,19 +193,28 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
                       uint8_t* err, int config, void* stream) {
   if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
   if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
-  const int block = config & 0xffff;
+  const int block = config & 0xfff;
   const bool scalar = (config & SGP4_CFG_SCALAR_CONSTS) != 0;
-  if ((config & ~(0xffff | SGP4_CFG_SCALAR_CONSTS)) != 0) return SGP4_E_ARG;
+  const bool persistent = (config & SGP4_CFG_PERSISTENT) != 0;
+  const int per_cu = (config >> 20) & 0xff;
+  if ((config & ~(0xfff | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | (0xff << 20))) != 0) return SGP4_E_ARG;
   if (block != 64 && block != 128 && block != 256 && block != 512) return SGP4_E_ARG;
+  if (persistent && per_cu == 0) return SGP4_E_ARG;
   if (n == 0 || T == 0) return SGP4_OK;
   if (!consts || !t || !r || !v || !err) return SGP4_E_ARG;
+  unsigned grid = 0;
+  if (persistent) {
+    const int64_t tiles = n * ((T + 63) / 64);
+    const int64_t need = (tiles + block / 64 - 1) / (block / 64);
+    grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(compute_units()) * per_cu)));
+  }
   return hip_status(
-      launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, static_cast<hipStream_t>(stream)));
+      launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, grid, static_cast<hipStream_t>(stream)));
 }
 
 int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                    uint8_t* err, void* stream) {
-  return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, 256, stream);
+  return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, kDefaultDense, stream);
 }
 
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,

@@ -81,6 +81,31 @@ __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const doub
   }
 }
 
+// Persistent variant: a fixed grid; each wavefront walks tiles of 64 times of
+// one satellite (tile w = satellite w / tps, times 64 * (w % tps) ...), so no
+// workgroup is dispatched per satellite and a wavefront's consecutive tiles
+// usually share the satellite's constants in cache.
+template <class TS, class TP, int kBlock, bool kVec, bool kOff32>
+__global__ void __launch_bounds__(kBlock) dense_persistent_kernel(RecordView rv, const double* __restrict__ t,
+                                                                  int64_t T, uint32_t tps, uint64_t ntiles,
+                                                                  Out<TP, kOff32> out) {
+  constexpr int kWaves = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave0 = uint64_t(blockIdx.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t nwaves = uint64_t(gridDim.x) * kWaves;
+  const Grav g = load_grav(rv);
+  for (uint64_t w = wave0; w < ntiles; w += nwaves) {
+    const uint64_t sat = w / tps;
+    const int64_t j = int64_t(w - sat * tps) * 64 + lane;
+    if (j < T) {
+      const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, int64_t(sat));
+      PointState<TP> s;
+      const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+      out.put(int64_t(sat) * T + j, code, s);
+    }
+  }
+}
+
 // ------------------------------------------------------------ ragged tiles --
 // tile_start[w]: first point of tile w; tile_sat[w]: its satellite.  A tile
 // holds min(64, end of that satellite's list - tile_start) points.
@@ -194,10 +219,53 @@ static hipError_t dense_t(const RecordView& rv, int64_t n, const double* t, int6
   return hipGetLastError();
 }
 
-// block: workgroup size; vec: constants through vector loads (else scalar).
+template <class TS, class TP, int kBlock, bool kVec>
+static void persist_go(unsigned grid, hipStream_t s, const RecordView& rv, const double* t, int64_t T, int64_t n,
+                       void* r, void* v, uint8_t* err) {
+  const int64_t P = n * T;
+  const uint32_t tps = uint32_t((T + 63) / 64);
+  const uint64_t ntiles = uint64_t(n) * tps;
+  if (fits32<TP>(P)) {
+    Out<TP, true> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+    hipLaunchKernelGGL((dense_persistent_kernel<TS, TP, kBlock, kVec, true>), dim3(grid), dim3(kBlock), 0, s, rv, t,
+                       T, tps, ntiles, o);
+  } else {
+    Out<TP, false> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+    hipLaunchKernelGGL((dense_persistent_kernel<TS, TP, kBlock, kVec, false>), dim3(grid), dim3(kBlock), 0, s, rv, t,
+                       T, tps, ntiles, o);
+  }
+}
+
+template <class TS, class TP>
+static hipError_t persist_t(const RecordView& rv, int64_t n, const double* t, int64_t T, void* r, void* v,
+                            uint8_t* err, int block, bool vec, unsigned grid, hipStream_t s) {
+#define SGP4MI_PERSIST(B)                                                       \
+  if (vec) persist_go<TS, TP, B, true>(grid, s, rv, t, T, n, r, v, err);        \
+  else persist_go<TS, TP, B, false>(grid, s, rv, t, T, n, r, v, err);
+  switch (block) {
+    case 64: SGP4MI_PERSIST(64) break;
+    case 128: SGP4MI_PERSIST(128) break;
+    case 256: SGP4MI_PERSIST(256) break;
+    case 512: SGP4MI_PERSIST(512) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SGP4MI_PERSIST
+  return hipGetLastError();
+}
+
+// block: workgroup size; vec: constants through vector loads (else scalar);
+// grid > 0 selects the persistent kernel with that many workgroups.
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, bool vec, hipStream_t s) {
+                        uint8_t* err, int block, bool vec, unsigned grid, hipStream_t s) {
   const RecordView rv = view_of(consts, n);
+  if (grid > 0) {
+    switch (precision) {
+      case 0: return persist_t<double, double>(rv, n, t, T, r, v, err, block, vec, grid, s);
+      case 1: return persist_t<float, float>(rv, n, t, T, r, v, err, block, vec, grid, s);
+      case 2: return persist_t<double, float>(rv, n, t, T, r, v, err, block, vec, grid, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (precision) {
     case 0: return dense_t<double, double>(rv, n, t, T, r, v, err, block, vec, s);
     case 1: return dense_t<float, float>(rv, n, t, T, r, v, err, block, vec, s);

@@ -37,7 +37,7 @@ def say(msg):
     print(msg, flush=True)
 
 
-def gpu_dense(elem, t, prec="fp64", block=256, grav=None):
+def gpu_dense(elem, t, prec="fp64", block=sg.DEFAULT_DENSE, grav=None):
     rec = sg.init(dev(elem), grav)
     r, v, err = sg.propagate(rec, dev(t), prec, block=block)
     return host(r, v, err)
@@ -58,13 +58,24 @@ def check_fp64(r, v, err, ro, vo, eo, tol_r=1e-6, tol_v=1e-9):
 
 
 # ------------------------------------------------------------------- FP64 --
-@pytest.mark.parametrize("block", [64, 128, 256, 512])
-def test_smoke_grid_fp64_every_block(block):
+SCALAR, PERSIST = 0x10000, 0x20000
+CONFIGS = [64, 128, 256, 512, 256 | SCALAR, 512 | SCALAR, 256 | PERSIST | (4 << 20),
+           512 | SCALAR | PERSIST | (8 << 20), 64 | SCALAR | PERSIST | (1 << 20)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_smoke_grid_every_launch_config(cfg, prec):
     cat = synth.config0()
-    say(f"[gpu] c0 64x100 fp64 block={block}")
-    r, v, err = gpu_dense(cat.elem, cat.t, "fp64", block)
+    say(f"[gpu] c0 64x100 {prec} config={cfg:#x}")
+    r, v, err = gpu_dense(cat.elem, cat.t, prec, cfg)
     ro, vo, eo = oracle.propagate(cat.elem, cat.t)
-    check_fp64(r, v, err, ro, vo, eo)
+    if prec == "fp64":
+        check_fp64(r, v, err, ro, vo, eo)
+    else:
+        assert np.array_equal(err, eo)
+        dr, dv = _errors(r.reshape(3, -1), v.reshape(3, -1), ro.reshape(3, -1), vo.reshape(3, -1))
+        assert dr.max() <= 0.010 and dv.max() <= 1e-5
 
 
 def test_starlink_grid_fp64_full_size():
@@ -82,7 +93,7 @@ def test_tail_shapes_fp64(n, T):
     elem = synth.shell_elements(n, 40 + n)
     t = np.sort(np.random.default_rng(T).uniform(-500.0, 9000.0, T))
     say(f"[gpu] tail shape n={n} T={T}")
-    for block in (64, 256):
+    for block in (64, 256, 512 | SCALAR, 256 | PERSIST | (2 << 20)):
         r, v, err = gpu_dense(elem, t, "fp64", block)
         ro, vo, eo = oracle.propagate(elem, t)
         check_fp64(r, v, err, ro, vo, eo)
@@ -318,15 +329,21 @@ def test_ragged_all_mappings_match_oracle(prec):
             ok = (eo == 0) | (eo == 6)
             dr, dv = _errors(r[:, ok], v[:, ok], ro[:, ok], vo[:, ok])
             assert dr.max() <= 0.010 and dv.max() <= 1e-5, (name, dr.max(), dv.max())
+    # Mappings agree to rounding: the Kepler loop stops when every lane of a
+    # wavefront has converged, so a lane's last (sub-tolerance) step depends
+    # on which points share its wavefront.
     base = results["search"]
+    tol_r, tol_v = (1e-8, 1e-11) if prec == "fp64" else (2e-4, 2e-7)
     for name, (r, v, err) in results.items():
         assert np.array_equal(err, base[2])
-        np.testing.assert_array_equal(np.nan_to_num(r, nan=1e300), np.nan_to_num(base[0], nan=1e300))
+        ok = (err == 0) | (err == 6)
+        assert np.max(np.abs(r[:, ok].astype(np.float64) - base[0][:, ok])) <= tol_r, name
+        assert np.max(np.abs(v[:, ok].astype(np.float64) - base[1][:, ok])) <= tol_v, name
 
 
 def test_ragged_tile_and_flat_modes_explicitly():
     """Every (mapping, workgroup, grid) configuration the autotuner may pick
-    gives the same output."""
+    gives the same codes and states equal to rounding (1e-8 km, 1e-11 km/s)."""
     el, off, t = small_ragged(300, 5)
     rec = sg.init(dev(el))
     doff, dt = dev(off), dev(t)
@@ -338,24 +355,30 @@ def test_ragged_tile_and_flat_modes_explicitly():
                 out = host(*plan.launch())
                 plan.close()
                 assert np.array_equal(out[2], ref[2]), (mode, block, per_cu)
-                np.testing.assert_array_equal(np.nan_to_num(out[0], nan=5.0), np.nan_to_num(ref[0], nan=5.0))
-                np.testing.assert_array_equal(np.nan_to_num(out[1], nan=5.0), np.nan_to_num(ref[1], nan=5.0))
+                ok = (ref[2] == 0) | (ref[2] == 6)
+                assert np.all(np.isnan(out[0][:, ~ok]))
+                assert np.max(np.abs(out[0][:, ok] - ref[0][:, ok])) <= 1e-8
+                assert np.max(np.abs(out[1][:, ok] - ref[1][:, ok])) <= 1e-11
 
 
 def test_ragged_graph_replays_match_eager():
+    """A captured plan replayed several times, with eager work between the
+    replays, reproduces the plan's direct (uncaptured) launch bit for bit."""
     el, off, t = small_ragged(400, 9)
     rec = sg.init(dev(el))
     doff, dt = dev(off), dev(t)
-    eager = host(*sg.propagate_ragged(rec, doff, dt, "fp64"))
     plan = sg.RaggedPlan(rec, doff, dt, "fp64", autotune=False, graph=True)
     assert '"graph": true' in plan.describe()
+    direct = host(*sg.propagate_ragged(rec, doff, dt, "fp64", plan=plan))
+    direct = [x.copy() for x in direct]
     for k in range(4):
         for x in plan.out:
             x.zero_()
         _ = torch.ones(1000, device=DEV).sum()  # unrelated eager work between replays
         out = host(*plan.launch())
-        assert np.array_equal(out[2], eager[2]), k
-        np.testing.assert_array_equal(np.nan_to_num(out[0], nan=7.0), np.nan_to_num(eager[0], nan=7.0))
+        assert np.array_equal(out[2], direct[2]), k
+        np.testing.assert_array_equal(np.nan_to_num(out[0], nan=7.0), np.nan_to_num(direct[0], nan=7.0))
+        np.testing.assert_array_equal(np.nan_to_num(out[1], nan=7.0), np.nan_to_num(direct[1], nan=7.0))
     plan.close()
 
 
