@@ -39,6 +39,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dense_9341x1000_hbm_traffic.md")
+KERNEL_SOURCES = ("sgp4mi_common.h", "sgp4mi_math.h", "sgp4mi_point.h", "sgp4mi_prop.hip")
+
+
+def measured_traffic(path_name):
+    """HBM bytes per launch of the dense kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the kernel
+    sources changed after the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        parts = line.strip().split(":")
+        if len(parts) == 2 and parts[0].strip().replace("_", "").isalnum():
+            vals[parts[0].strip()] = parts[1].strip()
+    blob = b"".join(open(os.path.join(ROOT, "paper_2603_27830_amd", "csrc", f), "rb").read() for f in KERNEL_SOURCES)
+    if hashlib.sha256(blob).hexdigest()[:16] != vals.get("kernel_sources_sha256_16"):
+        return None
+    try:
+        return float(vals[f"{path_name}_fetch_bytes"]) + float(vals[f"{path_name}_write_bytes"])
+    except KeyError:
+        return None
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -274,10 +301,11 @@ def main():
     k_s = head["propagate_kernel_us"] * 1e-6
     gbs = BYTES_PER_POINT[head_name] * P / k_s / 1e9
     tfl = ALG_FLOP_PER_POINT * P / k_s / 1e12
+    traffic = measured_traffic(head_name)
     hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-           "traffic": None}
+           "traffic": traffic}
     alu = {"bound": "alu", "achieved": tfl, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-           "frac": tfl / VALU_PEAK_TFLOPS, "traffic": None}
+           "frac": tfl / VALU_PEAK_TFLOPS, "traffic": traffic}
     roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
 
     line = {
