@@ -179,8 +179,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-c2", action="store_true", help="skip the 100k x 1440 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--ragged", action="store_true", help="also time the 1M-satellite ragged catalogue")
-    ap.add_argument("--vjp", action="store_true", help="also time the VJP on the 9341 x 1000 grid")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the 1M-satellite ragged catalogue")
+    ap.add_argument("--no-vjp", action="store_true", help="skip the VJP on the 9341 x 1000 grid")
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
     ap.add_argument("--sweep", action="store_true",
                     help="time every dense launch configuration (workgroup size x constant residency) per precision")
@@ -279,7 +279,26 @@ def main():
             del out2, rec2
         torch.cuda.empty_cache()
 
-    if args.ragged:
+    if not args.no_vjp and not args.only:
+        # Differentiation workload: g_r = 2 (r - r_obs), observations from the
+        # perturbed truth elements propagated by the FP64 kernel plus 10 m noise
+        # (the oracle is not used outside the CPU-baseline leg).
+        c4, truth, noise = synth.config4()
+        rec = sg.init(elem)
+        r_obs, _, _ = sg.propagate(sg.init(torch.from_numpy(truth).to(dev)), t, "fp64")
+        r_obs += torch.from_numpy(noise).to(dev)
+        paths["vjp_9341x1000"] = {}
+        for name in ("fp64", "mixed"):
+            r, _, _ = sg.propagate(rec, t, name)
+            gr = (2.0 * (r.double() - r_obs)).to(r.dtype).contiguous()
+            kv = kernel_time(lambda: sg.vjp(rec, t, gr, None, name), torch, reps=5)
+            paths["vjp_9341x1000"][name] = {"points_per_s": P / kv, "kernel_ms": kv * 1e3}
+            log(f"[bench] vjp {name}: {P / kv:.3e} pts/s, {kv * 1e3:.3f} ms")
+            del r, gr
+        del r_obs
+        torch.cuda.empty_cache()
+
+    if not args.no_ragged and not args.only:
         c3 = synth.config3()
         rec3 = sg.init(torch.from_numpy(c3.elem).to(dev))
         off3 = torch.from_numpy(c3.offsets).to(dev)

@@ -129,8 +129,9 @@ int sgp4_plan_create(sgp4_plan** out, const void* consts, int64_t n, const int64
 
 /* As sgp4_plan_create with a fixed configuration instead of autotuning:
  * mode 0 = tiles of one satellite per wavefront, 1 = flat runs of 64 points;
- * block = workgroup size (64, 128, 256, 512); waves_per_cu scales the
- * persistent grid (workgroups = min(needed, compute units * waves_per_cu)).
+ * block = workgroup size (64, 128, 256, 512); waves_per_cu > 0 scales the
+ * persistent grid (workgroups = min(needed, compute units * waves_per_cu)),
+ * 0 launches one wavefront per tile or chunk (no loop).
  * SGP4_PLAN_AUTOTUNE in flags is ignored; SGP4_PLAN_GRAPH is honoured. */
 int sgp4_plan_create_config(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
                             int64_t nnz, int precision, void* r, void* v, uint8_t* err, int mode, int block,

@@ -128,7 +128,7 @@ std::string tune_key(const sgp4_plan* p) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
   for (auto& ch : arch) if (ch == ' ' || ch == ':') ch = '_';
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s/p%d/n%d/z%d", arch.c_str(), p->precision, int(std::log2(double(p->n) + 1)),
+  std::snprintf(buf, sizeof buf, "v2/%s/p%d/n%d/z%d", arch.c_str(), p->precision, int(std::log2(double(p->n) + 1)),
                 int(std::log2(double(p->nnz) + 1)));
   return buf;
 }
@@ -246,7 +246,7 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
   if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
   if (!consts || !offsets || !t || !r || !v || !err) return SGP4_E_ARG;
   if (force_mode >= 0 && (force_mode > 1 || (force_block != 64 && force_block != 128 && force_block != 256 &&
-                                             force_block != 512) || force_per_cu <= 0))
+                                             force_block != 512) || force_per_cu < 0))
     return SGP4_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<int64_t> off(size_t(n) + 1);
@@ -309,7 +309,7 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
   if (force_mode >= 0) {
     p->mode = force_mode;
     p->block = force_block;
-    p->grid = grid_for(force_mode, force_block, force_per_cu);
+    p->grid = grid_for(force_mode, force_block, force_per_cu > 0 ? force_per_cu : (1 << 30));
     flags &= ~unsigned(SGP4_PLAN_AUTOTUNE);
   }
 
@@ -325,13 +325,14 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
       hipEvent_t e0, e1;
       if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { plan_free(p); return SGP4_E_HIP; }
       const int blocks[] = {128, 256, 512};
-      const int per_cu[] = {2, 4, 8, 16};
+      // waves per CU for the persistent grid; 0 = one wavefront per tile/chunk (no loop)
+      const int per_cu[] = {4, 8, 16, 0};
       double best = 1e300;
       for (int mode = 0; mode < 2; ++mode)
         for (int b : blocks)
           for (int pc : per_cu) {
             sgp4_plan c = *p;
-            c.mode = mode; c.block = b; c.grid = grid_for(mode, b, pc);
+            c.mode = mode; c.block = b; c.grid = grid_for(mode, b, pc > 0 ? pc : (1 << 30));
             c.graph = nullptr; c.exec = nullptr;
             if (plan_launch_direct(&c, s) != hipSuccess) continue;  // warm-up
             (void)hipEventRecord(e0, s);

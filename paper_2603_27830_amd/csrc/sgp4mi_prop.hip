@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int6
     const int64_t start = tile_start[w];
     const int32_t sat = __builtin_amdgcn_readfirstlane(tile_sat[w]);
     const int64_t end = offsets[sat + 1];
-    const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, sat);
+    const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, sat);  // satellite uniform: scalar constants
     const int64_t p = start + lane;
     if (p < end) {
       PointState<TP> s;

@@ -350,7 +350,7 @@ def test_ragged_tile_and_flat_modes_explicitly():
     ref = host(*sg.propagate_ragged(rec, doff, dt, "fp64"))
     for mode in (0, 1):
         for block in (64, 128, 256, 512):
-            for per_cu in (1, 8):
+            for per_cu in (0, 1, 8):
                 plan = sg.RaggedPlan(rec, doff, dt, "fp64", autotune=False, graph=False, config=(mode, block, per_cu))
                 out = host(*plan.launch())
                 plan.close()
