@@ -1,17 +1,14 @@
-// Device math for the per-point path: sine/cosine of reduced arguments,
-// rotation by small angles, and fast reciprocals.
+// Device math for the per-point path: sine/cosine of any angle of the
+// model, rotation by small angles, and fast reciprocals.
 //
-// sincos_rr: any |x| whose multiple k of pi/2 is below 2^53 (the error of the
-// reduction grows like k * 2e-33; for the angles of this model, below 1e5 rad
-// in practice, it is negligible).  x = k*pi/2 + r with k = rint(2x/pi) and r by
-// a two-constant Cody-Waite step (the product k*pi/2_hi is exact inside the
-// fused multiply-add), |r| <= pi/4, then the Taylor series of sin and cos
-// (1/n! coefficients): through r^15 / r^16 in double (truncation below
-// 5e-17 absolute), r^9 / r^10 in float (below 2e-9).  The quadrant k mod 4
-// permutes and signs the pair.
-//
-// sincos_mx: argument in double, reduction in double, series in float: the
-// reduced angle has no float rounding beyond its final conversion.
+// sincos_rr / sincos_mx: y = x - 2*pi*k with k = rint(x / 2*pi) (a two-part
+// 2*pi, the product exact inside the fused multiply-add), h = y / 2 in
+// [-pi/2, pi/2], the Taylor series of sin h and cos h (1/n! coefficients:
+// through h^21 / h^20 in double, truncation below 2e-17; h^13 / h^12 in
+// float, below 7e-10), then the double-angle identities sin x = 2 sin h cos h,
+// cos x = 1 - 2 sin^2 h.  No quadrant selection is needed, so nothing depends
+// on k fitting an integer.  sincos_mx reduces in double and evaluates the
+// series in float.
 //
 // rotate_small: (sin x, cos x) -> (sin(x+d), cos(x+d)) by angle addition with
 // the series of sin d and cos d; used for |d| <= kRotMax, exact to rounding
@@ -22,117 +19,86 @@
 
 namespace sgp4mi {
 
-constexpr double kTwoOverPi = 0.63661977236758134308;
-constexpr double kPio2Hi = 1.5707963267948966192;    // double nearest pi/2
-constexpr double kPio2Lo = 6.123233995736766036e-17;  // pi/2 - kPio2Hi
 constexpr double kRotMax = 0.05;
 
-template <class T>
-__device__ __forceinline__ void quadrant(int q, T sr, T cr, T* s, T* c) {
-  T ss = (q & 1) ? cr : sr;
-  T cc = (q & 1) ? sr : cr;
-  *s = (q & 2) ? -ss : ss;
-  *c = ((q + 1) & 2) ? -cc : cc;
+// Double-precision constants live in constant memory: gfx9 VALU instructions
+// take no 64-bit literals, and scalar-register operands (one per instruction)
+// avoid holding every coefficient in a vector register pair.
+__constant__ double kHalfAngle64[24] = {
+    // sin h = h + h^3 * P(h^2): -1/3!, 1/5!, ..., 1/21! (index 0 = highest order)
+    1.95729410633912612308e-20, -8.22063524662432971696e-18, 2.8114572543455207632e-15,
+    -7.6471637318198164759e-13, 1.60590438368216145994e-10, -2.50521083854417187751e-8,
+    2.75573192239858906526e-6, -1.98412698412698412698e-4, 8.33333333333333333333e-3,
+    -1.66666666666666666667e-1,
+    // cos h = 1 + h^2 * Q(h^2): -1/2!, 1/4!, ..., 1/20! (index 10 = highest order)
+    4.11031762331216485848e-19, -1.56192069685862264622e-16, 4.77947733238738529744e-14,
+    -1.14707455977297247139e-11, 2.08767569878680989792e-9, -2.75573192239858906526e-7,
+    2.48015873015873015873e-5, -1.38888888888888888889e-3, 4.16666666666666666667e-2, -0.5,
+    // 1 / (2*pi), 2*pi (double nearest), 2*pi minus that
+    0.15915494309189533577, 6.2831853071795864769, 2.4492935982947063e-16,
+    // unused
+    0.0};
+
+__device__ __forceinline__ void half_angle(double h, double* s, double* c) {
+  const double* k = kHalfAngle64;
+  const double h2 = h * h;
+  double p = fma(k[0], h2, k[1]);
+#pragma unroll
+  for (int i = 2; i < 10; ++i) p = fma(p, h2, k[i]);
+  const double sh = fma(p * h2, h, h);
+  double q = fma(k[10], h2, k[11]);
+#pragma unroll
+  for (int i = 12; i < 20; ++i) q = fma(q, h2, k[i]);
+  const double ch = fma(q, h2, 1.0);
+  *s = 2.0 * sh * ch;
+  *c = fma(-2.0 * sh, sh, 1.0);
 }
 
-// Double-precision coefficients live in constant memory: gfx9 VALU
-// instructions take no 64-bit literals, and scalar-register operands (one per
-// instruction) avoid holding every coefficient in a vector register pair.
-__constant__ double kSinCos64[17] = {
-    -7.6471637318198164759e-13,  // -1/15!
-    1.6059043836821614599e-10,   // 1/13!
-    -2.5052108385441718775e-8,   // -1/11!
-    2.7557319223985890653e-6,    // 1/9!
-    -1.9841269841269841270e-4,   // -1/7!
-    8.3333333333333333333e-3,    // 1/5!
-    -1.6666666666666666667e-1,   // -1/3!
-    4.7794773323873852974e-14,   // 1/16!
-    -1.1470745597729724714e-11,  // -1/14!
-    2.0876756987868098979e-9,    // 1/12!
-    -2.7557319223985890653e-7,   // -1/10!
-    2.4801587301587301587e-5,    // 1/8!
-    -1.3888888888888888889e-3,   // -1/6!
-    4.1666666666666666667e-2,    // 1/4!
-    0.63661977236758134308,      // 2/pi
-    1.5707963267948966192,       // pi/2 (double nearest)
-    6.123233995736766036e-17,    // pi/2 minus the above
-};
-
-__device__ __forceinline__ void series(double r, double* s, double* c) {
-  const double* k = kSinCos64;
-  const double r2 = r * r;
-  double ps = fma(k[0], r2, k[1]);
-  ps = fma(ps, r2, k[2]);
-  ps = fma(ps, r2, k[3]);
-  ps = fma(ps, r2, k[4]);
-  ps = fma(ps, r2, k[5]);
-  ps = fma(ps, r2, k[6]);
-  *s = fma(ps * r2, r, r);
-  double pc = fma(k[7], r2, k[8]);
-  pc = fma(pc, r2, k[9]);
-  pc = fma(pc, r2, k[10]);
-  pc = fma(pc, r2, k[11]);
-  pc = fma(pc, r2, k[12]);
-  pc = fma(pc, r2, k[13]);
-  pc = fma(pc, r2, -0.5);
-  *c = fma(pc, r2, 1.0);
+__device__ __forceinline__ void half_angle(float h, float* s, float* c) {
+  const float h2 = h * h;
+  float p = fmaf(h2, 1.60590438368e-10f, -2.50521083854e-8f);
+  p = fmaf(p, h2, 2.75573192240e-6f);
+  p = fmaf(p, h2, -1.98412698413e-4f);
+  p = fmaf(p, h2, 8.33333333333e-3f);
+  p = fmaf(p, h2, -1.66666666667e-1f);
+  const float sh = fmaf(p * h2, h, h);
+  float q = fmaf(h2, 2.08767569879e-9f, -2.75573192240e-7f);
+  q = fmaf(q, h2, 2.48015873016e-5f);
+  q = fmaf(q, h2, -1.38888888889e-3f);
+  q = fmaf(q, h2, 4.16666666667e-2f);
+  q = fmaf(q, h2, -0.5f);
+  const float ch = fmaf(q, h2, 1.0f);
+  *s = 2.0f * sh * ch;
+  *c = fmaf(-2.0f * sh, sh, 1.0f);
 }
 
-__device__ __forceinline__ void series(float r, float* s, float* c) {
-  const float r2 = r * r;
-  float ps = 2.7557319224e-6f;                  // 1/9!
-  ps = fmaf(ps, r2, -1.9841269841e-4f);         // -1/7!
-  ps = fmaf(ps, r2, 8.3333333333e-3f);          // 1/5!
-  ps = fmaf(ps, r2, -1.6666666667e-1f);         // -1/3!
-  *s = fmaf(ps * r2, r, r);
-  float pc = -2.7557319224e-7f;                 // -1/10!
-  pc = fmaf(pc, r2, 2.4801587302e-5f);          // 1/8!
-  pc = fmaf(pc, r2, -1.3888888889e-3f);         // -1/6!
-  pc = fmaf(pc, r2, 4.1666666667e-2f);          // 1/4!
-  pc = fmaf(pc, r2, -0.5f);
-  *c = fmaf(pc, r2, 1.0f);
+__device__ __forceinline__ double half_reduced(double x) {
+  const double* k = kHalfAngle64;
+  const double n = rint(x * k[20]);
+  double y = fma(-n, k[21], x);
+  y = fma(-n, k[22], y);
+  return 0.5 * y;
 }
 
-// k mod 4 taken in floating point (exact for any integral k below 2^53, or
-// 2^24 in float), so the quadrant stays right when k exceeds the int range.
-__device__ __forceinline__ int quad_of(double k) { return int(fma(-4.0, floor(k * 0.25), k)); }
-__device__ __forceinline__ int quad_of(float k) { return int(fmaf(-4.0f, floorf(k * 0.25f), k)); }
-
-__device__ __forceinline__ void sincos_rr(double x, double* s, double* c) {
-  const double k = rint(x * kSinCos64[14]);
-  double r = fma(-k, kSinCos64[15], x);
-  r = fma(-k, kSinCos64[16], r);
-  double sr, cr;
-  series(r, &sr, &cr);
-  quadrant(quad_of(k), sr, cr, s, c);
-}
+__device__ __forceinline__ void sincos_rr(double x, double* s, double* c) { half_angle(half_reduced(x), s, c); }
 
 __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
-  const float k = rintf(x * 0.63661977236758134308f);
-  float r = fmaf(-k, 1.57079637050628662109375f, x);   // float nearest pi/2
-  r = fmaf(-k, -4.37113900018624283e-8f, r);            // pi/2 minus that
-  float sr, cr;
-  series(r, &sr, &cr);
-  quadrant(quad_of(k), sr, cr, s, c);
+  const float n = rintf(x * 0.15915494309189533577f);
+  float y = fmaf(-n, 6.28318548202514648438f, x);   // float nearest 2*pi
+  y = fmaf(-n, -1.7484556e-7f, y);                   // 2*pi minus that
+  half_angle(0.5f * y, s, c);
 }
 
-__device__ __forceinline__ void sincos_mx(double x, float* s, float* c) {
-  const double k = rint(x * kSinCos64[14]);
-  double r = fma(-k, kSinCos64[15], x);
-  r = fma(-k, kSinCos64[16], r);
-  float sr, cr;
-  series(float(r), &sr, &cr);
-  quadrant(quad_of(k), sr, cr, s, c);
-}
+__device__ __forceinline__ void sincos_mx(double x, float* s, float* c) { half_angle(float(half_reduced(x)), s, c); }
 
 __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
-  const double* k = kSinCos64;
+  const double* k = kHalfAngle64;
   const double d2 = d * d;
-  double ps = fma(d2, k[4], k[5]);
-  ps = fma(ps, d2, k[6]);
+  double ps = fma(d2, k[7], k[8]);  // -1/7!, 1/5!
+  ps = fma(ps, d2, k[9]);            // -1/3!
   *sd = fma(ps * d2, d, d);
-  double pc = fma(d2, k[11], k[12]);
-  pc = fma(pc, d2, k[13]);
+  double pc = fma(d2, k[16], k[17]);  // 1/8!, -1/6!
+  pc = fma(pc, d2, k[18]);            // 1/4!
   pc = fma(pc, d2, -0.5);
   *cd = fma(pc, d2, 1.0);
 }
