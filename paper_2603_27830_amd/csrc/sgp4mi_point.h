@@ -225,8 +225,8 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP ra = rsq(a);
   const TP sqa = a * ra;
   const TP rdotl = sqa * esE * inv_rl;
-  const TP rvdotl = sq_root(pL) * inv_rl;
   const TP betal = sq_root(TP(1) - eL2);
+  const TP rvdotl = sqa * betal * inv_rl;  // sqrt(pL) = sqrt(a) * sqrt(1 - eL^2)
   const TP w = esE * rcp(TP(1) + betal);
   const TP ar = a * inv_rl;
   const TP sinu = ar * (sp - ayn - axn * w);

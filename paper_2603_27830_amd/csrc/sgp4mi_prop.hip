@@ -26,11 +26,16 @@ struct Out {
   uint8_t* err;
   int64_t P;
   __device__ __forceinline__ void put(int64_t p, uint32_t code, const PointState<TP>& s) const {
-    TP x0 = s.r[0], x1 = s.r[1], x2 = s.r[2], y0 = s.v[0], y1 = s.v[1], y2 = s.v[2];
+    // Codes 1, 2, 4 and 7 carry no state: such lanes (rare, and usually whole
+    // satellites) take their own store path instead of a select per component.
     if (code != 0 && code != 6) {
       const TP q = TP(__builtin_nan(""));
-      x0 = x1 = x2 = y0 = y1 = y2 = q;
+      store(p, code, q, q, q, q, q, q);
+    } else {
+      store(p, code, s.r[0], s.r[1], s.r[2], s.v[0], s.v[1], s.v[2]);
     }
+  }
+  __device__ __forceinline__ void store(int64_t p, uint32_t code, TP x0, TP x1, TP x2, TP y0, TP y1, TP y2) const {
     if (kOff32) {
       const uint32_t off = uint32_t(p) * uint32_t(sizeof(TP));
       char* rb = reinterpret_cast<char*>(r);
