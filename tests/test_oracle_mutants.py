@@ -4,8 +4,9 @@ Each mutant is the oracle source with one planted mistake (a dropped term, a
 flipped sign, a wrong coefficient or power), built on the CPU into a temporary
 library and run against the pin tests; at least one pin must fail.  Mistakes
 that no available pin can see are listed in the design notes as weakly pinned
-(J3 long-period mean-longitude term, the eccentricity-dependent drag
-coefficients, the J4 perigee rate, the low-perigee density parameter).
+(J3 long-period mean-longitude term, the J2 parts and the O(eta^2) terms of the
+drag coefficients C3, C4, C5, the J4 perigee rate, the low-perigee density
+parameter).
 """
 import concurrent.futures
 import os
@@ -34,6 +35,9 @@ MUTANTS = [
     ("un-Kozai coefficient", "0.75 * J2 * c.c41", "1.5 * J2 * c.c41"),
     ("J3 long-period eccentricity sign", "ayn = e * sin(argp) + tau * c.aycof", "ayn = e * sin(argp) - tau * c.aycof"),
     ("first-order mean-anomaly rate", "0.5 * T1 * c.beta0 * c.c41", "0.6 * T1 * c.beta0 * c.c41"),
+    ("C2 eta-squared coefficient", "(1.0 + 1.5 * eta2 + e0eta", "(1.0 + 2.5 * eta2 + e0eta"),
+    ("C4 first-order bracket", "e0 * (0.5 + 2.0 * eta2)", "e0 * (0.5 + 1.0 * eta2)"),
+    ("C5 prefactor", "c.C5 = 2.0 * coef1", "c.C5 = 2.5 * coef1"),
     ("eccentricity floor of code 1", "if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);",
      "if (!(val(e) >= -0.01 && val(e) < 1.0)) return fail(1);"),
 ]

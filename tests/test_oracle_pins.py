@@ -272,6 +272,56 @@ def test_drag_coefficients_are_the_power_law_decay_series(alt, bstar):
         assert abs(ci[key][0] - w_) <= 1e-11 * abs(w_), key
 
 
+def _orbit_average(f, n=4096):
+    """Mean over the eccentric anomaly of a smooth periodic function (trapezoid
+    rule: spectrally accurate for periodic integrands)."""
+    E = np.arange(n) * (2 * math.pi / n)
+    return float(np.mean(f(E)))
+
+
+@pytest.mark.parametrize("alt,e", [(500.0, 1e-3), (500.0, 0.01), (800.0, 0.05), (1500.0, 0.08)])
+def test_eccentric_drag_coefficients_are_orbit_averages(alt, e):
+    """J2 = 0: with density Q4 xi^4 (1 - eta cos E)^-4 (r - s = (a - s)(1 - eta cos E))
+    and drag along the velocity, Gauss's equations averaged over one orbit, with
+    the velocity factors to first order in e, give
+        da/dt = -2 a B C2,  C2 = n a Q4 xi^4 <(1 - eta c)^-4 (1 + 2 e c)>,
+        de/dt = -B C4,      C4 = 2 n a (1 - e^2) Q4 xi^4 <(1 - eta c)^-4 (c + e c^2)>,
+    c = cos E.  The model's closed forms (eta polynomials over (1 - eta^2)^(7/2))
+    must equal these averages."""
+    grav = (MU, RE, 0.0, 0.0, 0.0)
+    a0 = (RE + alt) / RE
+    el = np.array([[KE * a0 ** -1.5], [e], [0.9], [0.1], [0.2], [0.3], [1e-4], [0.0]])
+    ci = oracle.init_constants(el, grav)
+    a, n, xi, eta, q4 = ci["a0pp"][0], ci["n0pp"][0], ci["xi"][0], ci["eta"][0], ci["q4"][0]
+    assert eta < 0.7
+    dens = lambda E: (1 - eta * np.cos(E)) ** -4
+    C2 = n * a * q4 * xi ** 4 * _orbit_average(lambda E: dens(E) * (1 + 2 * e * np.cos(E)))
+    C4 = 2 * n * a * (1 - e * e) * q4 * xi ** 4 * _orbit_average(lambda E: dens(E) * (np.cos(E) + e * np.cos(E) ** 2))
+    assert abs(ci["C2"][0] / C2 - 1) < 1e-12
+    assert abs(ci["C4"][0] / C4 - 1) < 1e-12
+
+
+@pytest.mark.parametrize("e", [1e-4, 3e-4, 1e-3])
+def test_periodic_drag_coefficient_leading_order(e):
+    """C5 multiplies sin M in the drag change of e, so C5 n must be the cos M
+    Fourier coefficient of the drag de/dt (per unit B*) as a function of mean
+    anomaly; the model keeps it to low order in eta, so they agree to O(eta^2)."""
+    grav = (MU, RE, 0.0, 0.0, 0.0)
+    a0 = (RE + 500.0) / RE
+    el = np.array([[KE * a0 ** -1.5], [e], [0.9], [0.1], [0.2], [0.3], [1e-4], [0.0]])
+    ci = oracle.init_constants(el, grav)
+    a, n, xi, eta, q4 = ci["a0pp"][0], ci["n0pp"][0], ci["xi"][0], ci["eta"][0], ci["q4"][0]
+    N = 4096
+    M = np.arange(N) * (2 * math.pi / N)
+    E = M.copy()
+    for _ in range(30):
+        E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+    c = np.cos(E)
+    dedt = 2 * n * a * (1 - e * e) * q4 * xi ** 4 * (1 - eta * c) ** -4 * c * np.sqrt((1 + e * c) / (1 - e * c))
+    a1 = 2 * np.mean(dedt * np.cos(M))
+    assert abs(ci["C5"][0] * n / a1 - 1) < 2 * eta ** 2 + 1e-9
+
+
 def test_drag_decay_applied_in_propagation():
     """With e0 <= 1e-4 the drag angle terms vanish, so M(t) - M0 - Mdot t = n0'' Ld(t)."""
     el = _elements(50, 8, 1e-6, 9e-5, (15.0, 15.5), bstar=3e-4, epoch=0.0)
