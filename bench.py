@@ -211,6 +211,10 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the 1M-satellite ragged catalogue")
     ap.add_argument("--no-vjp", action="store_true", help="skip the VJP on the 9341 x 1000 grid")
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
+    ap.add_argument("--ragged-only", default=None, metavar="PREC",
+                    help="profiling mode: only the 1M-satellite ragged catalogue in one precision (fp64, mixed)")
+    ap.add_argument("--ragged-config", default=None, metavar="MODE,BLOCK,PER_CU",
+                    help="with --ragged-only: a fixed plan configuration instead of the autotuner's choice")
     ap.add_argument("--sweep", action="store_true",
                     help="time every dense launch configuration (workgroup size x constant residency) per precision")
     ap.add_argument("--calibrate", action="store_true",
@@ -261,6 +265,19 @@ def main():
                 table[key] = round(us, 2)
                 log(f"[sweep] {key}: {us:.1f} us")
         print(json.dumps({"dense_sweep_us": table}), flush=True)
+        return
+    if args.ragged_only:
+        c3 = synth.config3()
+        rec3 = sg.init(torch.from_numpy(c3.elem).to(dev))
+        off3 = torch.from_numpy(c3.offsets).to(dev)
+        t3 = torch.from_numpy(c3.t).to(dev)
+        cfg = tuple(int(x) for x in args.ragged_config.split(",")) if args.ragged_config else None
+        plan = sg.RaggedPlan(rec3, off3, t3, args.ragged_only, autotune=cfg is None, graph=False, config=cfg)
+        k3 = kernel_time(plan.launch, torch, reps=3)
+        log(f"[ragged] {args.ragged_only}: {c3.nnz / k3:.3e} pts/s, {k3 * 1e3:.3f} ms ({plan.describe()})")
+        print(json.dumps({"ragged": args.ragged_only, "nnz": c3.nnz, "launch_ms": k3 * 1e3,
+                          "plan": json.loads(plan.describe())}), flush=True)
+        plan.close()
         return
     paths = {}
     names = [args.only] if args.only else ["fp64", "fp32", "mixed"]

@@ -13,6 +13,7 @@
 #pragma once
 
 #include "sgp4mi_common.h"
+#include "sgp4mi_math.h"
 
 namespace sgp4mi {
 
@@ -55,14 +56,9 @@ __device__ __forceinline__ Dual1 cbrt(Dual1 x) {
   return Dual1(c, x.d / (3.0 * c * c));
 }
 __device__ __forceinline__ Dual1 fabs(Dual1 x) { return x.v < 0 ? -x : x; }
-__device__ __forceinline__ Dual1 cos(Dual1 x) {
-  double s, c;
-  ::sincos(x.v, &s, &c);
-  return Dual1(c, -s * x.d);
-}
-__device__ __forceinline__ void sincos(Dual1 x, Dual1* s, Dual1* c) {
+__device__ __forceinline__ void sin_cos(Dual1 x, Dual1* s, Dual1* c) {
   double sv, cv;
-  ::sincos(x.v, &sv, &cv);
+  sincos_rr(x.v, &sv, &cv);
   *s = Dual1(sv, cv * x.d);
   *c = Dual1(cv, -sv * x.d);
 }
@@ -71,6 +67,17 @@ __device__ __forceinline__ void sincos(Dual1 x, Dual1* s, Dual1* c) {
 using dual::Dual1;
 __device__ __forceinline__ double value(double x) { return x; }
 using dual::value;
+// Sine and cosine of an element angle: the reduced-range series of the
+// propagation kernels (any argument, no quadrant logic, no library branches).
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos_rr(x, s, c); }
+using dual::sin_cos;
+// Quotient: for double, the reciprocal estimate refined by Newton steps times
+// the numerator (within about an ulp of the rounded quotient, and a shorter
+// dependency chain than the correctly rounded division); for dual numbers, their
+// own division.
+__device__ __forceinline__ double quot(double a, double b) { return a * rcp(b); }
+template <class A, class B>
+__device__ __forceinline__ Dual1 quot(A a, B b) { return Dual1(a) / Dual1(b); }
 
 struct GravIn {
   double radius, j2, j4, ke, j3oj2;
@@ -82,9 +89,7 @@ template <class S>
 __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S rec[kNRec], uint32_t* code_out,
                                             bool* isimp_out) {
   using ::cbrt;
-  using ::cos;
   using ::fabs;
-  using ::sincos;
   using ::sqrt;
   const S& no_kozai = el[0];
   const S& ecco = el[1];
@@ -96,7 +101,7 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   const double R = g.radius, J2 = g.j2, J4 = g.j4, ke = g.ke, j3oj2 = g.j3oj2;
 
   S sin_i, cos_i;
-  sincos(inclo, &sin_i, &cos_i);
+  sin_cos(inclo, &sin_i, &cos_i);
   const S c2 = cos_i * cos_i;
   const S omeosq = 1.0 - ecco * ecco;  // beta0^2
   const S rteosq = sqrt(omeosq);       // beta0
@@ -106,14 +111,14 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
 
   // Original mean motion: invert the Kozai definition with the second-order
   // correction of the published model.
-  const S ak = cbrt(ke / no_kozai);
+  const S ak = cbrt(quot(ke, no_kozai));
   const S a1 = ak * ak;
-  const S d1 = 0.75 * J2 * con41 / (rteosq * omeosq);
-  const S del1 = d1 / (a1 * a1);
+  const S d1 = quot(0.75 * J2 * con41, rteosq * omeosq);
+  const S del1 = quot(d1, a1 * a1);
   const S adel = a1 * (1.0 - del1 * (1.0 / 3.0 + del1 * (1.0 + (134.0 / 81.0) * del1)));
-  const S del0 = d1 / (adel * adel);
-  const S nbar = no_kozai / (1.0 + del0);
-  const S ab = cbrt(ke / nbar);
+  const S del0 = quot(d1, adel * adel);
+  const S nbar = quot(no_kozai, 1.0 + del0);
+  const S ab = cbrt(quot(ke, nbar));
   const S abar = ab * ab;
 
   // Perigee height -> density parameter s and (q0 - s)^4.
@@ -136,29 +141,31 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   else if (kTwoPi / value(nbar) >= 225.0) code = 7;
 
   // Power-law drag coefficients.
-  const S tsi = 1.0 / (abar - sfour);
+  const S tsi = quot(1.0, abar - sfour);
   const S eta = abar * ecco * tsi;
   const S etasq = eta * eta;
   const S eeta = ecco * eta;
   const S psisq = fabs(1.0 - etasq);
   const S tsi2 = tsi * tsi;
   const S coef = qoms24 * tsi2 * tsi2;
-  const S coef1 = coef / (psisq * psisq * psisq * sqrt(psisq));
+  const S coef1 = quot(coef, psisq * psisq * psisq * sqrt(psisq));
   const S cc2 = coef1 * nbar *
                 (abar * (1.0 + 1.5 * etasq + eeta * (4.0 + etasq)) +
-                 0.375 * J2 * tsi / psisq * con41 * (8.0 + 3.0 * etasq * (8.0 + etasq)));
+                 0.375 * J2 * quot(tsi, psisq) * con41 * (8.0 + 3.0 * etasq * (8.0 + etasq)));
   const S cc1 = bstar * cc2;
-  const S cc3 = (value(ecco) > 1.0e-4) ? -2.0 * coef * tsi * j3oj2 * nbar * sin_i / ecco : S(0.0);
-  const S cos_2w = cos(2.0 * argpo);
+  const S cc3 = (value(ecco) > 1.0e-4) ? quot(-2.0 * coef * tsi * j3oj2 * nbar * sin_i, ecco) : S(0.0);
+  S sin_w, cos_w;
+  sin_cos(argpo, &sin_w, &cos_w);
+  const S cos_2w = 2.0 * cos_w * cos_w - 1.0;
   const S cc4 = 2.0 * nbar * coef1 * abar * omeosq *
                 (eta * (2.0 + 0.5 * etasq) + ecco * (0.5 + 2.0 * etasq) -
-                 J2 * tsi / (abar * psisq) *
+                 quot(J2 * tsi, abar * psisq) *
                      (-3.0 * con41 * (1.0 - 2.0 * eeta + etasq * (1.5 - 0.5 * eeta)) +
                       0.75 * x1mth2 * (2.0 * etasq - eeta * (1.0 + etasq)) * cos_2w));
   const S cc5 = 2.0 * coef1 * abar * omeosq * (1.0 + 2.75 * (etasq + eeta) + eeta * etasq);
 
   // Secular rates.
-  const S pinv = 1.0 / (abar * omeosq);
+  const S pinv = quot(1.0, abar * omeosq);
   const S pinvsq = pinv * pinv;
   const S c4 = c2 * c2;
   const S temp1 = 1.5 * J2 * pinvsq * nbar;
@@ -171,14 +178,14 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   const S nodedot = xhdot1 + (0.5 * temp2 * (4.0 - 19.0 * c2) + 2.0 * temp3 * (3.0 - 7.0 * c2)) * cos_i;
 
   S sin_m0, cos_m0;
-  sincos(mo, &sin_m0, &cos_m0);
-  S argpcof = bstar * cc3 * cos(argpo);
-  S xmcof = (value(ecco) > 1.0e-4) ? -(2.0 / 3.0) * coef * bstar / eeta : S(0.0);
+  sin_cos(mo, &sin_m0, &cos_m0);
+  S argpcof = bstar * cc3 * cos_w;
+  S xmcof = (value(ecco) > 1.0e-4) ? quot(-(2.0 / 3.0) * coef * bstar, eeta) : S(0.0);
   const S nodecf = 3.5 * omeosq * xhdot1 * cc1;
   const S t2cof = 1.5 * cc1;
   S den = 1.0 + cos_i;
   if (::fabs(value(den)) <= 1.5e-12) den = S(1.5e-12);
-  const S xlcof = -0.25 * j3oj2 * sin_i * (3.0 + 5.0 * cos_i) / den;
+  const S xlcof = quot(-0.25 * j3oj2 * sin_i * (3.0 + 5.0 * cos_i), den);
   const S aycof = -0.5 * j3oj2 * sin_i;
   const S dm = 1.0 + eta * cos_m0;
   const S delmo = dm * dm * dm;
@@ -188,7 +195,7 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   if (!isimp) {
     const S cc1sq = cc1 * cc1;
     d2 = 4.0 * abar * tsi * cc1sq;
-    const S tmp = d2 * tsi * cc1 / 3.0;
+    const S tmp = d2 * tsi * cc1 * (1.0 / 3.0);
     d3 = (17.0 * abar + sfour) * tmp;
     d4 = 0.5 * tmp * abar * tsi * (221.0 * abar + 31.0 * sfour) * cc1;
     t3cof = d2 + 2.0 * cc1sq;

@@ -91,6 +91,20 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
 
 __device__ __forceinline__ void sincos_mx(double x, float* s, float* c) { half_angle(float(half_reduced(x)), s, c); }
 
+// Hardware sine and cosine (v_sin_f32 / v_cos_f32 take the argument in
+// revolutions): the angle is reduced to a fraction of a turn in its own type,
+// then rounded to float.
+__device__ __forceinline__ void sincos_hw(double x, float* s, float* c) {
+  const float r = float(__builtin_amdgcn_fract(x * kHalfAngle64[20]));
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void sincos_hw(float x, float* s, float* c) {
+  const float r = __builtin_amdgcn_fractf(x * 0.15915494309189533577f);
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
+
 __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
   const double* k = kHalfAngle64;
   const double d2 = d * d;

@@ -91,20 +91,27 @@ __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
 
 // ------------------------------------------------------- typed primitives --
 // Sine and cosine of an angle held in the secular type, evaluated in the
-// periodic type (reduction in the secular type).
+// periodic type (reduction in the secular type).  sc is the full-accuracy
+// evaluation; sc_damped serves angles whose sine and cosine enter the state
+// only through a small factor (the eccentricity in e cos w, e sin w; the drag
+// coefficients multiplying functions of M), where the 32-bit hardware sine
+// and cosine (argument in revolutions) suffice.
 template <class TS, class TP>
 struct Trig;
 template <>
 struct Trig<double, double> {
   static __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos_rr(x, s, c); }
+  static __device__ __forceinline__ void sc_damped(double x, double* s, double* c) { sincos_rr(x, s, c); }
 };
 template <>
 struct Trig<float, float> {
   static __device__ __forceinline__ void sc(float x, float* s, float* c) { sincos_rr(x, s, c); }
+  static __device__ __forceinline__ void sc_damped(float x, float* s, float* c) { sincos_hw(x, s, c); }
 };
 template <>
 struct Trig<double, float> {
   static __device__ __forceinline__ void sc(double x, float* s, float* c) { sincos_mx(x, s, c); }
+  static __device__ __forceinline__ void sc_damped(double x, float* s, float* c) { sincos_hw(x, s, c); }
 };
 
 __device__ __forceinline__ double wrap(double x) { return wrap_pi(x); }
@@ -124,6 +131,12 @@ __device__ __forceinline__ float arctan2(float y, float x) { return atan2f(y, x)
 template <class T> __device__ __forceinline__ T kepler_tol();
 template <> __device__ __forceinline__ double kepler_tol<double>() { return 1.0e-12; }
 template <> __device__ __forceinline__ float kepler_tol<float>() { return 1.0e-7f; }
+
+// Newton step clamped to [-0.95, 0.95] (one median-of-three in float).  A NaN
+// step (possible only when e_L >= 1, where the point's code is 4 and its state
+// is not used) comes out finite here.
+__device__ __forceinline__ double clamp_step(double x) { return fmax(fmin(x, 0.95), -0.95); }
+__device__ __forceinline__ float clamp_step(float x) { return __builtin_amdgcn_fmed3f(x, -0.95f, 0.95f); }
 
 template <class TP>
 struct PointState {
@@ -159,7 +172,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TS M = Mdf, argp = argpdf;
   if (!(c.info & kInfoIsimp)) {
     TP sM, cM;
-    TR::sc(Mdf, &sM, &cM);
+    TR::sc_damped(Mdf, &sM, &cM);
     const TP x = TP(1) + c.eta * cM;
     const TS dM = c.Mcof * TS(x * x * x - c.dM0);
     const TS dargp = c.argpcof * t;
@@ -169,7 +182,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
     const TS t3 = t2 * t, t4 = t3 * t;
     A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
     if (vabs(dMa) <= TS(kRotMax)) rotate_small(&sM, &cM, TP(dMa));
-    else TR::sc(M, &sM, &cM);
+    else TR::sc_damped(M, &sM, &cM);
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
     Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
   }
@@ -185,7 +198,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   // Long-period periodics (J3).
   const TP a = TP(a_s), e = TP(e_s);
   TP sw, cw;
-  TR::sc(argp, &sw, &cw);
+  TR::sc_damped(argp, &sw, &cw);
   const TP axn = e * cw;
   const TP tau = rcp(a * (TP(1) - e * e));
   const TP ayn = e * sw + tau * c.aycof;
@@ -205,8 +218,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP quad = eb < TP(0.5) ? TP(0.5) * eb * rcp(TP(1) - eb) : TP(1.0e30);
   for (int k = 0; k < 10; ++k) {
     TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
-    step = step > TP(0.95) ? TP(0.95) : step;
-    step = step < TP(-0.95) ? TP(-0.95) : step;
+    step = clamp_step(step);
     dpsi = dpsi + step;
     if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
     else TR::sc(U + TS(dpsi), &sp, &cp);
