@@ -213,8 +213,8 @@ def main():
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
     ap.add_argument("--ragged-only", default=None, metavar="PREC",
                     help="profiling mode: only the 1M-satellite ragged catalogue in one precision (fp64, mixed)")
-    ap.add_argument("--ragged-config", default=None, metavar="MODE,BLOCK,PER_CU",
-                    help="with --ragged-only: a fixed plan configuration instead of the autotuner's choice")
+    ap.add_argument("--ragged-config", default=None, metavar="MODE,BLOCK,PER_CU[;...]",
+                    help="with --ragged-only: fixed plan configurations (';'-separated) instead of the autotuner's")
     ap.add_argument("--sweep", action="store_true",
                     help="time every dense launch configuration (workgroup size x constant residency) per precision")
     ap.add_argument("--calibrate", action="store_true",
@@ -257,11 +257,14 @@ def main():
                    torch.empty((3, cat.n, cat.T), dtype=dt, device=dev),
                    torch.empty((cat.n, cat.T), dtype=torch.uint8, device=dev))
             cfgs = [(b, sc, 0) for b in (256, 512) for sc in (False, True)]
-            cfgs += [(b, sc, k) for b in (256, 512) for sc in (False, True) for k in (2, 4, 8)]
+            cfgs += [(b, True, -1) for b in (64, 128, 256, 512)]
+            cfgs += [(b, True, k) for b in (256, 512) for k in (4, 8)]
             for block, scalar, per_cu in cfgs:
-                cfg = block | (0x10000 if scalar else 0) | ((0x20000 | (per_cu << 20)) if per_cu else 0)
+                cfg = block | (0x10000 if scalar else 0)
+                cfg |= 0x40000 if per_cu < 0 else ((0x20000 | (per_cu << 20)) if per_cu else 0)
                 us = kernel_time(lambda: sg.propagate(rec, t, name, out=out, block=cfg), torch) * 1e6
-                key = f"{name}/b{block}/{'scalar' if scalar else 'vector'}/{'persist' + str(per_cu) if per_cu else 'grid'}"
+                mapping = "tiles" if per_cu < 0 else ("persist" + str(per_cu) if per_cu else "grid")
+                key = f"{name}/b{block}/{'scalar' if scalar else 'vector'}/{mapping}"
                 table[key] = round(us, 2)
                 log(f"[sweep] {key}: {us:.1f} us")
         print(json.dumps({"dense_sweep_us": table}), flush=True)
@@ -271,13 +274,15 @@ def main():
         rec3 = sg.init(torch.from_numpy(c3.elem).to(dev))
         off3 = torch.from_numpy(c3.offsets).to(dev)
         t3 = torch.from_numpy(c3.t).to(dev)
-        cfg = tuple(int(x) for x in args.ragged_config.split(",")) if args.ragged_config else None
-        plan = sg.RaggedPlan(rec3, off3, t3, args.ragged_only, autotune=cfg is None, graph=False, config=cfg)
-        k3 = kernel_time(plan.launch, torch, reps=3)
-        log(f"[ragged] {args.ragged_only}: {c3.nnz / k3:.3e} pts/s, {k3 * 1e3:.3f} ms ({plan.describe()})")
-        print(json.dumps({"ragged": args.ragged_only, "nnz": c3.nnz, "launch_ms": k3 * 1e3,
-                          "plan": json.loads(plan.describe())}), flush=True)
-        plan.close()
+        cfgs = ([tuple(int(x) for x in c.split(",")) for c in args.ragged_config.split(";")]
+                if args.ragged_config else [None])
+        for cfg in cfgs:
+            plan = sg.RaggedPlan(rec3, off3, t3, args.ragged_only, autotune=cfg is None, graph=False, config=cfg)
+            k3 = kernel_time(plan.launch, torch, reps=3)
+            log(f"[ragged] {args.ragged_only}: {c3.nnz / k3:.3e} pts/s, {k3 * 1e3:.3f} ms ({plan.describe()})")
+            print(json.dumps({"ragged": args.ragged_only, "nnz": c3.nnz, "launch_ms": k3 * 1e3,
+                              "plan": json.loads(plan.describe())}), flush=True)
+            plan.close()
         return
     paths = {}
     names = [args.only] if args.only else ["fp64", "fp32", "mixed"]

@@ -94,10 +94,15 @@ int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, in
  *                           (otherwise vector registers);
  *   SGP4_CFG_PERSISTENT     a fixed grid of compute-units x k workgroups whose
  *                           wavefronts loop over 64-time tiles, with k given
- *                           by SGP4_CFG_PER_CU(k), 1 <= k <= 255.
+ *                           by SGP4_CFG_PER_CU(k), 1 <= k <= 255;
+ *   SGP4_CFG_TILES          one wavefront per 64-time tile of one satellite
+ *                           (workgroups of independent wavefronts); needs
+ *                           SGP4_CFG_SCALAR_CONSTS and no SGP4_CFG_PERSISTENT
+ *                           (else SGP4_E_ARG), and n * ceil(T / 64) < 2^32
+ *                           (else SGP4_E_SIZE).
  * Codes are identical for every configuration and states agree to rounding
  * (the Kepler loop ends when all lanes of a wavefront have converged). */
-enum { SGP4_CFG_SCALAR_CONSTS = 0x10000, SGP4_CFG_PERSISTENT = 0x20000 };
+enum { SGP4_CFG_SCALAR_CONSTS = 0x10000, SGP4_CFG_PERSISTENT = 0x20000, SGP4_CFG_TILES = 0x40000 };
 #define SGP4_CFG_PER_CU(k) ((int)(k) << 20)
 int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                       uint8_t* err, int config, void* stream);
@@ -120,18 +125,22 @@ int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets,
 
 /* Build a plan for one ragged batch: copies and checks the offsets (returns
  * SGP4_E_OFFSETS when malformed), builds the tile tables, optionally times
- * the candidate mappings (tiles of one satellite per wavefront or flat runs,
- * workgroup size, persistent grid size) and keeps the fastest
- * (SGP4_PLAN_AUTOTUNE), and optionally captures the launch in a HIP graph
- * (SGP4_PLAN_GRAPH).  Synchronises `stream`.  Autotuning writes r, v, err. */
+ * the candidate mappings (tiles of <= 64 points of one satellite or flat runs
+ * of 64 points; workgroup size; one wavefront per tile or a persistent grid
+ * of a given size) and keeps the fastest (SGP4_PLAN_AUTOTUNE), and optionally
+ * captures the launch in a HIP graph (SGP4_PLAN_GRAPH).  Without autotuning
+ * the plan launches one wavefront per tile in 256-wide workgroups.
+ * Synchronises `stream`.  Autotuning writes r, v, err. */
 int sgp4_plan_create(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
                      int64_t nnz, int precision, void* r, void* v, uint8_t* err, unsigned flags, void* stream);
 
 /* As sgp4_plan_create with a fixed configuration instead of autotuning:
- * mode 0 = tiles of one satellite per wavefront, 1 = flat runs of 64 points;
- * block = workgroup size (64, 128, 256, 512); waves_per_cu > 0 scales the
- * persistent grid (workgroups = min(needed, compute units * waves_per_cu)),
- * 0 launches one wavefront per tile or chunk (no loop).
+ * mode 0 = tiles of <= 64 points of one satellite per wavefront, 1 = flat
+ * runs of 64 points; block = workgroup size (64, 128, 256, 512);
+ * waves_per_cu > 0 scales the persistent grid (workgroups = min(needed,
+ * compute units * waves_per_cu)), 0 launches one wavefront per tile or chunk
+ * (no loop; grids are capped at 2^31 - 1 workgroups, beyond which the
+ * wavefronts loop).
  * SGP4_PLAN_AUTOTUNE in flags is ignored; SGP4_PLAN_GRAPH is honoured. */
 int sgp4_plan_create_config(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
                             int64_t nnz, int precision, void* r, void* v, uint8_t* err, int mode, int block,

@@ -85,12 +85,10 @@ def init(elem: torch.Tensor, grav: Optional[Sequence[float]] = None) -> Record:
     return Record(consts, n, flags[:n], elem)
 
 
-DEFAULT_DENSE = 512 | 0x10000  # the library's default launch (512-wide workgroups, scalar constants)
-
-
-def propagate(rec: Record, t: torch.Tensor, precision="fp64", out=None, block: int = DEFAULT_DENSE):
+def propagate(rec: Record, t: torch.Tensor, precision="fp64", out=None, block: Optional[int] = None):
     """Dense grid: returns r [3, n, T], v [3, n, T] (km, km/s, TEME) and err uint8 [n, T].
-    block: launch configuration word of sgp4_propagate_ex (workgroup size and flags)."""
+    block: None for the library's default launch (sgp4_propagate), else the launch
+    configuration word of sgp4_propagate_ex (workgroup size and flags)."""
     p = _prec(precision)
     _need(t, torch.float64, "t", rec.device)
     n, T = rec.n, int(t.numel())
@@ -102,8 +100,13 @@ def propagate(rec: Record, t: torch.Tensor, precision="fp64", out=None, block: i
     else:
         r, v, err = out
     with torch.cuda.device(rec.device):
-        _native.check(_native.lib().sgp4_propagate_ex(_ptr(rec.consts), n, _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err),
-                                                      int(block), _stream(rec.device)), "sgp4_propagate")
+        if block is None:
+            rc = _native.lib().sgp4_propagate(_ptr(rec.consts), n, _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err),
+                                              _stream(rec.device))
+        else:
+            rc = _native.lib().sgp4_propagate_ex(_ptr(rec.consts), n, _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err),
+                                                 int(block), _stream(rec.device))
+        _native.check(rc, "sgp4_propagate")
     return r, v, err
 
 

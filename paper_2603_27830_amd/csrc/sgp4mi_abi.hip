@@ -20,7 +20,8 @@ namespace sgp4mi {
 hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
                        hipStream_t s);
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, bool vec, unsigned grid, hipStream_t s);
+                        uint8_t* err, int block, bool vec, unsigned grid, bool tiles, hipStream_t s);
+bool dense_tiles_fit(int64_t n, int64_t T);
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
@@ -34,10 +35,15 @@ namespace {
 
 constexpr double kWgs72[5] = {398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597};
 constexpr int64_t kMaxSats = 2147483647LL;
-// Default dense launch: 512-wide workgroups, constants in scalar registers
-// (fastest of the workgroup x residency sweep on MI355X for all three
-// precisions at 9,341 x 1,000).
-constexpr int kDefaultDense = 512 | SGP4_CFG_SCALAR_CONSTS;
+// Default dense launch: one wavefront per 64-time tile with the satellite's
+// constants in scalar registers, in 256-wide workgroups for FP64 and 512-wide
+// for the float paths (fastest of the mapping x workgroup x residency sweep on
+// MI355X at 9,341 x 1,000); the satellite-by-time grid where the tiles do not
+// fit 32-bit indices.
+int default_dense(int precision, int64_t n, int64_t T) {
+  if (!dense_tiles_fit(n, T)) return 512 | SGP4_CFG_SCALAR_CONSTS;
+  return (precision == SGP4_FP64 ? 256 : 512) | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_TILES;
+}
 
 int check_gravity(const double* g) {
   for (int k = 0; k < 5; ++k)
@@ -80,7 +86,7 @@ struct sgp4_plan {
   void* v = nullptr;
   uint8_t* err = nullptr;
   int64_t* tile_start = nullptr;  // device, tiles mode
-  int32_t* tile_sat = nullptr;    // device, tiles mode
+  int32_t* tile_sat = nullptr;    // device, tiles mode: (satellite, length) pairs
   int64_t ntiles = 0;
   int32_t* chunk_sat = nullptr;   // device, flat mode
   int64_t nchunks = 0;
@@ -128,7 +134,7 @@ std::string tune_key(const sgp4_plan* p) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
   for (auto& ch : arch) if (ch == ' ' || ch == ':') ch = '_';
   char buf[256];
-  std::snprintf(buf, sizeof buf, "v2/%s/p%d/n%d/z%d", arch.c_str(), p->precision, int(std::log2(double(p->n) + 1)),
+  std::snprintf(buf, sizeof buf, "v3/%s/p%d/n%d/z%d", arch.c_str(), p->precision, int(std::log2(double(p->n) + 1)),
                 int(std::log2(double(p->nnz) + 1)));
   return buf;
 }
@@ -196,25 +202,29 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
   const int block = config & 0xfff;
   const bool scalar = (config & SGP4_CFG_SCALAR_CONSTS) != 0;
   const bool persistent = (config & SGP4_CFG_PERSISTENT) != 0;
+  const bool tiles = (config & SGP4_CFG_TILES) != 0;
   const int per_cu = (config >> 20) & 0xff;
-  if ((config & ~(0xfff | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | (0xff << 20))) != 0) return SGP4_E_ARG;
+  if ((config & ~(0xfff | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | SGP4_CFG_TILES | (0xff << 20))) != 0)
+    return SGP4_E_ARG;
   if (block != 64 && block != 128 && block != 256 && block != 512) return SGP4_E_ARG;
   if (persistent && per_cu == 0) return SGP4_E_ARG;
+  if (tiles && (persistent || !scalar || per_cu != 0)) return SGP4_E_ARG;
   if (n == 0 || T == 0) return SGP4_OK;
   if (!consts || !t || !r || !v || !err) return SGP4_E_ARG;
+  if (tiles && !dense_tiles_fit(n, T)) return SGP4_E_SIZE;
   unsigned grid = 0;
   if (persistent) {
     const int64_t tiles = n * ((T + 63) / 64);
     const int64_t need = (tiles + block / 64 - 1) / (block / 64);
     grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(compute_units()) * per_cu)));
   }
-  return hip_status(
-      launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, grid, static_cast<hipStream_t>(stream)));
+  return hip_status(launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, grid, tiles,
+                                static_cast<hipStream_t>(stream)));
 }
 
 int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                    uint8_t* err, void* stream) {
-  return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, kDefaultDense, stream);
+  return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, default_dense(precision, n, T), stream);
 }
 
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,
@@ -266,11 +276,12 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
   std::vector<int64_t> ts;
   std::vector<int32_t> tsat;
   ts.reserve(size_t(nnz / 64 + n));
-  tsat.reserve(size_t(nnz / 64 + n));
+  tsat.reserve(2 * size_t(nnz / 64 + n));
   for (int64_t i = 0; i < n; ++i)
     for (int64_t q = off[size_t(i)]; q < off[size_t(i) + 1]; q += 64) {
       ts.push_back(q);
       tsat.push_back(int32_t(i));
+      tsat.push_back(int32_t(std::min<int64_t>(64, off[size_t(i) + 1] - q)));
     }
   p->ntiles = int64_t(ts.size());
   p->nchunks = (nnz + 63) / 64;
@@ -300,12 +311,15 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
     const int64_t work = mode == 0 ? p->ntiles : p->nchunks;
     const int64_t waves_needed = work;
     const int64_t blocks_needed = (waves_needed + block / 64 - 1) / (block / 64);
-    return unsigned(std::max<int64_t>(1, std::min<int64_t>(blocks_needed, int64_t(cus) * per_cu)));
+    constexpr int64_t kMaxGrid = 0x7fffffff;  // a smaller grid makes the kernels loop
+    return unsigned(std::max<int64_t>(1, std::min({blocks_needed, int64_t(cus) * per_cu, kMaxGrid})));
   };
-  // default choice (or the caller's fixed configuration)
+  // default choice: one wavefront per tile, 256-wide workgroups (fastest on
+  // MI355X for the 1M-satellite catalogue in every precision); or the caller's
+  // fixed configuration
   p->mode = 0;
   p->block = 256;
-  p->grid = grid_for(0, 256, 8);
+  p->grid = grid_for(0, 256, 1 << 30);
   if (force_mode >= 0) {
     p->mode = force_mode;
     p->block = force_block;
@@ -318,8 +332,13 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
     int m, b;
     unsigned g;
     double us;
-    if (cache_lookup(key, &m, &b, &g, &us)) {
-      p->mode = m; p->block = b; p->grid = std::min(g, grid_for(m, b, 1 << 20)); p->best_us = us;
+    // A cached choice is used only when it is a valid configuration for this
+    // batch.
+    const bool cached = cache_lookup(key, &m, &b, &g, &us) && m >= 0 && m <= 1 &&
+                        (b == 64 || b == 128 || b == 256 || b == 512) && g > 0;
+    if (cached) {
+      p->mode = m; p->block = b; p->best_us = us;
+      p->grid = std::min(g, grid_for(m, b, 1 << 30));
       p->from_cache = true;
     } else {
       hipEvent_t e0, e1;

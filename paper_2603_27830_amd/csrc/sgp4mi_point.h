@@ -55,11 +55,13 @@ template <> __device__ __forceinline__ float rec_val<float, const Slot*>(const S
 template <> __device__ __forceinline__ double rec_val<double, GSlot>(GSlot sp, int k) { return sp->d[k]; }
 template <> __device__ __forceinline__ float rec_val<float, GSlot>(GSlot sp, int k) { return sp->f[k]; }
 
-template <class TS, class TP, class P>
-__device__ __forceinline__ SatC<TS, TP> load_from(P sp) {
+// Secular constants (and the info word) through sp, periodic constants
+// through pp (the same slot, possibly seen through another address space).
+template <class TS, class TP, class P, class PP>
+__device__ __forceinline__ SatC<TS, TP> load_from(P sp, PP pp) {
   SatC<TS, TP> c;
 #define S_(k) rec_val<TS, P>(sp, k)
-#define P_(k) rec_val<TP, P>(sp, k)
+#define P_(k) rec_val<TP, PP>(pp, k)
   c.M0 = S_(kM0); c.Mdot = S_(kMdot); c.argp0 = S_(kArgp0); c.argpdot = S_(kArgpdot); c.node0 = S_(kNode0);
   c.nodedot = S_(kNodedot); c.nodecf = S_(kNodecf); c.C1 = S_(kC1); c.bC4 = S_(kBC4); c.t2cof = S_(kT2cof);
   c.argpcof = S_(kArgpcof); c.Mcof = S_(kMcof); c.D2 = S_(kD2); c.D3 = S_(kD3); c.D4 = S_(kD4); c.bC5 = S_(kBC5);
@@ -76,8 +78,11 @@ __device__ __forceinline__ SatC<TS, TP> load_from(P sp) {
 
 template <class TS, class TP, bool kVec>
 __device__ __forceinline__ SatC<TS, TP> load_sat(const RecordView& rv, int64_t i) {
-  if (kVec) return load_from<TS, TP, GSlot>(lane_slot(rv.slots + i));
-  return load_from<TS, TP, const Slot*>(rv.slots + i);
+  if (kVec) {
+    const GSlot v = lane_slot(rv.slots + i);
+    return load_from<TS, TP, GSlot, GSlot>(v, v);
+  }
+  return load_from<TS, TP, const Slot*, const Slot*>(rv.slots + i, rv.slots + i);
 }
 
 __device__ __forceinline__ Grav load_grav(const RecordView& rv) {

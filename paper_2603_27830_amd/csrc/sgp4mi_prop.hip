@@ -86,6 +86,26 @@ __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const doub
   }
 }
 
+// Tile variant: one wavefront per tile of 64 times of one satellite (tile w =
+// satellite w / tps, times 64 * (w % tps) ...), workgroups of kBlock / 64
+// independent wavefronts, no loop.  Tile indices fit 32 bits (checked by the
+// launcher).
+template <class TS, class TP, int kBlock, bool kOff32>
+__global__ void __launch_bounds__(kBlock) dense_tile_kernel(RecordView rv, const double* __restrict__ t, int64_t T,
+                                                            uint32_t tps, uint32_t ntiles, Out<TP, kOff32> out) {
+  constexpr int kWaves = kBlock / 64;
+  const uint32_t w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= ntiles) return;
+  const uint32_t sat = w / tps;
+  const int64_t j = int64_t(w - sat * tps) * 64 + (threadIdx.x & 63);
+  if (j >= T) return;
+  const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, int64_t(sat));
+  const Grav g = load_grav(rv);
+  PointState<TP> s;
+  const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+  out.put(int64_t(sat) * T + j, code, s);
+}
+
 // Persistent variant: a fixed grid; each wavefront walks tiles of 64 times of
 // one satellite (tile w = satellite w / tps, times 64 * (w % tps) ...), so no
 // workgroup is dispatched per satellite and a wavefront's consecutive tiles
@@ -112,13 +132,39 @@ __global__ void __launch_bounds__(kBlock) dense_persistent_kernel(RecordView rv,
 }
 
 // ------------------------------------------------------------ ragged tiles --
-// tile_start[w]: first point of tile w; tile_sat[w]: its satellite.  A tile
-// holds min(64, end of that satellite's list - tile_start) points.
+// tile_start[w]: first point of tile w; tile_meta[2w], tile_meta[2w + 1]: its
+// satellite and its length (<= 64 points of that satellite's list).
+//
+// tile_once_kernel: the grid covers every tile, one wavefront each and no
+// loop, like the dense kernel: the wavefront ends after its stores, so nothing
+// waits for them.  tiles_kernel: a persistent grid whose wavefronts loop over
+// tiles (fewer workgroups; each iteration waits for the previous one's stores
+// before reusing their registers).
 template <class TS, class TP, int kBlock, bool kOff32>
-__global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int64_t* __restrict__ offsets,
-                                                       const double* __restrict__ t,
+__global__ void __launch_bounds__(kBlock) tile_once_kernel(RecordView rv, const double* __restrict__ t,
+                                                           const int64_t* __restrict__ tile_start,
+                                                           const int32_t* __restrict__ tile_meta, int64_t ntiles,
+                                                           Out<TP, kOff32> out) {
+  constexpr int kWaves = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = int64_t(blockIdx.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= ntiles) return;
+  const int64_t start = tile_start[w];
+  const int32_t sat = tile_meta[2 * w];
+  const int32_t len = tile_meta[2 * w + 1];
+  if (lane >= len) return;
+  const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, sat);
+  const Grav g = load_grav(rv);
+  const int64_t p = start + lane;
+  PointState<TP> s;
+  const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
+  out.put(p, code, s);
+}
+
+template <class TS, class TP, int kBlock, bool kOff32>
+__global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const double* __restrict__ t,
                                                        const int64_t* __restrict__ tile_start,
-                                                       const int32_t* __restrict__ tile_sat, int64_t ntiles,
+                                                       const int32_t* __restrict__ tile_meta, int64_t ntiles,
                                                        Out<TP, kOff32> out) {
   constexpr int kWaves = kBlock / 64;
   const int lane = threadIdx.x & 63;
@@ -127,14 +173,13 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const int6
   const Grav g = load_grav(rv);
   for (int64_t w = wave0; w < ntiles; w += nwaves) {
     const int64_t start = tile_start[w];
-    const int32_t sat = __builtin_amdgcn_readfirstlane(tile_sat[w]);
-    const int64_t end = offsets[sat + 1];
+    const int32_t sat = __builtin_amdgcn_readfirstlane(tile_meta[2 * w]);
+    const int32_t len = __builtin_amdgcn_readfirstlane(tile_meta[2 * w + 1]);
     const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, sat);  // satellite uniform: scalar constants
-    const int64_t p = start + lane;
-    if (p < end) {
+    if (lane < len) {
       PointState<TP> s;
-      const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
-      out.put(p, code, s);
+      const uint32_t code = sgp4_point<TS, TP>(c, g, t[start + lane], s);
+      out.put(start + lane, code, s);
     }
   }
 }
@@ -258,11 +303,59 @@ static hipError_t persist_t(const RecordView& rv, int64_t n, const double* t, in
   return hipGetLastError();
 }
 
+template <class TS, class TP, int kBlock>
+static void tile_go(hipStream_t s, const RecordView& rv, const double* t, int64_t T, int64_t n, void* r, void* v,
+                    uint8_t* err) {
+  const int64_t P = n * T;
+  const uint32_t tps = uint32_t((T + 63) / 64);
+  const uint32_t ntiles = uint32_t(n * tps);
+  const unsigned grid = unsigned((int64_t(ntiles) + kBlock / 64 - 1) / (kBlock / 64));
+  if (fits32<TP>(P)) {
+    Out<TP, true> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+    hipLaunchKernelGGL((dense_tile_kernel<TS, TP, kBlock, true>), dim3(grid), dim3(kBlock), 0, s, rv, t, T, tps,
+                       ntiles, o);
+  } else {
+    Out<TP, false> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+    hipLaunchKernelGGL((dense_tile_kernel<TS, TP, kBlock, false>), dim3(grid), dim3(kBlock), 0, s, rv, t, T, tps,
+                       ntiles, o);
+  }
+}
+
+template <class TS, class TP>
+static hipError_t tile_t(const RecordView& rv, int64_t n, const double* t, int64_t T, void* r, void* v, uint8_t* err,
+                         int block, hipStream_t s) {
+  switch (block) {
+    case 64: tile_go<TS, TP, 64>(s, rv, t, T, n, r, v, err); break;
+    case 128: tile_go<TS, TP, 128>(s, rv, t, T, n, r, v, err); break;
+    case 256: tile_go<TS, TP, 256>(s, rv, t, T, n, r, v, err); break;
+    case 512: tile_go<TS, TP, 512>(s, rv, t, T, n, r, v, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Number of 64-time tiles of an n x T batch, and whether the tile kernel can
+// index them (32-bit tile indices).
+bool dense_tiles_fit(int64_t n, int64_t T) {
+  const int64_t tps = (T + 63) / 64;
+  return n <= INT64_MAX / (tps > 0 ? tps : 1) && n * tps <= 0xffffffffLL;
+}
+
 // block: workgroup size; vec: constants through vector loads (else scalar);
-// grid > 0 selects the persistent kernel with that many workgroups.
+// grid > 0 selects the persistent kernel with that many workgroups; tiles
+// selects one wavefront per 64-time tile (scalar constants; the caller checks
+// dense_tiles_fit).
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, bool vec, unsigned grid, hipStream_t s) {
+                        uint8_t* err, int block, bool vec, unsigned grid, bool tiles, hipStream_t s) {
   const RecordView rv = view_of(consts, n);
+  if (tiles) {
+    switch (precision) {
+      case 0: return tile_t<double, double>(rv, n, t, T, r, v, err, block, s);
+      case 1: return tile_t<float, float>(rv, n, t, T, r, v, err, block, s);
+      case 2: return tile_t<double, float>(rv, n, t, T, r, v, err, block, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (grid > 0) {
     switch (precision) {
       case 0: return persist_t<double, double>(rv, n, t, T, r, v, err, block, vec, grid, s);
@@ -284,9 +377,12 @@ static void ragged_go(int mode, unsigned grid, hipStream_t s, const RecordView& 
                       int64_t n, const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                       int64_t ntiles, void* r, void* v, uint8_t* err) {
   Out<TP, kOff32> o{static_cast<TP*>(r), static_cast<TP*>(v), err, nnz};
-  if (mode == 0)
-    hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, t,
-                       tile_start, tile_sat, ntiles, o);
+  if (mode == 0 && int64_t(grid) * (kBlock / 64) >= ntiles)
+    hipLaunchKernelGGL((tile_once_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, t, tile_start,
+                       tile_sat, ntiles, o);
+  else if (mode == 0)
+    hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, t, tile_start,
+                       tile_sat, ntiles, o);
   else
     hipLaunchKernelGGL((flat_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, n, t, nnz,
                        tile_sat, ntiles, o);
@@ -316,7 +412,9 @@ static hipError_t ragged_t(int mode, const RecordView& rv, const int64_t* offset
   return hipGetLastError();
 }
 
-// mode 0: tiles (tile_start/tile_sat of ntiles); mode 1: flat (tile_sat holds
+// mode 0: tiles (tile_start and the (satellite, length) pairs in tile_sat, of
+// ntiles tiles; one wavefront per tile when the grid covers them all, else a
+// persistent loop); mode 1: flat (tile_sat holds
 // the chunk satellites of ntiles = ceil(nnz / 64) chunks or is null for the
 // in-kernel search; tile_start unused).
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,

@@ -53,6 +53,14 @@ def test_argument_errors_need_no_gpu():
     assert L.sgp4_propagate(fake, 10, fake, 10, 0, fake, None, fake, None) == E["SGP4_E_ARG"]
     # block size
     assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 96, None) == E["SGP4_E_ARG"]
+    # one-wavefront-per-tile mapping: scalar constants only, not persistent, unknown bits rejected
+    assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x40000, None) == E["SGP4_E_ARG"]
+    assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x10000 | 0x40000 | 0x20000 | (4 << 20),
+                               None) == E["SGP4_E_ARG"]
+    assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x80000, None) == E["SGP4_E_ARG"]
+    # more 64-time tiles than 32-bit tile indices address
+    assert L.sgp4_propagate_ex(fake, 2**31 - 1, fake, 64 * 4, 0, fake, fake, fake, 256 | 0x10000 | 0x40000,
+                               None) == E["SGP4_E_SIZE"]
     # empty batches are valid no-ops
     assert L.sgp4_propagate(fake, 0, fake, 10, 0, fake, fake, fake, None) == 0
     assert L.sgp4_propagate(fake, 10, fake, 0, 0, fake, fake, fake, None) == 0
@@ -71,6 +79,11 @@ def test_argument_errors_need_no_gpu():
     assert L.sgp4_plan_create(None, fake, 10, fake, fake, 10, 0, fake, fake, fake, 0, None) == E["SGP4_E_ARG"]
     assert L.sgp4_plan_create(ctypes.byref(out), fake, 10, fake, fake, 10, 7, fake, fake, fake, 0,
                               None) == E["SGP4_E_PRECISION"]
+    # unknown ragged mapping, bad workgroup size
+    assert L.sgp4_plan_create_config(ctypes.byref(out), fake, 10, fake, fake, 10, 0, fake, fake, fake, 2, 256, 0, 0,
+                                     None) == E["SGP4_E_ARG"]
+    assert L.sgp4_plan_create_config(ctypes.byref(out), fake, 10, fake, fake, 10, 0, fake, fake, fake, 1, 96, 0, 0,
+                                     None) == E["SGP4_E_ARG"]
     assert L.sgp4_plan_launch(None, None) == E["SGP4_E_ARG"]
     L.sgp4_plan_destroy(None)
 

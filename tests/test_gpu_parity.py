@@ -37,7 +37,7 @@ def say(msg):
     print(msg, flush=True)
 
 
-def gpu_dense(elem, t, prec="fp64", block=sg.DEFAULT_DENSE, grav=None):
+def gpu_dense(elem, t, prec="fp64", block=None, grav=None):
     rec = sg.init(dev(elem), grav)
     r, v, err = sg.propagate(rec, dev(t), prec, block=block)
     return host(r, v, err)
@@ -58,9 +58,10 @@ def check_fp64(r, v, err, ro, vo, eo, tol_r=1e-6, tol_v=1e-9):
 
 
 # ------------------------------------------------------------------- FP64 --
-SCALAR, PERSIST = 0x10000, 0x20000
+SCALAR, PERSIST, TILES = 0x10000, 0x20000, 0x40000
 CONFIGS = [64, 128, 256, 512, 256 | SCALAR, 512 | SCALAR, 256 | PERSIST | (4 << 20),
-           512 | SCALAR | PERSIST | (8 << 20), 64 | SCALAR | PERSIST | (1 << 20)]
+           512 | SCALAR | PERSIST | (8 << 20), 64 | SCALAR | PERSIST | (1 << 20),
+           64 | SCALAR | TILES, 256 | SCALAR | TILES, 512 | SCALAR | TILES]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
@@ -337,6 +338,10 @@ def test_plain_fp32_reproduces_the_papers_error_growth():
 
 
 # ------------------------------------------------------------------ ragged --
+# Agreement between ragged mappings (km, km/s): one sub-tolerance Kepler step.
+MAPPING_TOL = {"fp64": (1e-8, 1e-11), "mixed": (1e-3, 1e-6)}
+
+
 def small_ragged(n=700, seed=21):
     """Short lognormal lists (several tiles per list, ragged tails), 5% heavy
     drag, and empty lists at the start, middle and end."""
@@ -375,11 +380,13 @@ def test_ragged_all_mappings_match_oracle(prec):
             ok = (eo == 0) | (eo == 6)
             dr, dv = _errors(r[:, ok], v[:, ok], ro[:, ok], vo[:, ok])
             assert dr.max() <= 0.010 and dv.max() <= 1e-5, (name, dr.max(), dv.max())
-    # Mappings agree to rounding: the Kepler loop stops when every lane of a
-    # wavefront has converged, so a lane's last (sub-tolerance) step depends
-    # on which points share its wavefront.
+    # Mappings agree to the Kepler tolerance: the loop stops when every lane
+    # of a wavefront has converged, so whether a lane takes one more
+    # (sub-tolerance) step depends on which points share its wavefront; a
+    # step below 1e-12 rad (FP64) or 1e-7 rad (float) moves r by < 7e-9 km or
+    # 7e-4 km and v by < 8e-12 km/s or 8e-7 km/s.
     base = results["search"]
-    tol_r, tol_v = (1e-8, 1e-11) if prec == "fp64" else (2e-4, 2e-7)
+    tol_r, tol_v = MAPPING_TOL[prec]
     for name, (r, v, err) in results.items():
         assert np.array_equal(err, base[2])
         ok = (err == 0) | (err == 6)
@@ -405,6 +412,43 @@ def test_ragged_tile_and_flat_modes_explicitly():
                 assert np.all(np.isnan(out[0][:, ~ok]))
                 assert np.max(np.abs(out[0][:, ok] - ref[0][:, ok])) <= 1e-8
                 assert np.max(np.abs(out[1][:, ok] - ref[1][:, ok])) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ragged_long_lists_every_mapping(prec):
+    """Lists of 0 to 5,000 points (several tiles, ragged tails, empty lists):
+    one wavefront per tile, the persistent tile loop and the flat mapping match
+    the oracle, and the two tile mappings (same 64-point chunks) agree to the
+    Kepler tolerance."""
+    lens = [0, 1, 63, 64, 65, 1023, 1024, 1025, 2047, 2048, 2049, 3000, 4096, 5000, 0, 700]
+    n = len(lens)
+    el = synth.shell_elements(n, 31)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    rng = np.random.default_rng(31)
+    t = np.concatenate([np.sort(rng.uniform(0.0, 10080.0, L)) for L in lens])
+    say(f"[gpu] ragged long lists {prec} nnz={t.shape[0]}")
+    rec = sg.init(dev(el))
+    doff, dt = dev(off), dev(t)
+    ro, vo, eo = oracle.propagate_ragged(el, off, t)
+    outs = []
+    for cfg in [(0, 256, 0), (0, 256, 1), (1, 128, 0)]:
+        plan = sg.RaggedPlan(rec, doff, dt, prec, autotune=False, graph=False, config=cfg)
+        r, v, err = host(*plan.launch())
+        plan.close()
+        if prec == "fp64":
+            check_fp64(r, v, err, ro, vo, eo)
+        else:
+            assert np.array_equal(err, eo), cfg
+            ok = (eo == 0) | (eo == 6)
+            dr, dv = _errors(r[:, ok], v[:, ok], ro[:, ok], vo[:, ok])
+            assert dr.max() <= 0.010 and dv.max() <= 1e-5, (cfg, dr.max(), dv.max())
+        outs.append((r, v, err))
+    (r, v, err), (r1, v1, e1) = outs[0], outs[1]
+    assert np.array_equal(err, e1)
+    ok = (err == 0) | (err == 6)
+    tol_r, tol_v = MAPPING_TOL[prec]
+    assert np.max(np.abs(r[:, ok].astype(np.float64) - r1[:, ok])) <= tol_r
+    assert np.max(np.abs(v[:, ok].astype(np.float64) - v1[:, ok])) <= tol_v
 
 
 def test_ragged_graph_replays_match_eager():
