@@ -180,7 +180,8 @@ def cpu_baseline(cat, prec_name="fp64"):
 
 def calibrate(torch):
     """Achievable rates on this GPU: unpacked FP64 and FP32 FMA (8 independent
-    chains per lane) and a non-temporal store stream."""
+    chains per lane; FP32 with all operands in vector registers and with one in a
+    scalar register) and a non-temporal store stream."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2603_27830_amd", "libsgp4mi_calib.so"))
     lib.sgp4mi_calib_fma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
@@ -188,11 +189,23 @@ def calibrate(torch):
     stream = torch.cuda.current_stream().cuda_stream
     blocks, iters = 256 * 64, 4096
     res = {}
-    for prec, dt in ((0, torch.float64), (1, torch.float32)):
+    names = {0: "fma_f64_tflops", 1: "fma_f32_vgpr_tflops", 2: "fma_f32_sgpr_operand_tflops"}
+    for prec, dt in ((0, torch.float64), (1, torch.float32), (2, torch.float32)):
         out = torch.empty(blocks * 256, dtype=dt, device="cuda")
         launch = lambda: lib.sgp4mi_calib_fma(prec, ctypes.c_void_p(out.data_ptr()), blocks, iters, stream)
         sec = kernel_time(launch, torch, reps=5)
-        res["fma_f64_tflops" if prec == 0 else "fma_f32_tflops"] = blocks * 256 * iters * 8 * 2 / sec / 1e12
+        res[names[prec]] = blocks * 256 * iters * 8 * 2 / sec / 1e12
+    lib.sgp4mi_calib_rate.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    kinds = ["v_fma_f32 (vector operands)", "v_fma_f32 (one scalar operand)", "v_mul_f32", "v_fma_f64", "v_sin_f32",
+             "v_rcp_f32", "v_rcp_f64", "v_cvt_f32_f64"]
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    res["clocks_per_wave_instruction_per_simd_at_2.4GHz"] = {}
+    for kind, name in enumerate(kinds):
+        launch = lambda: lib.sgp4mi_calib_rate(kind, ctypes.c_void_p(out.data_ptr()), blocks, 1024, stream)
+        sec = kernel_time(launch, torch, reps=5)
+        per_simd = blocks * 4 * 1024 * 8 / simds
+        res["clocks_per_wave_instruction_per_simd_at_2.4GHz"][name] = round(sec * 2.4e9 / per_simd, 2)
     n = 1 << 30  # 8 GiB of doubles
     buf = torch.empty(n, dtype=torch.float64, device="cuda")
     launch = lambda: lib.sgp4mi_calib_store(ctypes.c_void_p(buf.data_ptr()), n, 256 * 64, stream)
