@@ -4,19 +4,24 @@
 //
 // One workgroup per satellite.  Each lane recomputes the forward pass of its
 // points (nothing from the forward launch is stored), then runs the reverse
-// sweep of the per-point steps by hand, accumulating the adjoint of every
+// sweep of the per-point steps by hand, giving the adjoint of every
 // per-satellite constant in double.  Kepler's equation is differentiated
-// through the implicit-function theorem at its root.  The workgroup reduces
-// the constant adjoints in a fixed order (wavefront butterfly, then the
-// wavefronts in index order: no atomics, so results repeat bit for bit), and
-// seven lanes then push them through the initialisation by forward-mode
-// duals, one element each: g_m = sum_k cbar_k * d c_k / d theta_m.
+// through the implicit-function theorem at its root.  Each lane accumulates
+// the adjoints of its points; the workgroup then sums them in a fixed order
+// (wavefront butterfly, then the wavefronts in index order: no atomics, so
+// results repeat bit for bit), and seven lanes push the sums through the
+// initialisation by forward-mode duals, one element each:
+// g_m = sum_k cbar_k * d c_k / d theta_m.
 #include "sgp4mi_initcore.h"
 #include "sgp4mi_point.h"
 
 namespace sgp4mi {
 
 constexpr int kVjpBlock = 256;
+// Workgroups per compute unit the register allocation must allow: two (two
+// wavefronts per SIMD) in FP64, whose reverse sweep otherwise spills past 256
+// registers and runs one wavefront per SIMD; three in the mixed path.
+template <class TP> constexpr int kVjpBlocksPerCU = sizeof(TP) == 8 ? 2 : 3;
 
 template <class TS, class TP>
 __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, double t_abs, const TP gr[3],
@@ -26,6 +31,9 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   const bool simp = (c.info & kInfoIsimp) != 0;
 
   // ---------------------------------------------------------- forward --
+  // The forward kernel's formulation (reciprocals, small-angle rotations,
+  // the argument of latitude kept as a (sin, cos) pair), keeping what the
+  // reverse sweep needs.
   const TS t = TS(t_abs - c.epoch_min);
   const TS t2 = t * t, t3 = t2 * t, t4 = t3 * t;
   const TS Mdf = c.M0 + c.Mdot * t;
@@ -37,14 +45,17 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   TS M = Mdf, argp = argpdf;
   TP sMdf = TP(0), cMdf = TP(1), x = TP(1), sM = TP(0), cM = TP(1);
   if (!simp) {
-    TR::sc(Mdf, &sMdf, &cMdf);
+    TR::sc_damped(Mdf, &sMdf, &cMdf);
     x = TP(1) + c.eta * cMdf;
     const TS dM = c.Mcof * TS(x * x * x - c.dM0);
     const TS dMa = c.argpcof * t + dM;
     M = Mdf + dMa;
     argp = argpdf - dMa;
     A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
-    TR::sc(M, &sM, &cM);
+    sM = sMdf;
+    cM = cMdf;
+    if (vabs(dMa) <= TS(kRotMax)) rotate_small(&sM, &cM, TP(dMa));
+    else TR::sc_damped(M, &sM, &cM);
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
     Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
   }
@@ -53,26 +64,30 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   if (!(e_s >= TS(-0.001) && e_s < TS(1))) return;
   const bool clamped = e_s < TS(1.0e-6);
   if (clamped) e_s = TS(1.0e-6);
-  const TS L = M + c.n0pp * Ld + argp + node;
   const TP a = TP(a_s), e = TP(e_s);
   TP sw, cw;
-  TR::sc(argp, &sw, &cw);
+  TR::sc_damped(argp, &sw, &cw);
   const TP axn = e * cw;
   const TP q = a * (TP(1) - e * e);
-  const TP tau = TP(1) / q;
+  const TP tau = rcp(q);
   const TP ayn = e * sw + tau * c.aycof;
-  const TS LT = L + TS(tau * c.Lcof * axn);
-  const TS U = LT - node;
+  // U = L_T - node with L = M + n0 Ld + argp + node
+  const TS U = M + c.n0pp * Ld + argp + TS(tau * c.Lcof * axn);
   TP sp, cp;
   TR::sc(U, &sp, &cp);
-  TP dpsi = TP(0);
-  for (int k = 0; k < 10; ++k) {
-    TP step = (axn * sp - ayn * cp - dpsi) / (TP(1) - axn * cp - ayn * sp);
-    step = step > TP(0.95) ? TP(0.95) : step;
-    step = step < TP(-0.95) ? TP(-0.95) : step;
-    dpsi = dpsi + step;
-    TR::sc(U + TS(dpsi), &sp, &cp);
-    if (__all(vabs(step) < kepler_tol<TP>())) break;
+  {
+    TP dpsi = TP(0);
+    const TP eb = vabs(axn) + vabs(ayn);
+    const TP quad = eb < TP(0.5) ? TP(0.5) * eb * rcp(TP(1) - eb) : TP(1.0e30);
+    for (int k = 0; k < 10; ++k) {
+      TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
+      step = clamp_step(step);
+      dpsi = dpsi + step;
+      if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
+      else TR::sc(U + TS(dpsi), &sp, &cp);
+      const TP as = vabs(step);
+      if (__all(as < kepler_tol<TP>() || quad * as * as < kepler_tol<TP>())) break;
+    }
   }
   const TP D = TP(1) - axn * cp - ayn * sp;
   const TP ecE = axn * cp + ayn * sp;
@@ -81,36 +96,47 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   const TP pL = a * (TP(1) - eL2);
   if (!(pL >= TP(0))) return;
   const TP rl = a * (TP(1) - ecE);
-  const TP sqa = sq_root(a), sqp = sq_root(pL);
-  const TP rdotl = sqa * esE / rl;
-  const TP rvdotl = sqp / rl;
+  const TP irl = rcp(rl);
+  const TP ra = rsq(a);
+  const TP sqa = a * ra;
+  const TP rdotl = sqa * esE * irl;
   const TP betal = sq_root(TP(1) - eL2);
+  const TP sqp = sqa * betal;  // sqrt(pL)
+  const TP rvdotl = sqp * irl;
   const TP opb = TP(1) + betal;
-  const TP w = esE / opb;
-  const TP ar = a / rl;
+  const TP iopb = rcp(opb);
+  const TP w = esE * iopb;
+  const TP ar = a * irl;
   const TP f1 = sp - ayn - axn * w;
   const TP f2 = cp - axn + ayn * w;
   const TP sinu = ar * f1, cosu = ar * f2;
   const TP nu2 = sinu * sinu + cosu * cosu;
-  const TP u = arctan2(sinu, cosu);
   const TP sin2u = TP(2) * sinu * cosu;
   const TP cos2u = TP(1) - TP(2) * sinu * sinu;
-  const TP ipl = TP(1) / pL;
+  const TP ipl = rcp(pL);
   const TP k2g = TP(g.k2);
   const TP k1 = k2g * ipl;
   const TP k2 = k1 * ipl;
-  const TP nk = TP(1) / (a * sqa);
+  const TP nk = ra * ra * ra;  // a^-3/2
   const TP g1 = c.x1 * cos2u + TP(1.5) * c.c41;
   const TP mrt = rl * (TP(1) - TP(1.5) * k2 * betal * c.c41) + TP(0.5) * k1 * c.x1 * cos2u;
-  const TP su = u - TP(0.25) * k2 * c.x7 * sin2u;
+  const TP du = TP(-0.25) * k2 * c.x7 * sin2u;
   const TP dnode = TP(1.5) * k2 * c.cosi * sin2u;
-  const TP xinc = c.i0 + TP(1.5) * k2 * c.cosi * c.sini * cos2u;
+  const TP dinc = TP(1.5) * k2 * c.cosi * c.sini * cos2u;
   const TP mvt = rdotl - nk * k1 * c.x1 * sin2u;
   const TP rvdot = rvdotl + nk * k1 * g1;
-  TP ssu, csu, snod, cnod, sinc, cinc;
-  sincos_rr(su, &ssu, &csu);
+  TP ssu, csu, snod, cnod, sinc = c.sini, cinc = c.cosi;
+  if (vabs(du) <= TP(kRotMax)) {
+    const TP h = rsq(nu2);
+    ssu = sinu * h;
+    csu = cosu * h;
+    rotate_small(&ssu, &csu, du);
+  } else {
+    TR::sc(TS(arctan2(sinu, cosu) + du), &ssu, &csu);
+  }
+  if (vabs(dinc) <= TP(kRotMax)) rotate_small(&sinc, &cinc, dinc);
+  else TR::sc(TS(c.i0 + dinc), &sinc, &cinc);
   TR::sc(node + TS(dnode), &snod, &cnod);
-  sincos_rr(xinc, &sinc, &cinc);
   const TP xmx = -snod * cinc, xmy = cnod * cinc;
   const TP ux = xmx * ssu + cnod * csu, uy = xmy * ssu + snod * csu, uz = sinc * ssu;
   const TP vx = xmx * csu - cnod * ssu, vy = xmy * csu - snod * ssu, vz = sinc * csu;
@@ -163,29 +189,30 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   k1_b += mrt_b * TP(0.5) * c.x1 * cos2u;
   x1_b += mrt_b * TP(0.5) * k1 * cos2u;
   cos2u_b += mrt_b * TP(0.5) * k1 * c.x1;
-  TP a_b = nk_b * TP(-1.5) * nk / a;
+  TP a_b = nk_b * TP(-1.5) * nk * ra * ra;
   k1_b += k2_b * ipl;
   const TP ipl_b = k2_b * k1 + k1_b * k2g;
   TP pL_b = -ipl_b * ipl * ipl;
 
   // short-period preliminaries
-  const TP sinu_b = TP(-4) * sinu * cos2u_b + TP(2) * cosu * sin2u_b + u_b * cosu / nu2;
-  const TP cosu_b = TP(2) * sinu * sin2u_b - u_b * sinu / nu2;
+  const TP inu2 = rcp(nu2);
+  const TP sinu_b = TP(-4) * sinu * cos2u_b + TP(2) * cosu * sin2u_b + u_b * cosu * inu2;
+  const TP cosu_b = TP(2) * sinu * sin2u_b - u_b * sinu * inu2;
   const TP ar_b = sinu_b * f1 + cosu_b * f2;
   TP sp_b = sinu_b * ar, cp_b = cosu_b * ar;
   TP ayn_b = -sinu_b * ar + cosu_b * ar * w;
   TP axn_b = -sinu_b * ar * w - cosu_b * ar;
   const TP w_b = -sinu_b * ar * axn + cosu_b * ar * ayn;
-  a_b += ar_b / rl;
-  rl_b -= ar_b * ar / rl;
-  TP esE_b = w_b / opb;
-  betal_b -= w_b * w / opb;
-  TP eL2_b = -betal_b * TP(0.5) / betal;
-  pL_b += rvdotl_b * TP(0.5) / (sqp * rl);
-  rl_b -= rvdotl_b * rvdotl / rl;
-  a_b += rdotl_b * TP(0.5) * rdotl / a;
-  esE_b += rdotl_b * sqa / rl;
-  rl_b -= rdotl_b * rdotl / rl;
+  a_b += ar_b * irl;
+  rl_b -= ar_b * ar * irl;
+  TP esE_b = w_b * iopb;
+  betal_b -= w_b * w * iopb;
+  TP eL2_b = -betal_b * TP(0.5) * rcp(betal);
+  pL_b += rvdotl_b * TP(0.5) * rcp(sqp) * irl;
+  rl_b -= rvdotl_b * rvdotl * irl;
+  a_b += rdotl_b * TP(0.5) * rdotl * ra * ra;
+  esE_b += rdotl_b * sqa * irl;
+  rl_b -= rdotl_b * rdotl * irl;
   a_b += rl_b * (TP(1) - ecE);
   const TP ecE_b = -rl_b * a;
   a_b += pL_b * (TP(1) - eL2);
@@ -197,7 +224,7 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   const TP psi_b = sp_b * cp - cp_b * sp;
 
   // Kepler's equation at its root: d psi = (dU + sin psi daxn - cos psi dayn) / D
-  const TP pD = psi_b / D;
+  const TP pD = psi_b * rcp(D);
   const TS U_b = TS(pD);
   axn_b += pD * sp;
   ayn_b -= pD * cp;
@@ -277,10 +304,9 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
 }
 
 template <class TS, class TP>
-__global__ void __launch_bounds__(kVjpBlock) vjp_kernel(RecordView rv, int64_t n, const double* __restrict__ elem,
-                                                         const double* __restrict__ t, int64_t T,
-                                                         const TP* __restrict__ gr, const TP* __restrict__ gv,
-                                                         double* __restrict__ gelem) {
+__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
+    vjp_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t, int64_t T,
+               const TP* __restrict__ gr, const TP* __restrict__ gv, double* __restrict__ gelem) {
   constexpr int kWaves = kVjpBlock / 64;
   __shared__ double part[kWaves][kNRec];
   __shared__ double cbar[kNRec];
