@@ -1,14 +1,14 @@
 // Device math for the per-point path: sine/cosine of any angle of the
 // model, rotation by small angles, and fast reciprocals.
 //
-// sincos_rr / sincos_mx: y = x - 2*pi*k with k = rint(x / 2*pi) (a two-part
-// 2*pi, the product exact inside the fused multiply-add), h = y / 2 in
-// [-pi/2, pi/2], the Taylor series of sin h and cos h (1/n! coefficients:
-// through h^21 / h^20 in double, truncation below 2e-17; h^13 / h^12 in
-// float, below 7e-10), then the double-angle identities sin x = 2 sin h cos h,
-// cos x = 1 - 2 sin^2 h.  No quadrant selection is needed, so nothing depends
-// on k fitting an integer.  sincos_mx reduces in double and evaluates the
-// series in float.
+// sincos_rr: y = x - 2*pi*k with k = rint(x / 2*pi) (a two-part 2*pi, the
+// product exact inside the fused multiply-add), h = y / 2 in [-pi/2, pi/2],
+// the Taylor series of sin h and cos h (1/n! coefficients: through h^21 /
+// h^20 in double, truncation below 2e-17; h^13 / h^12 in float, below 7e-9),
+// then the double-angle identities sin x = 2 sin h cos h, cos x = 1 -
+// 2 sin^2 h.  No quadrant selection is needed, so nothing depends on k
+// fitting an integer.  sincos_mx reduces to a fraction of a turn in double and
+// evaluates the same series, scaled, in float.
 //
 // rotate_small: (sin x, cos x) -> (sin(x+d), cos(x+d)) by angle addition with
 // the series of sin d and cos d; used for |d| <= kRotMax, exact to rounding
@@ -89,7 +89,33 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
   half_angle(0.5f * y, s, c);
 }
 
-__device__ __forceinline__ void sincos_mx(double x, float* s, float* c) { half_angle(float(half_reduced(x)), s, c); }
+// Mixed: the angle as a fraction of a turn, f = x / 2pi - rint(x / 2pi) in
+// [-1/2, 1/2] (three double operations; rounding f to float costs at most
+// 2^-26 of a turn), then the series of sin(pi f) and cos(pi f) in f, whose
+// coefficients carry the powers of pi (the leading pi as a float pair), and
+// the double-angle identities.
+__device__ __forceinline__ void sincos_mx(double x, float* s, float* c) {
+  const double r = x * kHalfAngle64[20];
+  const float f = float(r - rint(r));
+  const float u = f * f;
+  float p = fmaf(u, 4.66302805768e-4f, -7.37043094571e-3f);
+  p = fmaf(p, u, 8.21458866111e-2f);
+  p = fmaf(p, u, -5.99264529321e-1f);
+  p = fmaf(p, u, 2.55016403988f);
+  p = fmaf(p, u, -5.16771278005f);
+  // sin(pi f) = pi f + f u P(u), pi = pi_hi + pi_lo in float: the leading
+  // product is exact inside the fused multiply-add, rounding only the sum
+  const float sh = fmaf(f, 3.14159274101257324f, f * fmaf(p, u, -8.74227800e-8f));
+  float q = fmaf(u, -1.04638104925e-4f, 1.92957430940e-3f);
+  q = fmaf(q, u, -2.58068913900e-2f);
+  q = fmaf(q, u, 2.35330630359e-1f);
+  q = fmaf(q, u, -1.33526276885f);
+  q = fmaf(q, u, 4.05871212642f);
+  q = fmaf(q, u, -4.93480220054f);
+  const float ch = fmaf(q, u, 1.0f);  // cos(pi f)
+  *s = 2.0f * sh * ch;
+  *c = fmaf(-2.0f * sh, sh, 1.0f);
+}
 
 // Hardware sine and cosine (v_sin_f32 / v_cos_f32 take the argument in
 // revolutions): the angle is reduced to a fraction of a turn in its own type,

@@ -196,9 +196,8 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
   if (e_s < TS(1.0e-6)) e_s = TS(1.0e-6);
   // Angles stay unreduced: every one of them only enters through sin/cos,
-  // whose own reduction (by multiples of pi/2) handles any size met here.
+  // whose own reduction handles any size met here.
   M = M + c.n0pp * Ld;
-  const TS L = M + argp + node;
 
   // Long-period periodics (J3).
   const TP a = TP(a_s), e = TP(e_s);
@@ -207,7 +206,6 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP axn = e * cw;
   const TP tau = rcp(a * (TP(1) - e * e));
   const TP ayn = e * sw + tau * c.aycof;
-  const TS LT = L + TS(tau * c.Lcof * axn);
 
   // Kepler: psi - axn sin psi + ayn cos psi = U, Newton from psi = U with the
   // step clamped to +-0.95; dpsi = psi - U.  A lane is done once its step is
@@ -215,7 +213,9 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   // step, eL / (2 (1 - eL)) * step^2 with eL <= |axn| + |ayn|, is below it (the
   // step that would follow changes psi by less than the tolerance).  The loop
   // ends when every lane of the wavefront is done (at most 10 steps).
-  const TS U = LT - node;
+  // U = L_T - node, with the mean longitude L = M + argp + node and its J3
+  // long-period correction L_T = L + tau L_cof a_xN: node cancels.
+  const TS U = M + argp + TS(tau * c.Lcof * axn);
   TP sp, cp;
   TR::sc(U, &sp, &cp);
   TP dpsi = TP(0);
