@@ -2,13 +2,14 @@
 // model, rotation by small angles, and fast reciprocals.
 //
 // sincos_rr: y = x - 2*pi*k with k = rint(x / 2*pi) (a two-part 2*pi, the
-// product exact inside the fused multiply-add), h = y / 2 in [-pi/2, pi/2],
-// the Taylor series of sin h and cos h (1/n! coefficients: through h^21 /
-// h^20 in double, truncation below 2e-17; h^13 / h^12 in float, below 7e-9),
-// then the double-angle identities sin x = 2 sin h cos h, cos x = 1 -
-// 2 sin^2 h.  No quadrant selection is needed, so nothing depends on k
+// product exact inside the fused multiply-add), then the Taylor series of sin
+// and cos (1/n! coefficients) at a fraction of y and the double-angle
+// identities sin 2h = 2 sin h cos h, cos 2h = 1 - 2 sin^2 h: in float at
+// h = y / 2 in [-pi/2, pi/2] (through h^13 / h^12, truncation below 7e-9),
+// in double at h = y / 4 in [-pi/4, pi/4] (through h^15 / h^16, below 5e-17),
+// doubling twice.  No quadrant selection is needed, so nothing depends on k
 // fitting an integer.  sincos_mx reduces to a fraction of a turn in double and
-// evaluates the same series, scaled, in float.
+// evaluates the float series, scaled, at it.
 //
 // rotate_small: (sin x, cos x) -> (sin(x+d), cos(x+d)) by angle addition with
 // the series of sin d and cos d; used for |d| <= kRotMax, exact to rounding
@@ -72,15 +73,34 @@ __device__ __forceinline__ void half_angle(float h, float* s, float* c) {
   *c = fmaf(-2.0f * sh, sh, 1.0f);
 }
 
-__device__ __forceinline__ double half_reduced(double x) {
+// Double: a quarter of the reduced angle, |h| <= pi/4, where the series need
+// only the terms through h^15 (sin) and h^16 (cos), truncation below 5e-17
+// (fewer coefficients held in scalar registers), then the double-angle
+// identities twice.
+__device__ __forceinline__ void quarter_angle(double h, double* s, double* c) {
+  const double* k = kHalfAngle64;
+  const double h2 = h * h;
+  double p = fma(k[3], h2, k[4]);
+#pragma unroll
+  for (int i = 5; i < 10; ++i) p = fma(p, h2, k[i]);
+  const double sh = fma(p * h2, h, h);
+  double q = fma(k[12], h2, k[13]);
+#pragma unroll
+  for (int i = 14; i < 20; ++i) q = fma(q, h2, k[i]);
+  const double ch = fma(q, h2, 1.0);
+  const double s2 = 2.0 * sh * ch;
+  const double c2 = fma(-2.0 * sh, sh, 1.0);
+  *s = 2.0 * s2 * c2;
+  *c = fma(-2.0 * s2, s2, 1.0);
+}
+
+__device__ __forceinline__ void sincos_rr(double x, double* s, double* c) {
   const double* k = kHalfAngle64;
   const double n = rint(x * k[20]);
   double y = fma(-n, k[21], x);
   y = fma(-n, k[22], y);
-  return 0.5 * y;
+  quarter_angle(0.25 * y, s, c);
 }
-
-__device__ __forceinline__ void sincos_rr(double x, double* s, double* c) { half_angle(half_reduced(x), s, c); }
 
 __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
   const float n = rintf(x * 0.15915494309189533577f);
