@@ -27,7 +27,10 @@ enum Rec : int {
 };
 
 // Header slots (doubles).
-enum Hdr : int { kHMagic, kHN, kHNpad, kHKe, kHRadius, kHVkms, kHK2, kHJ2, kHJ3oJ2, kHJ4, kHMu, kHCount = 64 };
+// kHF32: float copies of radius, velocity unit and k2 (three floats in the
+// eight bytes of slots kHF32 and kHF32 + 1), so the float paths read them
+// without a conversion per point.
+enum Hdr : int { kHMagic, kHN, kHNpad, kHKe, kHRadius, kHVkms, kHK2, kHJ2, kHJ3oJ2, kHJ4, kHMu, kHF32, kHCount = 64 };
 constexpr double kMagic = 20260331.0;
 
 constexpr uint32_t kInfoCodeMask = 0xffu;
@@ -66,7 +69,17 @@ inline RecordView view_of(const void* base, int64_t n) {
 // Gravity-derived scalars read by the kernels (from the record header).
 struct Grav {
   double ke, radius, vkms, k2;
+  float radius_f, vkms_f, k2_f;
 };
+template <class T> __device__ __forceinline__ T grav_radius(const Grav& g);
+template <class T> __device__ __forceinline__ T grav_vkms(const Grav& g);
+template <class T> __device__ __forceinline__ T grav_k2(const Grav& g);
+template <> __device__ __forceinline__ double grav_radius<double>(const Grav& g) { return g.radius; }
+template <> __device__ __forceinline__ double grav_vkms<double>(const Grav& g) { return g.vkms; }
+template <> __device__ __forceinline__ double grav_k2<double>(const Grav& g) { return g.k2; }
+template <> __device__ __forceinline__ float grav_radius<float>(const Grav& g) { return g.radius_f; }
+template <> __device__ __forceinline__ float grav_vkms<float>(const Grav& g) { return g.vkms_f; }
+template <> __device__ __forceinline__ float grav_k2<float>(const Grav& g) { return g.k2_f; }
 
 // ------------------------------------------------------------- math (FP64) --
 constexpr double kPi = 3.14159265358979323846;

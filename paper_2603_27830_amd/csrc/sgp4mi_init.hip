@@ -32,6 +32,11 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     h[kHJ3oJ2] = j3oj2;
     h[kHJ4] = a.j4;
     h[kHMu] = a.mu;
+    float* hf = reinterpret_cast<float*>(h + kHF32);
+    hf[0] = float(a.radius);
+    hf[1] = float(a.radius * ke / 60.0);
+    hf[2] = float(0.5 * a.j2);
+    hf[3] = 0.0f;
   }
   if (i >= a.n) return;
   const int64_t n = a.n;

@@ -91,6 +91,10 @@ __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
   g.radius = rv.hdr[kHRadius];
   g.vkms = rv.hdr[kHVkms];
   g.k2 = rv.hdr[kHK2];
+  const float* f = reinterpret_cast<const float*>(rv.hdr + kHF32);
+  g.radius_f = f[0];
+  g.vkms_f = f[1];
+  g.k2_f = f[2];
   return g;
 }
 
@@ -253,7 +257,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
 
   // Short-period periodics (J2).
   const TP inv_pl = rcp(pL);
-  const TP k1 = TP(g.k2) * inv_pl;
+  const TP k1 = grav_k2<TP>(g) * inv_pl;
   const TP k2 = k1 * inv_pl;
   const TP nk = ra * ra * ra;  // n / ke = a^-3/2
   const TP mrt = rl * (TP(1) - TP(1.5) * k2 * betal * c.c41) + TP(0.5) * k1 * c.x1 * cos2u;
@@ -286,8 +290,8 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP xmx = -snod * cinc, xmy = cnod * cinc;
   const TP ux = xmx * ssu + cnod * csu, uy = xmy * ssu + snod * csu, uz = sinc * ssu;
   const TP vx = xmx * csu - cnod * ssu, vy = xmy * csu - snod * ssu, vz = sinc * csu;
-  const TP rk = mrt * TP(g.radius);
-  const TP vk = TP(g.vkms);
+  const TP rk = mrt * grav_radius<TP>(g);
+  const TP vk = grav_vkms<TP>(g);
   out.r[0] = rk * ux; out.r[1] = rk * uy; out.r[2] = rk * uz;
   out.v[0] = vk * (mvt * ux + rvdot * vx);
   out.v[1] = vk * (mvt * uy + rvdot * vy);

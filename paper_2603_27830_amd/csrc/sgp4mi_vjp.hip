@@ -114,7 +114,7 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   const TP sin2u = TP(2) * sinu * cosu;
   const TP cos2u = TP(1) - TP(2) * sinu * sinu;
   const TP ipl = rcp(pL);
-  const TP k2g = TP(g.k2);
+  const TP k2g = grav_k2<TP>(g);
   const TP k1 = k2g * ipl;
   const TP k2 = k1 * ipl;
   const TP nk = ra * ra * ra;  // a^-3/2
@@ -142,7 +142,7 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   const TP vx = xmx * csu - cnod * ssu, vy = xmy * csu - snod * ssu, vz = sinc * csu;
 
   // ---------------------------------------------------------- reverse --
-  const TP R = TP(g.radius), vk = TP(g.vkms);
+  const TP R = grav_radius<TP>(g), vk = grav_vkms<TP>(g);
   const TP mrt_b = R * (gr[0] * ux + gr[1] * uy + gr[2] * uz);
   const TP mvt_b = vk * (gv[0] * ux + gv[1] * uy + gv[2] * uz);
   const TP rvdot_b = vk * (gv[0] * vx + gv[1] * vy + gv[2] * vz);
