@@ -38,6 +38,7 @@ MUTANTS = [
     ("C2 eta-squared coefficient", "(1.0 + 1.5 * eta2 + e0eta", "(1.0 + 2.5 * eta2 + e0eta"),
     ("C4 first-order bracket", "e0 * (0.5 + 2.0 * eta2)", "e0 * (0.5 + 1.0 * eta2)"),
     ("C5 prefactor", "c.C5 = 2.0 * coef1", "c.C5 = 2.5 * coef1"),
+    ("drag node coefficient", "c.nodecf = 3.5 * c.beta0sq", "c.nodecf = 3.0 * c.beta0sq"),
     ("eccentricity floor of code 1", "if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);",
      "if (!(val(e) >= -0.01 && val(e) < 1.0)) return fail(1);"),
 ]

@@ -211,6 +211,28 @@ def test_secular_rates_first_order_j2():
     assert np.max(np.abs(ci["Mdot"] - mean) / scale) < 0.01
 
 
+@pytest.mark.parametrize("inc", [0.3, 0.93, 1.7])
+def test_drag_node_term_is_the_nodal_rate_along_the_decaying_orbit(inc):
+    """The node's t^2 drag term: the first-order J2 nodal rate -1.5 J2 n cos i / p^2
+    (proportional to a^-7/2) followed along the model's decaying semi-major axis
+    a(t) = a0 (1 - C1 t)^2 gives node - node0 - nodedot t = (1/2) dOmegadot/dt t^2,
+    which for e0 -> 0 is nodecf.  The derivative is taken numerically here."""
+    a0 = (RE + 400.0) / RE
+    el = np.array([[KE * a0 ** -1.5], [1e-5], [inc], [0.1], [0.2], [0.3], [5e-4], [0.0]])
+    ci = oracle.init_constants(el)
+    a, C1 = ci["a0pp"][0], ci["C1"][0]
+    assert C1 > 0
+
+    def rate(t):
+        at = a * (1.0 - C1 * t) ** 2
+        return -1.5 * J2 * KE * at ** -1.5 * math.cos(inc) / at ** 2
+
+    assert abs(rate(0.0) / ci["nodedot1"][0] - 1) < 1e-9
+    h = 10.0
+    half_second_derivative = 0.5 * (rate(h) - rate(-h)) / (2 * h)
+    assert abs(ci["nodecf"][0] / half_second_derivative - 1) < 1e-6
+
+
 def test_nodal_regression_of_starlink_shells():
     """Magnitudes in degrees/day: ~-4.5 at 53 deg / 550 km, and the 97.6 deg / 560 km
     shell is sun-synchronous (+360/365.2422 deg/day) to ~1%."""
