@@ -39,6 +39,8 @@ MUTANTS = [
     ("C4 first-order bracket", "e0 * (0.5 + 2.0 * eta2)", "e0 * (0.5 + 1.0 * eta2)"),
     ("C5 prefactor", "c.C5 = 2.0 * coef1", "c.C5 = 2.5 * coef1"),
     ("drag node coefficient", "c.nodecf = 3.5 * c.beta0sq", "c.nodecf = 3.0 * c.beta0sq"),
+    ("J4 perigee polynomial", "T3 * (3.0 - 36.0 * th2 + 49.0 * th4)", "T3 * (3.0 - 36.0 * th2 + 48.0 * th4)"),
+    ("J4 node polynomial", "2.0 * T3 * (3.0 - 7.0 * th2)", "2.0 * T3 * (3.0 - 6.0 * th2)"),
     ("eccentricity floor of code 1", "if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);",
      "if (!(val(e) >= -0.01 && val(e) < 1.0)) return fail(1);"),
 ]

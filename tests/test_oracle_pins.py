@@ -249,6 +249,50 @@ def _init_diff(el_a, el_b, grav_a=None, grav_b=None):
     return {k for k in oracle.INIT_NAMES if not np.array_equal(a[k], b[k])}
 
 
+def _averaged_zonal_potential(a, e, inc, n_deg, jn, mu, npts=1024, nw=32):
+    """Average over the mean anomaly and the argument of perigee (the secular part) of
+    the disturbing function of one zonal harmonic, R = -(mu / r) J_n (1 / r)^n
+    P_n(sin(lat)), sin(lat) = sin i sin(w + f) (lengths in earth radii), by the
+    trapezoid rule on uniform grids (exact for the trigonometric polynomials in w)."""
+    M = np.arange(npts) * (2 * math.pi / npts)
+    E = M.copy()
+    for _ in range(50):
+        E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+    r = a * (1 - e * np.cos(E))
+    f = 2 * np.arctan2(math.sqrt(1 + e) * np.sin(E / 2), math.sqrt(1 - e) * np.cos(E / 2))
+    w = np.arange(nw)[:, None] * (2 * math.pi / nw)
+    x = math.sin(inc) * np.sin(w + f[None, :])
+    P = np.polynomial.legendre.legval(x, [0] * n_deg + [1])
+    return float(np.mean(-(mu / r[None, :]) * jn * r[None, :] ** -n_deg * P))
+
+
+@pytest.mark.parametrize("inc,e", [(0.4, 0.002), (0.93, 0.005), (1.2, 0.002), (1.71, 0.004)])
+def test_j4_secular_rates_follow_lagrange_equations(inc, e):
+    """J4 alone (J2 = J3 = 0): the model's secular perigee and node rates equal
+    Lagrange's planetary equations applied to the numerically orbit-averaged J4
+    disturbing function, dw/dt = sqrt(1-e^2)/(n a^2 e) dR/de - cos i/(n a^2 sqrt(1-e^2)
+    sin i) dR/di and dnode/dt = dR/di / (n a^2 sqrt(1-e^2) sin i), to the model's
+    order in e (its J4 terms drop the e^2 parts: relative 10 e^2 here)."""
+    grav = (MU, RE, 0.0, 0.0, J4)
+    a0 = (RE + 700.0) / RE
+    el = np.array([[KE * a0 ** -1.5], [e], [inc], [0.3], [0.7], [0.1], [0.0], [0.0]])
+    ci = oracle.init_constants(el, grav)
+    a, n = ci["a0pp"][0], ci["n0pp"][0]
+    assert abs(n - KE * a ** -1.5) < 1e-15 * n
+    mu = KE * KE
+    Rbar = lambda aa, ee, ii: _averaged_zonal_potential(aa, ee, ii, 4, J4, mu)
+    he, hi = 1e-4 * e, 1e-5
+    dR_de = (Rbar(a, e + he, inc) - Rbar(a, e - he, inc)) / (2 * he)
+    dR_di = (Rbar(a, e, inc + hi) - Rbar(a, e, inc - hi)) / (2 * hi)
+    b = math.sqrt(1 - e * e)
+    wdot = b / (n * a * a * e) * dR_de - math.cos(inc) / (n * a * a * b * math.sin(inc)) * dR_di
+    nodedot = dR_di / (n * a * a * b * math.sin(inc))
+    scale = abs(1.5 * n * J4 / a ** 4)
+    tol = 10 * e * e + 1e-6
+    assert abs(ci["argpdot"][0] - wdot) <= tol * scale, (ci["argpdot"][0], wdot)
+    assert abs(ci["nodedot"][0] - nodedot) <= tol * scale, (ci["nodedot"][0], nodedot)
+
+
 def test_term_groups_are_separable():
     el = synth.config1(64, 2).elem
     no_j3 = (MU, RE, J2, 0.0, J4)
