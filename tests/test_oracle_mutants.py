@@ -41,6 +41,8 @@ MUTANTS = [
     ("drag node coefficient", "c.nodecf = 3.5 * c.beta0sq", "c.nodecf = 3.0 * c.beta0sq"),
     ("J4 perigee polynomial", "T3 * (3.0 - 36.0 * th2 + 49.0 * th4)", "T3 * (3.0 - 36.0 * th2 + 48.0 * th4)"),
     ("J4 node polynomial", "2.0 * T3 * (3.0 - 7.0 * th2)", "2.0 * T3 * (3.0 - 6.0 * th2)"),
+    ("J3 long-period longitude polynomial", "(3.0 + 5.0 * c.cosi) / den", "(3.0 + 4.0 * c.cosi) / den"),
+    ("J3 long-period eccentricity coefficient", "c.aycof = -0.5 * j3oj2", "c.aycof = -0.45 * j3oj2"),
     ("eccentricity floor of code 1", "if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);",
      "if (!(val(e) >= -0.01 && val(e) < 1.0)) return fail(1);"),
 ]

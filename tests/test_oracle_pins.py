@@ -293,6 +293,63 @@ def test_j4_secular_rates_follow_lagrange_equations(inc, e):
     assert abs(ci["nodedot"][0] - nodedot) <= tol * scale, (ci["nodedot"][0], nodedot)
 
 
+def _averaged_j3_potential(a, e, inc, w, npts=2048):
+    """Average over the mean anomaly (argument of perigee w held) of the J3 disturbing
+    function R = -(mu / r) J3 (1 / r)^3 P3(sin i sin(w + f)), lengths in earth radii."""
+    M = np.arange(npts) * (2 * math.pi / npts)
+    E = M.copy()
+    for _ in range(50):
+        E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+    r = a * (1 - e * np.cos(E))
+    f = 2 * np.arctan2(math.sqrt(1 + e) * np.sin(E / 2), math.sqrt(1 - e) * np.cos(E / 2))
+    x = math.sin(inc) * np.sin(w + f)
+    return float(np.mean(-(KE * KE / r) * J3 * r ** -3 * 0.5 * (5 * x ** 3 - 3 * x)))
+
+
+@pytest.mark.parametrize("inc", [0.4, 0.93, 1.2, 1.71])
+def test_j3_long_period_coefficients_follow_lagrange_equations(inc):
+    """The J3 long-period terms, rebuilt from Lagrange's planetary equations: the
+    orbit-averaged J3 disturbing function is K e sin w (numerical quadrature, K read at
+    w = pi/2), the first-order J2 secular rates turn w (w' = 0.75 n J2 (5 cos^2 i - 1) /
+    p^2), and integrating over w gives
+      d(e sin w) = -sqrt(1-e^2) K / (n a^2 w')                 (a constant: aycof / p),
+      d(e cos w) = 0,
+      d(lambda)  = -G' cos w / w',  G' = the sin w amplitude of the mean longitude's rate:
+                   Lagrange's J3 rate (-2/(na) dR/da + sqrt(1-e^2)(1-sqrt(1-e^2))/(n a^2 e)
+                   dR/de + tan(i/2)/(n a^2 sqrt(1-e^2)) dR/di) plus the J2 rate of
+                   lambda = M + w + node moved by the long-period changes of e and i,
+    which must equal the model's aycof / p and L_cof e cos w / p (first order in e)."""
+    e = 1e-3
+    a0 = (RE + 700.0) / RE
+    el = np.array([[KE * a0 ** -1.5], [e], [inc], [0.3], [0.7], [0.1], [0.0], [0.0]])
+    ci = oracle.init_constants(el)
+    a, n = ci["a0pp"][0], ci["n0pp"][0]
+    b, p, c, s = math.sqrt(1 - e * e), a * (1 - e * e), math.cos(inc), math.sin(inc)
+    wdot2 = 0.75 * n * J2 * (5 * c * c - 1) / p ** 2
+    K = _averaged_j3_potential(a, e, inc, math.pi / 2) / e
+    assert abs(-b * K / (n * a * a * wdot2) * p / ci["aycof"][0] - 1) < 1e-4
+
+    def lam_j3(w):
+        ha, he, hi = 1e-6, 1e-4 * e, 1e-5
+        dRa = (_averaged_j3_potential(a + ha, e, inc, w) - _averaged_j3_potential(a - ha, e, inc, w)) / (2 * ha)
+        dRe = (_averaged_j3_potential(a, e + he, inc, w) - _averaged_j3_potential(a, e - he, inc, w)) / (2 * he)
+        dRi = (_averaged_j3_potential(a, e, inc + hi, w) - _averaged_j3_potential(a, e, inc - hi, w)) / (2 * hi)
+        return (-2 / (n * a) * dRa + b * (1 - b) / (n * a * a * e) * dRe
+                + math.tan(inc / 2) / (n * a * a * b) * dRi)
+
+    def lam_j2(ee, ii):
+        bb, pp, cc = math.sqrt(1 - ee * ee), a * (1 - ee * ee), math.cos(ii)
+        return 0.75 * n * J2 * (bb * (3 * cc * cc - 1) + 5 * cc * cc - 1 - 2 * cc) / pp ** 2
+
+    G = (lam_j3(math.pi / 2) - lam_j3(-math.pi / 2)) / 2
+    de = -b * K / (n * a * a * wdot2)                      # d e = de sin w
+    di = c * K * e / (n * a * a * b * s * wdot2)            # d i = di sin w
+    dl2_de = (lam_j2(e * (1 + 1e-4), inc) - lam_j2(e * (1 - 1e-4), inc)) / (2e-4 * e)
+    dl2_di = (lam_j2(e, inc + 1e-6) - lam_j2(e, inc - 1e-6)) / 2e-6
+    Gp = G + dl2_de * de + dl2_di * di
+    assert abs(-Gp / wdot2 * p / e / ci["Lcof"][0] - 1) < 1e-4
+
+
 def test_term_groups_are_separable():
     el = synth.config1(64, 2).elem
     no_j3 = (MU, RE, J2, 0.0, J4)
