@@ -116,8 +116,9 @@ enum { SGP4_PLAN_AUTOTUNE = 1, SGP4_PLAN_GRAPH = 2 };
 /* Ragged propagation: satellite i has times t[offsets[i] .. offsets[i+1]).
  * offsets: device int64 [n+1] with offsets[0] = 0, non-decreasing,
  * offsets[n] = nnz.  t: device float64 [nnz].  r, v: [3][nnz]; err: [nnz].
- * plan: NULL (one persistent launch whose wavefronts locate their satellites
- * by binary search of the offsets; the offsets are not checked on the host) or
+ * plan: NULL (one launch, a wavefront per 64 consecutive points, whose lanes
+ * locate their satellites by binary search of the offsets; the offsets are not
+ * checked on the host) or
  * a plan created for exactly these buffers (launches its tuned kernel
  * directly, without the graph). */
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,

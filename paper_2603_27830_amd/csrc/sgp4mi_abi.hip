@@ -241,8 +241,11 @@ int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets,
       return SGP4_E_PLAN;
     return hip_status(plan_launch_direct(plan, s));
   }
+  // One wavefront per 64-point chunk (a wavefront that ends after its stores
+  // never waits for them); the grid is capped at 2^31 - 1 workgroups, beyond
+  // which the wavefronts loop.
   const int64_t nchunks = (nnz + 63) / 64;
-  const unsigned grid = unsigned(std::min<int64_t>((nchunks + 3) / 4, int64_t(compute_units()) * 8));
+  const unsigned grid = unsigned(std::min<int64_t>((nchunks + 3) / 4, 0x7fffffff));
   return hip_status(launch_ragged(precision, 1, consts, n, offsets, t, nnz, nullptr, nullptr, nchunks, r, v, err, 256,
                                   std::max(grid, 1u), s));
 }

@@ -202,12 +202,22 @@ __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64
     if (chunk_sat) {
       first = chunk_sat[k];
     } else {
-      // offsets[lo] <= q < offsets[hi] holds throughout (offsets[0] = 0 <= q < nnz = offsets[n]).
+      // 64-way search by the whole wavefront: each round every lane probes one
+      // of 64 evenly spaced offsets of [lo, hi) and a ballot keeps the piece
+      // holding q.  offsets[lo] <= q < offsets[hi] holds throughout
+      // (offsets[0] = 0 <= q < nnz = offsets[n]); offsets are non-decreasing,
+      // so the probes that pass form a prefix of the lanes, lane 0 always.
       const int64_t q = k * 64;
       int64_t lo = 0, hi = n;
       while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (offsets[mid] <= q) lo = mid; else hi = mid;
+        const int64_t step = (hi - lo + 63) >> 6;
+        const int64_t idx = lo + step * lane;
+        const bool pass = idx < hi && offsets[idx] <= q;
+        const uint64_t ballot = __ballot(pass);
+        const int last = 63 - __builtin_clzll(ballot);
+        const int64_t nlo = lo + step * last;
+        hi = nlo + step < hi ? nlo + step : hi;
+        lo = nlo;
       }
       first = lo;
     }
