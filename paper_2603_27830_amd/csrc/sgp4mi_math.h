@@ -8,8 +8,7 @@
 // h = y / 2 in [-pi/2, pi/2] (through h^13 / h^12, truncation below 7e-9),
 // in double at h = y / 4 in [-pi/4, pi/4] (through h^15 / h^16, below 5e-17),
 // doubling twice.  No quadrant selection is needed, so nothing depends on k
-// fitting an integer.  sincos_mx reduces to a fraction of a turn in double and
-// evaluates the float series, scaled, at it.
+// fitting an integer.
 //
 // rotate_small: (sin x, cos x) -> (sin(x+d), cos(x+d)) by angle addition with
 // the series of sin d and cos d; used for |d| <= kRotMax, exact to rounding
@@ -25,6 +24,8 @@ constexpr double kRotMax = 0.05;
 // Double-precision constants live in constant memory: gfx9 VALU instructions
 // take no 64-bit literals, and scalar-register operands (one per instruction)
 // avoid holding every coefficient in a vector register pair.
+// The quarter-angle series reads the sine terms from index 3 (1/15!) and the
+// cosine terms from index 12 (1/16!); the higher orders are kept for reference.
 __constant__ double kHalfAngle64[24] = {
     // sin h = h + h^3 * P(h^2): -1/3!, 1/5!, ..., 1/21! (index 0 = highest order)
     1.95729410633912612308e-20, -8.22063524662432971696e-18, 2.8114572543455207632e-15,
@@ -39,21 +40,6 @@ __constant__ double kHalfAngle64[24] = {
     0.15915494309189533577, 6.2831853071795864769, 2.4492935982947063e-16,
     // unused
     0.0};
-
-__device__ __forceinline__ void half_angle(double h, double* s, double* c) {
-  const double* k = kHalfAngle64;
-  const double h2 = h * h;
-  double p = fma(k[0], h2, k[1]);
-#pragma unroll
-  for (int i = 2; i < 10; ++i) p = fma(p, h2, k[i]);
-  const double sh = fma(p * h2, h, h);
-  double q = fma(k[10], h2, k[11]);
-#pragma unroll
-  for (int i = 12; i < 20; ++i) q = fma(q, h2, k[i]);
-  const double ch = fma(q, h2, 1.0);
-  *s = 2.0 * sh * ch;
-  *c = fma(-2.0 * sh, sh, 1.0);
-}
 
 __device__ __forceinline__ void half_angle(float h, float* s, float* c) {
   const float h2 = h * h;
@@ -107,34 +93,6 @@ __device__ __forceinline__ void sincos_rr(float x, float* s, float* c) {
   float y = fmaf(-n, 6.28318548202514648438f, x);   // float nearest 2*pi
   y = fmaf(-n, -1.7484556e-7f, y);                   // 2*pi minus that
   half_angle(0.5f * y, s, c);
-}
-
-// Mixed: the angle as a fraction of a turn, f = x / 2pi - rint(x / 2pi) in
-// [-1/2, 1/2] (three double operations; rounding f to float costs at most
-// 2^-26 of a turn), then the series of sin(pi f) and cos(pi f) in f, whose
-// coefficients carry the powers of pi (the leading pi as a float pair), and
-// the double-angle identities.
-__device__ __forceinline__ void sincos_mx(double x, float* s, float* c) {
-  const double r = x * kHalfAngle64[20];
-  const float f = float(r - rint(r));
-  const float u = f * f;
-  float p = fmaf(u, 4.66302805768e-4f, -7.37043094571e-3f);
-  p = fmaf(p, u, 8.21458866111e-2f);
-  p = fmaf(p, u, -5.99264529321e-1f);
-  p = fmaf(p, u, 2.55016403988f);
-  p = fmaf(p, u, -5.16771278005f);
-  // sin(pi f) = pi f + f u P(u), pi = pi_hi + pi_lo in float: the leading
-  // product is exact inside the fused multiply-add, rounding only the sum
-  const float sh = fmaf(f, 3.14159274101257324f, f * fmaf(p, u, -8.74227800e-8f));
-  float q = fmaf(u, -1.04638104925e-4f, 1.92957430940e-3f);
-  q = fmaf(q, u, -2.58068913900e-2f);
-  q = fmaf(q, u, 2.35330630359e-1f);
-  q = fmaf(q, u, -1.33526276885f);
-  q = fmaf(q, u, 4.05871212642f);
-  q = fmaf(q, u, -4.93480220054f);
-  const float ch = fmaf(q, u, 1.0f);  // cos(pi f)
-  *s = 2.0f * sh * ch;
-  *c = fmaf(-2.0f * sh, sh, 1.0f);
 }
 
 // Hardware sine and cosine (v_sin_f32 / v_cos_f32 take the argument in

@@ -100,11 +100,13 @@ __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
 
 // ------------------------------------------------------- typed primitives --
 // Sine and cosine of an angle held in the secular type, evaluated in the
-// periodic type (reduction in the secular type).  sc is the full-accuracy
-// evaluation; sc_damped serves angles whose sine and cosine enter the state
-// only through a small factor (the eccentricity in e cos w, e sin w; the drag
-// coefficients multiplying functions of M), where the 32-bit hardware sine
-// and cosine (argument in revolutions) suffice.
+// periodic type (reduction in the secular type).  sc_damped serves angles whose
+// sine and cosine enter the state only through a small factor (the
+// eccentricity in e cos w, e sin w; the drag coefficients multiplying
+// functions of M).  In the mixed path every angle goes to the 32-bit hardware
+// sine and cosine (argument reduced to a turn fraction in double; absolute
+// error ~1.3e-7, a few tenths of a metre at LEO radius); the plain FP32 path
+// keeps its series for the undamped angles, FP64 its series everywhere.
 template <class TS, class TP>
 struct Trig;
 template <>
@@ -119,7 +121,7 @@ struct Trig<float, float> {
 };
 template <>
 struct Trig<double, float> {
-  static __device__ __forceinline__ void sc(double x, float* s, float* c) { sincos_mx(x, s, c); }
+  static __device__ __forceinline__ void sc(double x, float* s, float* c) { sincos_hw(x, s, c); }
   static __device__ __forceinline__ void sc_damped(double x, float* s, float* c) { sincos_hw(x, s, c); }
 };
 
