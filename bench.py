@@ -383,6 +383,15 @@ def main():
             log(f"[bench] vjp {name}: {P / kv:.3e} pts/s, {kv * 1e3:.3f} ms")
             del r, gr
         del r_obs
+        # Full Jacobian d(r, v)/d(elements) at every point: 42 doubles per point.
+        paths["jacobian_9341x1000"] = {}
+        jac = torch.empty((6, 7, cat.n, cat.T), dtype=torch.float64, device=dev)
+        for name in ("fp64", "mixed"):
+            kj = kernel_time(lambda: sg.jacobian(rec, t, name, out=jac), torch, reps=3)
+            paths["jacobian_9341x1000"][name] = {"points_per_s": P / kj, "kernel_ms": kj * 1e3,
+                                                 "hbm_gbs": 336 * P / kj / 1e9}
+            log(f"[bench] jacobian {name}: {P / kj:.3e} pts/s, {kj * 1e3:.3f} ms")
+        del jac
         torch.cuda.empty_cache()
 
     if not args.no_ragged and not args.only:

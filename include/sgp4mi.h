@@ -169,6 +169,17 @@ void sgp4_plan_destroy(sgp4_plan* plan);
 int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
              const void* gr, const void* gv, double* gelem, void* stream);
 
+/* Jacobian of the dense propagation (section 5: the state's sensitivity to the
+ * elements, as for state-transition matrices and covariance propagation):
+ * jac[(c * 7 + m) * n*T + i*T + j] = d s_c / d theta_m at satellite i, time j,
+ * with s = (r_x, r_y, r_z, v_x, v_y, v_z) (km, km/s) and theta as for sgp4_vjp.
+ * jac: device float64 [6][7][n*T], written in full; NaN where the point's
+ * code is 1, 2, 4 or 7.  elem, consts, t as for sgp4_vjp.  Computed by one
+ * reverse sweep per state component, so it costs about six VJPs.  FP32 is
+ * rejected (SGP4_E_PRECISION). */
+int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
+                  double* jac, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -211,6 +211,22 @@ def vjp(rec: Record, t: torch.Tensor, gr: torch.Tensor, gv: Optional[torch.Tenso
     return out
 
 
+def jacobian(rec: Record, t: torch.Tensor, precision="fp64", out: Optional[torch.Tensor] = None):
+    """Jacobian of the dense propagation: float64 [6, 7, n, T], d(r, v)/d(elements),
+    NaN at points whose code is 1, 2, 4 or 7."""
+    p = _prec(precision)
+    _need(t, torch.float64, "t", rec.device)
+    n, T = rec.n, int(t.numel())
+    if out is None:
+        out = torch.empty((6, 7, n, T), dtype=torch.float64, device=rec.device)
+    elif out.dtype != torch.float64 or out.numel() != 42 * n * T or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of 42*n*T elements")
+    with torch.cuda.device(rec.device):
+        _native.check(_native.lib().sgp4_jacobian(n, _ptr(rec.elem), _ptr(rec.consts), _ptr(t), T, p, _ptr(out),
+                                                  _stream(rec.device)), "sgp4_jacobian")
+    return out
+
+
 class SGP4Function(torch.autograd.Function):
     """(elem [8, n], t [T]) -> (r [3, n, T], v [3, n, T]); backward through the
     hand-written VJP kernel (no gradient for the epoch row or the times)."""

@@ -27,6 +27,8 @@ hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
 hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* consts, const double* t, int64_t T,
                       const void* gr, const void* gv, double* gelem, hipStream_t s);
+hipError_t launch_jacobian(int precision, int64_t n, const double* elem, const void* consts, const double* t,
+                           int64_t T, double* jac, hipStream_t s);
 }  // namespace sgp4mi
 
 using namespace sgp4mi;
@@ -434,6 +436,15 @@ int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t,
   if (n == 0) return SGP4_OK;
   if (!elem || !consts || !gelem || (T > 0 && (!t || !gr))) return SGP4_E_ARG;
   return hip_status(launch_vjp(precision, n, elem, consts, t, T, gr, gv, gelem, static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
+                  double* jac, void* stream) {
+  if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 42)) return SGP4_E_SIZE;
+  if (precision != SGP4_FP64 && precision != SGP4_FP32_MIXED) return SGP4_E_PRECISION;
+  if (n == 0 || T == 0) return SGP4_OK;
+  if (!elem || !consts || !t || !jac) return SGP4_E_ARG;
+  return hip_status(launch_jacobian(precision, n, elem, consts, t, T, jac, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

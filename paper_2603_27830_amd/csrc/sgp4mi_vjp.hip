@@ -24,10 +24,10 @@ constexpr int kVjpBlock = 256;
 template <class TP> constexpr int kVjpBlocksPerCU = sizeof(TP) == 8 ? 2 : 3;
 
 template <class TS, class TP>
-__device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, double t_abs, const TP gr[3],
+__device__ __forceinline__ uint32_t point_vjp(const SatC<TS, TP>& c, const Grav& g, double t_abs, const TP gr[3],
                                           const TP gv[3], double* cb) {
   using TR = Trig<TS, TP>;
-  if (c.info & kInfoCodeMask) return;
+  if (c.info & kInfoCodeMask) return c.info & kInfoCodeMask;
   const bool simp = (c.info & kInfoIsimp) != 0;
 
   // ---------------------------------------------------------- forward --
@@ -61,7 +61,7 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   }
   const TS a_s = c.a0pp * A * A;
   TS e_s = c.e0 - Ed;
-  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return;
+  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
   const bool clamped = e_s < TS(1.0e-6);
   if (clamped) e_s = TS(1.0e-6);
   const TP a = TP(a_s), e = TP(e_s);
@@ -94,7 +94,7 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   const TP esE = axn * sp - ayn * cp;
   const TP eL2 = axn * axn + ayn * ayn;
   const TP pL = a * (TP(1) - eL2);
-  if (!(pL >= TP(0))) return;
+  if (!(pL >= TP(0))) return 4;
   const TP rl = a * (TP(1) - ecE);
   const TP irl = rcp(rl);
   const TP ra = rsq(a);
@@ -301,6 +301,7 @@ __device__ __forceinline__ void point_vjp(const SatC<TS, TP>& c, const Grav& g, 
   cb[kCosi] += double(cosi_b);
   cb[kSini] += double(sini_b);
   cb[kI0] += double(i0_b);
+  return mrt < TP(1) ? 6u : 0u;
 }
 
 template <class TS, class TP>
@@ -360,6 +361,89 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
     }
     gelem[m * n + i] = out;
   }
+}
+
+// Jacobian of the dense propagation (paper section 5: the state's sensitivity
+// to the elements, the state-transition and covariance use):
+// jac[(c * 7 + m) * P + p] = d state_c / d theta_m at point p, c over r_x, r_y,
+// r_z, v_x, v_y, v_z and m over the seven differentiated elements; NaN where
+// the point's code is 1, 2, 4 or 7.  One workgroup per satellite: seven lanes
+// first push the unit tangents of the elements through the initialisation
+// (forward-mode duals) into the constants' sensitivities dc_k / dtheta_m (LDS);
+// then, per point, each lane runs the reverse sweep once per state component
+// (unit cotangent) and contracts the constants' adjoints with them.
+template <class TS, class TP>
+__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
+    jacobian_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t,
+                    int64_t T, double* __restrict__ jac) {
+  __shared__ double dc[7][kNRec];
+  const int64_t i = blockIdx.x;
+  const uint32_t scode = rv.slots[i].info & kInfoCodeMask;
+  if (threadIdx.x < 7) {
+    const int m = threadIdx.x;
+    if (scode == 0) {
+      Dual1 el[7];
+      for (int k = 0; k < 7; ++k) el[k] = Dual1(elem[k * n + i], k == m ? 1.0 : 0.0);
+      GravIn gi{rv.hdr[kHRadius], rv.hdr[kHJ2], rv.hdr[kHJ4], rv.hdr[kHKe], rv.hdr[kHJ3oJ2]};
+      Dual1 rec[kNRec];
+      uint32_t code;
+      bool isimp;
+      init_record<Dual1>(gi, el, rec, &code, &isimp);
+#pragma unroll
+      for (int k = 0; k < kNRec; ++k) dc[m][k] = k == kEpochMin ? 0.0 : rec[k].d;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kNRec; ++k) dc[m][k] = 0.0;
+    }
+  }
+  __syncthreads();
+  // the constants are read after the duals' registers are free again
+  const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, i);
+  const Grav g = load_grav(rv);
+  const int64_t P = n * T;
+  const double qnan = __builtin_nan("");
+  for (int64_t j = threadIdx.x; j < T; j += kVjpBlock) {
+    const int64_t p = i * T + j;
+    const double tj = t[j];
+#pragma unroll 1
+    for (int comp = 0; comp < 6; ++comp) {
+      TP gr[3], gv[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        gr[q] = comp == q ? TP(1) : TP(0);
+        gv[q] = comp == q + 3 ? TP(1) : TP(0);
+      }
+      double cb[kNRec];
+#pragma unroll
+      for (int k = 0; k < kNRec; ++k) cb[k] = 0.0;
+      const uint32_t code = point_vjp<TS, TP>(c, g, tj, gr, gv, cb);
+      const bool ok = code == 0 || code == 6;
+      // One element at a time, the sensitivities re-read from LDS (the empty
+      // asm keeps the compiler from hoisting all 238 of them into registers).
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        asm volatile("" ::: "memory");
+        double row = 0.0;
+#pragma unroll
+        for (int k = 0; k < kNRec; ++k) row = fma(cb[k], dc[m][k], row);
+        st_nt(jac + (comp * 7 + m) * P + p, ok ? row : qnan);
+      }
+    }
+  }
+}
+
+hipError_t launch_jacobian(int precision, int64_t n, const double* elem, const void* consts, const double* t,
+                           int64_t T, double* jac, hipStream_t s) {
+  const RecordView rv = view_of(consts, n);
+  if (precision == 0)
+    hipLaunchKernelGGL((jacobian_kernel<double, double>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n, elem, t, T,
+                       jac);
+  else if (precision == 2)
+    hipLaunchKernelGGL((jacobian_kernel<double, float>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n, elem, t, T,
+                       jac);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* consts, const double* t, int64_t T,

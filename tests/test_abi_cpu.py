@@ -48,6 +48,10 @@ def test_argument_errors_need_no_gpu():
     # precision
     assert L.sgp4_propagate(fake, 10, fake, 10, 3, fake, fake, fake, None) == E["SGP4_E_PRECISION"]
     assert L.sgp4_vjp(10, fake, fake, fake, 10, 1, fake, None, fake, None) == E["SGP4_E_PRECISION"]
+    assert L.sgp4_jacobian(10, fake, fake, fake, 10, 1, fake, None) == E["SGP4_E_PRECISION"]
+    assert L.sgp4_jacobian(-1, fake, fake, fake, 10, 0, fake, None) == E["SGP4_E_SIZE"]
+    assert L.sgp4_jacobian(10, None, fake, fake, 10, 0, fake, None) == E["SGP4_E_ARG"]
+    assert L.sgp4_jacobian(2**31 - 1, fake, fake, fake, 2**30, 0, fake, None) == E["SGP4_E_SIZE"]
     # null pointers
     assert L.sgp4_propagate(None, 10, fake, 10, 0, fake, fake, fake, None) == E["SGP4_E_ARG"]
     assert L.sgp4_propagate(fake, 10, fake, 10, 0, fake, None, fake, None) == E["SGP4_E_ARG"]
