@@ -242,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ragged", action="store_true", help="skip the 1M-satellite ragged catalogue")
     ap.add_argument("--no-vjp", action="store_true", help="skip the VJP on the 9341 x 1000 grid")
+    ap.add_argument("--no-short", action="store_true",
+                    help="skip the short-list (1M satellites x 1-32 times) elements-to-states comparison")
     ap.add_argument("--only", default=None, help="time one path only (fp64, fp32, mixed) for profiling")
     ap.add_argument("--ragged-only", default=None, metavar="PREC",
                     help="profiling mode: only the 1M-satellite ragged catalogue in one precision (fp64, mixed)")
@@ -392,6 +394,40 @@ def main():
                                                  "hbm_gbs": 336 * P / kj / 1e9}
             log(f"[bench] jacobian {name}: {P / kj:.3e} pts/s, {kj * 1e3:.3f} ms")
         del jac
+        torch.cuda.empty_cache()
+
+    if not args.no_short and not args.only:
+        # Short time lists over the 1M-satellite catalogue's elements: the fused
+        # elements-to-states launch against the two-stage path's parts (init;
+        # the flat and the 64-time tile dense mappings).
+        n5 = 1_000_000
+        el5 = synth.shell_elements(n5, 3)
+        el5[6, np.random.default_rng(1003).random(n5) < 0.05] *= 100.0
+        e5 = torch.from_numpy(el5).to(dev)
+        paths["short_lists_1M"] = {}
+        rec5 = sg.init(e5)
+        ki = kernel_time(lambda: sg.init(e5), torch, reps=5)
+        paths["short_lists_1M"]["init_ms"] = ki * 1e3
+        log(f"[bench] 1M init {ki * 1e3:.3f} ms")
+        for T5 in (1, 8, 16, 32, 48):
+            t5 = torch.from_numpy(np.linspace(0.0, 1440.0, T5)).to(dev)
+            row = {}
+            for name in ("fp64", "mixed"):
+                dt = torch.float64 if name == "fp64" else torch.float32
+                out5 = (torch.empty((3, n5, T5), dtype=dt, device=dev), torch.empty((3, n5, T5), dtype=dt, device=dev),
+                        torch.empty((n5, T5), dtype=torch.uint8, device=dev))
+                kf = kernel_time(lambda: sg.propagate_elements(e5, t5, name, out=out5), torch, reps=5)
+                kl = kernel_time(lambda: sg.propagate(rec5, t5, name, out=out5, block=256 | 0x80000), torch, reps=5)
+                kt = kernel_time(lambda: sg.propagate(rec5, t5, name, out=out5,
+                                                      block=(256 if name == "fp64" else 512) | 0x50000), torch, reps=5)
+                row[name] = {"fused_ms": kf * 1e3, "flat_ms": kl * 1e3, "tiles_ms": kt * 1e3,
+                             "fused_points_per_s": n5 * T5 / kf}
+                log(f"[bench] 1M x {T5} {name}: fused {kf * 1e3:.3f} ms; propagate flat {kl * 1e3:.3f} ms, "
+                    f"tiles {kt * 1e3:.3f} ms")
+                del out5
+            paths["short_lists_1M"][f"T{T5}"] = row
+        del rec5
+        del e5
         torch.cuda.empty_cache()
 
     if not args.no_ragged and not args.only:

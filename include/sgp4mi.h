@@ -59,7 +59,8 @@ enum {
   SGP4_E_PRECISION = -4, /* unknown precision */
   SGP4_E_HIP = -5,       /* HIP runtime or launch failure */
   SGP4_E_GRAVITY = -6,   /* gravity model rejected */
-  SGP4_E_PLAN = -7       /* plan does not match the call's buffers */
+  SGP4_E_PLAN = -7,      /* plan does not match the call's buffers */
+  SGP4_E_WORKSPACE = -8  /* workspace missing or too small */
 };
 
 /* Library version (integer, increases with ABI changes). */
@@ -99,13 +100,38 @@ int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, in
  *                           (workgroups of independent wavefronts); needs
  *                           SGP4_CFG_SCALAR_CONSTS and no SGP4_CFG_PERSISTENT
  *                           (else SGP4_E_ARG), and n * ceil(T / 64) < 2^32
- *                           (else SGP4_E_SIZE).
- * Codes are identical for every configuration and states agree to rounding
- * (the Kepler loop ends when all lanes of a wavefront have converged). */
-enum { SGP4_CFG_SCALAR_CONSTS = 0x10000, SGP4_CFG_PERSISTENT = 0x20000, SGP4_CFG_TILES = 0x40000 };
+ *                           (else SGP4_E_SIZE);
+ *   SGP4_CFG_FLAT           one lane per point in point order, whatever T, so
+ *                           short time lists leave no lane idle; each lane
+ *                           reads its satellite's constants (vector loads);
+ *                           excludes the three flags above (else SGP4_E_ARG)
+ *                           and needs ceil(n * T / block) < 2^31 (else
+ *                           SGP4_E_SIZE).
+ * The default is FLAT with 256-wide workgroups for T < 64, else TILES with
+ * scalar constants (256-wide for FP64, 512 for the float paths), else the
+ * satellite-by-time grid.  Codes are identical for every configuration and
+ * states agree to rounding (the Kepler loop ends when all lanes of a
+ * wavefront have converged). */
+enum { SGP4_CFG_SCALAR_CONSTS = 0x10000, SGP4_CFG_PERSISTENT = 0x20000, SGP4_CFG_TILES = 0x40000,
+       SGP4_CFG_FLAT = 0x80000 };
 #define SGP4_CFG_PER_CU(k) ((int)(k) << 20)
 int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                       uint8_t* err, int config, void* stream);
+
+/* Elements straight to states: initialisation and dense n x T propagation in
+ * one call, the pipeline jaxsgp4 traces as one function (sections 2.2 and
+ * 3.1).  Arguments as sgp4_init (grav, elem, sat_flags) and sgp4_propagate
+ * (t, precision, r, v, err).  For T <= 16, or when ws is NULL, one fused
+ * launch initialises each workgroup's 64 satellites into on-chip memory and
+ * propagates them (no record in device memory; ws untouched); for T > 16 with
+ * ws (device, at least sgp4_consts_bytes(n) bytes, else SGP4_E_WORKSPACE) it
+ * runs sgp4_init into ws and sgp4_propagate, and ws then holds the records.
+ * A fused launch covers T <= 524,280 (else SGP4_E_WORKSPACE when ws is NULL).
+ * Results equal the two-stage path's: codes identical, states to rounding.
+ * n = 0 or T = 0 writes nothing. */
+int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
+                            int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* Opaque ragged-propagation plan (host object owning device tile tables and
  * a captured HIP graph). */

@@ -167,6 +167,44 @@ class RaggedPlan:
             pass
 
 
+def propagate_elements(elem: torch.Tensor, t: torch.Tensor, precision="fp64", grav: Optional[Sequence[float]] = None,
+                       out=None, workspace: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None):
+    """Elements float64 [8, n] straight to r [3, n, T], v [3, n, T], err [n, T] in one
+    call (sgp4_propagate_elements): a fused initialise-and-propagate launch for
+    short time lists, initialisation into `workspace` (uint8, at least
+    consts_bytes(n) bytes) and the dense launch for longer ones when given.
+    flags: optional uint8 [n] tensor that receives the satellite flags."""
+    p = _prec(precision)
+    _need(elem, torch.float64, "elem")
+    if elem.dim() != 2 or elem.shape[0] != 8:
+        raise ValueError("elem must have shape [8, n]")
+    _need(t, torch.float64, "t", elem.device)
+    n, T = int(elem.shape[1]), int(t.numel())
+    if out is None:
+        dt = _out_dtype(p)
+        r = torch.empty((3, n, T), dtype=dt, device=elem.device)
+        v = torch.empty((3, n, T), dtype=dt, device=elem.device)
+        err = torch.empty((n, T), dtype=torch.uint8, device=elem.device)
+    else:
+        r, v, err = out
+    g = None
+    if grav is not None:
+        g = (ctypes.c_double * 5)(*[float(x) for x in grav])
+    ws_bytes = 0
+    if workspace is not None:
+        _need(workspace, torch.uint8, "workspace", elem.device)
+        ws_bytes = int(workspace.numel())
+    if flags is not None:
+        _need(flags, torch.uint8, "flags", elem.device)
+        if flags.numel() < n:
+            raise ValueError("flags must hold n entries")
+    with torch.cuda.device(elem.device):
+        _native.check(_native.lib().sgp4_propagate_elements(
+            g, n, _ptr(elem), _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err), _ptr(flags), _ptr(workspace), ws_bytes,
+            _stream(elem.device)), "sgp4_propagate_elements")
+    return r, v, err
+
+
 def propagate_ragged(rec: Record, offsets: torch.Tensor, t: torch.Tensor, precision="fp64",
                      plan: Optional[RaggedPlan] = None, out=None):
     """CSR lists: returns r [3, nnz], v [3, nnz], err [nnz]."""

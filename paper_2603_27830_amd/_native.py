@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsgp4mi.so")
 SGP4_FP64, SGP4_FP32, SGP4_FP32_MIXED = 0, 1, 2
 PLAN_AUTOTUNE, PLAN_GRAPH = 1, 2
 ERRORS = {0: "SGP4_OK", -1: "SGP4_E_ARG", -2: "SGP4_E_SIZE", -3: "SGP4_E_OFFSETS", -4: "SGP4_E_PRECISION",
-          -5: "SGP4_E_HIP", -6: "SGP4_E_GRAVITY", -7: "SGP4_E_PLAN"}
+          -5: "SGP4_E_HIP", -6: "SGP4_E_GRAVITY", -7: "SGP4_E_PLAN", -8: "SGP4_E_WORKSPACE"}
 
 # (name, restype, argtypes) for every symbol the public header declares.
 _vp, _i64, _int, _dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
@@ -25,6 +25,8 @@ SIGNATURES = [
     ("sgp4_init", _int, [_dp, _i64, _vp, _vp, _vp, _vp]),
     ("sgp4_propagate", _int, [_vp, _i64, _vp, _i64, _int, _vp, _vp, _vp, _vp]),
     ("sgp4_propagate_ex", _int, [_vp, _i64, _vp, _i64, _int, _vp, _vp, _vp, _int, _vp]),
+    ("sgp4_propagate_elements", _int, [_dp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                       _vp]),
     ("sgp4_propagate_ragged", _int, [_vp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp]),
     ("sgp4_plan_create", _int, [ctypes.POINTER(_vp), _vp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp,
                                 ctypes.c_uint, _vp]),

@@ -20,8 +20,12 @@ namespace sgp4mi {
 hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
                        hipStream_t s);
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, bool vec, unsigned grid, bool tiles, hipStream_t s);
+                        uint8_t* err, int block, bool vec, unsigned grid, bool tiles, bool flat, hipStream_t s);
 bool dense_tiles_fit(int64_t n, int64_t T);
+bool dense_flat_fits(int64_t n, int64_t T, int block);
+hipError_t launch_fused(int precision, const double g[5], int64_t n, const double* elem, const double* t, int64_t T,
+                        void* r, void* v, uint8_t* err, uint8_t* user_flags, hipStream_t s);
+int64_t fused_max_T();
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
@@ -37,12 +41,21 @@ namespace {
 
 constexpr double kWgs72[5] = {398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597};
 constexpr int64_t kMaxSats = 2147483647LL;
+// Time lists shorter than this take the flat dense mapping (one lane per
+// point in point order) instead of 64-time tiles, most of whose lanes would
+// be idle.
+constexpr int64_t kFlatBelowT = 64;
+// Elements-to-states calls with at most this many times run the fused
+// kernel (initialisation kept on chip); longer ones, given a record
+// workspace, run initialisation and the default dense launch.
+constexpr int64_t kFusedMaxT = 16;
 // Default dense launch: one wavefront per 64-time tile with the satellite's
 // constants in scalar registers, in 256-wide workgroups for FP64 and 512-wide
 // for the float paths (fastest of the mapping x workgroup x residency sweep on
 // MI355X at 9,341 x 1,000); the satellite-by-time grid where the tiles do not
 // fit 32-bit indices.
 int default_dense(int precision, int64_t n, int64_t T) {
+  if (T < kFlatBelowT && dense_flat_fits(n, T, 256)) return 256 | SGP4_CFG_FLAT;
   if (!dense_tiles_fit(n, T)) return 512 | SGP4_CFG_SCALAR_CONSTS;
   return (precision == SGP4_FP64 ? 256 : 512) | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_TILES;
 }
@@ -183,6 +196,7 @@ const char* sgp4_strerror(int code) {
     case SGP4_E_HIP: return "HIP runtime or launch failure";
     case SGP4_E_GRAVITY: return "gravity model rejected";
     case SGP4_E_PLAN: return "plan does not match the call";
+    case SGP4_E_WORKSPACE: return "workspace missing or too small";
   }
   return "unknown error code";
 }
@@ -205,28 +219,51 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
   const bool scalar = (config & SGP4_CFG_SCALAR_CONSTS) != 0;
   const bool persistent = (config & SGP4_CFG_PERSISTENT) != 0;
   const bool tiles = (config & SGP4_CFG_TILES) != 0;
+  const bool flat = (config & SGP4_CFG_FLAT) != 0;
   const int per_cu = (config >> 20) & 0xff;
-  if ((config & ~(0xfff | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | SGP4_CFG_TILES | (0xff << 20))) != 0)
+  if ((config & ~(0xfff | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | SGP4_CFG_TILES | SGP4_CFG_FLAT |
+                  (0xff << 20))) != 0)
     return SGP4_E_ARG;
   if (block != 64 && block != 128 && block != 256 && block != 512) return SGP4_E_ARG;
   if (persistent && per_cu == 0) return SGP4_E_ARG;
   if (tiles && (persistent || !scalar || per_cu != 0)) return SGP4_E_ARG;
+  if (flat && (persistent || tiles || scalar || per_cu != 0)) return SGP4_E_ARG;
   if (n == 0 || T == 0) return SGP4_OK;
   if (!consts || !t || !r || !v || !err) return SGP4_E_ARG;
   if (tiles && !dense_tiles_fit(n, T)) return SGP4_E_SIZE;
+  if (flat && !dense_flat_fits(n, T, block)) return SGP4_E_SIZE;
   unsigned grid = 0;
   if (persistent) {
     const int64_t tiles = n * ((T + 63) / 64);
     const int64_t need = (tiles + block / 64 - 1) / (block / 64);
     grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(compute_units()) * per_cu)));
   }
-  return hip_status(launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, grid, tiles,
+  return hip_status(launch_dense(precision, consts, n, t, T, r, v, err, block, !scalar, grid, tiles, flat,
                                 static_cast<hipStream_t>(stream)));
 }
 
 int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
                    uint8_t* err, void* stream) {
   return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, default_dense(precision, n, T), stream);
+}
+
+int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
+                            int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
+  if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
+  const double* g = grav ? grav : kWgs72;
+  if (int rc = check_gravity(g)) return rc;
+  if (ws && ws_bytes < sgp4_consts_bytes(n)) return SGP4_E_WORKSPACE;
+  if (n == 0 || T == 0) return SGP4_OK;
+  if (!elem || !t || !r || !v || !err) return SGP4_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (T <= kFusedMaxT || !ws) {
+    if (T > fused_max_T()) return SGP4_E_WORKSPACE;
+    return hip_status(launch_fused(precision, g, n, elem, t, T, r, v, err, sat_flags, s));
+  }
+  if (int rc = hip_status(launch_init(g, n, elem, ws, sat_flags, s))) return rc;
+  return sgp4_propagate(ws, n, t, T, precision, r, v, err, stream);
 }
 
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,

@@ -15,7 +15,13 @@ struct InitArgs {
   double mu, radius, j2, j3, j4;
 };
 
+// kStaged: the 64 records of the workgroup are assembled in LDS and copied
+// out as one contiguous run of 64 slots (each store instruction of the
+// wavefront writes 1 KiB of consecutive bytes), instead of each lane writing
+// its own 512-byte slot (each store instruction touching 64 cache lines).
+template <bool kStaged>
 __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
+  __shared__ Slot stage[kStaged ? 64 : 1];
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const double ke = 60.0 / sqrt(a.radius * a.radius * a.radius / a.mu);
   const double j3oj2 = (a.j3 == 0.0) ? 0.0 : a.j3 / a.j2;
@@ -38,33 +44,49 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     hf[2] = float(0.5 * a.j2);
     hf[3] = 0.0f;
   }
-  if (i >= a.n) return;
   const int64_t n = a.n;
-  double el[7];
+  const int64_t i0 = int64_t(blockIdx.x) * blockDim.x;
+  if (!kStaged && i >= n) return;
+  if (i < n) {
+    double el[7];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) el[k] = a.elem[k * n + i];
-  const double epoch = a.elem[7 * n + i];
-  GravIn gi{a.radius, a.j2, a.j4, ke, j3oj2};
-  double rec[kNRec];
-  uint32_t code;
-  bool isimp;
-  init_record<double>(gi, el, rec, &code, &isimp);
-  rec[kEpochMin] = 1440.0 * epoch;
-  Slot* slot = a.slots + i;
+    for (int k = 0; k < 7; ++k) el[k] = a.elem[k * n + i];
+    const double epoch = a.elem[7 * n + i];
+    GravIn gi{a.radius, a.j2, a.j4, ke, j3oj2};
+    double rec[kNRec];
+    uint32_t code;
+    bool isimp;
+    init_record<double>(gi, el, rec, &code, &isimp);
+    rec[kEpochMin] = 1440.0 * epoch;
+    Slot* slot = kStaged ? &stage[threadIdx.x] : a.slots + i;
 #pragma unroll
-  for (int k = 0; k < kNRec; ++k) {
-    slot->d[k] = rec[k];
-    slot->f[k] = float(rec[k]);
+    for (int k = 0; k < kNRec; ++k) {
+      slot->d[k] = rec[k];
+      slot->f[k] = float(rec[k]);
+    }
+    slot->info = code | (isimp ? kInfoIsimp : 0u);
+    if (a.user_flags) {
+      uint8_t f = 0;
+      if (code == 7) f |= 1;
+      if (isimp) f |= 2;
+      if (code == 1 || code == 2) f |= 4;
+      a.user_flags[i] = f;
+    }
   }
-  slot->info = code | (isimp ? kInfoIsimp : 0u);
-  if (a.user_flags) {
-    uint8_t f = 0;
-    if (code == 7) f |= 1;
-    if (isimp) f |= 2;
-    if (code == 1 || code == 2) f |= 4;
-    a.user_flags[i] = f;
+  if (kStaged) {
+    __syncthreads();
+    // Copy the workgroup's valid slots (whole 16-byte chunks) to device memory.
+    const int64_t valid = n - i0 < 64 ? n - i0 : 64;
+    const int chunks = int(valid) * (kSlotBytes / 16);
+    const uint4* src = reinterpret_cast<const uint4*>(stage);
+    uint4* dst = reinterpret_cast<uint4*>(a.slots + i0);
+    for (int c = threadIdx.x; c < chunks; c += 64) dst[c] = src[c];
   }
 }
+
+// Catalogues from this size on take the staged kernel (its copy-out adds
+// latency that a few hundred workgroups do not hide).
+constexpr int64_t kInitStagedFrom = 65536;
 
 hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
                        hipStream_t s) {
@@ -78,7 +100,10 @@ hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* c
   a.user_flags = user_flags;
   a.mu = g[0]; a.radius = g[1]; a.j2 = g[2]; a.j3 = g[3]; a.j4 = g[4];
   const int64_t blocks = (n + 63) / 64;  // 64-wide: a short kernel spread over more compute units
-  hipLaunchKernelGGL(init_kernel, dim3(unsigned(blocks > 0 ? blocks : 1)), dim3(64), 0, s, a);
+  if (n >= kInitStagedFrom)
+    hipLaunchKernelGGL(init_kernel<true>, dim3(unsigned(blocks)), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(init_kernel<false>, dim3(unsigned(blocks > 0 ? blocks : 1)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -11,54 +11,9 @@
 //              by a short forward scan of the offsets (constants per lane).
 // Outputs are component-major SoA, r[c * P + p], written with non-temporal
 // stores; codes 1, 2, 4 and 7 write NaN states.
-#include "sgp4mi_point.h"
+#include "sgp4mi_out.h"
 
 namespace sgp4mi {
-
-// Output writer: six component arrays and the code array.  With kOff32 the
-// per-lane offset is a 32-bit byte offset from uniform base pointers (valid
-// when each component array is below 4 GiB), so each store takes its base
-// from scalar registers and no 64-bit address arithmetic per store.
-template <class TP, bool kOff32>
-struct Out {
-  TP* r;
-  TP* v;
-  uint8_t* err;
-  int64_t P;
-  __device__ __forceinline__ void put(int64_t p, uint32_t code, const PointState<TP>& s) const {
-    // Codes 1, 2, 4 and 7 carry no state: such lanes (rare, and usually whole
-    // satellites) take their own store path instead of a select per component.
-    if (code != 0 && code != 6) {
-      const TP q = TP(__builtin_nan(""));
-      store(p, code, q, q, q, q, q, q);
-    } else {
-      store(p, code, s.r[0], s.r[1], s.r[2], s.v[0], s.v[1], s.v[2]);
-    }
-  }
-  __device__ __forceinline__ void store(int64_t p, uint32_t code, TP x0, TP x1, TP x2, TP y0, TP y1, TP y2) const {
-    if (kOff32) {
-      const uint32_t off = uint32_t(p) * uint32_t(sizeof(TP));
-      char* rb = reinterpret_cast<char*>(r);
-      char* vb = reinterpret_cast<char*>(v);
-      const size_t stride = size_t(P) * sizeof(TP);
-      st_nt(reinterpret_cast<TP*>(rb + off), x0);
-      st_nt(reinterpret_cast<TP*>(rb + stride + off), x1);
-      st_nt(reinterpret_cast<TP*>(rb + 2 * stride + off), x2);
-      st_nt(reinterpret_cast<TP*>(vb + off), y0);
-      st_nt(reinterpret_cast<TP*>(vb + stride + off), y1);
-      st_nt(reinterpret_cast<TP*>(vb + 2 * stride + off), y2);
-      st_nt(err + uint32_t(p), uint8_t(code));
-    } else {
-      st_nt(r + p, x0);
-      st_nt(r + P + p, x1);
-      st_nt(r + 2 * P + p, x2);
-      st_nt(v + p, y0);
-      st_nt(v + P + p, y1);
-      st_nt(v + 2 * P + p, y2);
-      st_nt(err + p, uint8_t(code));
-    }
-  }
-};
 
 // ------------------------------------------------------------------ dense --
 // Grid (n, ceil(T / kBlock)): one point per lane.  When T needs more than
@@ -104,6 +59,30 @@ __global__ void __launch_bounds__(kBlock) dense_tile_kernel(RecordView rv, const
   PointState<TP> s;
   const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
   out.put(int64_t(sat) * T + j, code, s);
+}
+
+// Flat variant for short time lists: lane p -> satellite p / T, time p % T,
+// so every lane of a wavefront has a point however short the list; each lane
+// reads its satellite's constants with vector loads.
+template <class TS, class TP, int kBlock, bool kOff32>
+__global__ void __launch_bounds__(kBlock) dense_flat_kernel(RecordView rv, const double* __restrict__ t, int64_t T,
+                                                            Out<TP, kOff32> out) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= out.P) return;
+  int64_t i, j;
+  if (kOff32) {  // P < 2^32: 32-bit division
+    const uint32_t i32 = uint32_t(p) / uint32_t(T);
+    i = i32;
+    j = int64_t(uint32_t(p) - i32 * uint32_t(T));
+  } else {
+    i = p / T;
+    j = p - i * T;
+  }
+  const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, i);
+  const Grav g = load_grav(rv);
+  PointState<TP> s;
+  const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+  out.put(p, code, s);
 }
 
 // Persistent variant: a fixed grid; each wavefront walks tiles of 64 times of
@@ -344,6 +323,39 @@ static hipError_t tile_t(const RecordView& rv, int64_t n, const double* t, int64
   return hipGetLastError();
 }
 
+template <class TS, class TP, int kBlock>
+static void flat_go(hipStream_t s, const RecordView& rv, const double* t, int64_t T, int64_t n, void* r, void* v,
+                    uint8_t* err) {
+  const int64_t P = n * T;
+  const unsigned grid = unsigned((P + kBlock - 1) / kBlock);
+  if (fits32<TP>(P)) {
+    Out<TP, true> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+    hipLaunchKernelGGL((dense_flat_kernel<TS, TP, kBlock, true>), dim3(grid), dim3(kBlock), 0, s, rv, t, T, o);
+  } else {
+    Out<TP, false> o{static_cast<TP*>(r), static_cast<TP*>(v), err, P};
+    hipLaunchKernelGGL((dense_flat_kernel<TS, TP, kBlock, false>), dim3(grid), dim3(kBlock), 0, s, rv, t, T, o);
+  }
+}
+
+template <class TS, class TP>
+static hipError_t flat_t(const RecordView& rv, int64_t n, const double* t, int64_t T, void* r, void* v, uint8_t* err,
+                         int block, hipStream_t s) {
+  switch (block) {
+    case 64: flat_go<TS, TP, 64>(s, rv, t, T, n, r, v, err); break;
+    case 128: flat_go<TS, TP, 128>(s, rv, t, T, n, r, v, err); break;
+    case 256: flat_go<TS, TP, 256>(s, rv, t, T, n, r, v, err); break;
+    case 512: flat_go<TS, TP, 512>(s, rv, t, T, n, r, v, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Whether the flat dense grid (one lane per point, ceil(n T / block)
+// workgroups) fits the launch limit of 2^31 - 1 workgroups.
+bool dense_flat_fits(int64_t n, int64_t T, int block) {
+  return n * T <= int64_t(0x7fffffff) * block;
+}
+
 // Number of 64-time tiles of an n x T batch, and whether the tile kernel can
 // index them (32-bit tile indices).
 bool dense_tiles_fit(int64_t n, int64_t T) {
@@ -354,10 +366,19 @@ bool dense_tiles_fit(int64_t n, int64_t T) {
 // block: workgroup size; vec: constants through vector loads (else scalar);
 // grid > 0 selects the persistent kernel with that many workgroups; tiles
 // selects one wavefront per 64-time tile (scalar constants; the caller checks
-// dense_tiles_fit).
+// dense_tiles_fit); flat one lane per point in point order (vector constants;
+// the caller checks dense_flat_fits).
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
-                        uint8_t* err, int block, bool vec, unsigned grid, bool tiles, hipStream_t s) {
+                        uint8_t* err, int block, bool vec, unsigned grid, bool tiles, bool flat, hipStream_t s) {
   const RecordView rv = view_of(consts, n);
+  if (flat) {
+    switch (precision) {
+      case 0: return flat_t<double, double>(rv, n, t, T, r, v, err, block, s);
+      case 1: return flat_t<float, float>(rv, n, t, T, r, v, err, block, s);
+      case 2: return flat_t<double, float>(rv, n, t, T, r, v, err, block, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (tiles) {
     switch (precision) {
       case 0: return tile_t<double, double>(rv, n, t, T, r, v, err, block, s);

@@ -61,7 +61,7 @@ def test_argument_errors_need_no_gpu():
     assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x40000, None) == E["SGP4_E_ARG"]
     assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x10000 | 0x40000 | 0x20000 | (4 << 20),
                                None) == E["SGP4_E_ARG"]
-    assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x80000, None) == E["SGP4_E_ARG"]
+    assert L.sgp4_propagate_ex(fake, 10, fake, 10, 0, fake, fake, fake, 256 | 0x8000, None) == E["SGP4_E_ARG"]
     # more 64-time tiles than 32-bit tile indices address
     assert L.sgp4_propagate_ex(fake, 2**31 - 1, fake, 64 * 4, 0, fake, fake, fake, 256 | 0x10000 | 0x40000,
                                None) == E["SGP4_E_SIZE"]
@@ -99,3 +99,32 @@ def test_product_package_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f
+
+
+def test_elements_to_states_and_flat_config_reject_bad_arguments():
+    """sgp4_propagate_elements and the flat dense flag: errors before any launch."""
+    L = _native.lib()
+    E = {v: k for k, v in _native.ERRORS.items()}
+    fake = ctypes.c_void_p(0x1000)
+    pe = L.sgp4_propagate_elements
+    assert pe(None, 10, fake, fake, 5, 3, fake, fake, fake, None, None, 0, None) == E["SGP4_E_PRECISION"]
+    assert pe(None, -1, fake, fake, 5, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_SIZE"]
+    assert pe(None, 10, fake, fake, -5, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_SIZE"]
+    assert pe(None, 2**40, fake, fake, 2**30, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_SIZE"]
+    assert pe(None, 10, None, fake, 5, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_ARG"]
+    assert pe(None, 10, fake, fake, 5, 0, None, fake, fake, None, None, 0, None) == E["SGP4_E_ARG"]
+    small = L.sgp4_consts_bytes(10) - 1
+    assert pe(None, 10, fake, fake, 5, 0, fake, fake, fake, None, fake, small, None) == E["SGP4_E_WORKSPACE"]
+    # a fused launch covers ceil(T / 8) <= 65535 workgroups in y; beyond that a workspace is required
+    assert pe(None, 10, fake, fake, 65535 * 8 + 1, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_WORKSPACE"]
+    bad = (ctypes.c_double * 5)(398600.8, -1.0, 0.0, 0.0, 0.0)
+    assert pe(bad, 10, fake, fake, 5, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_GRAVITY"]
+    # empty batches launch nothing and succeed, even with null buffers
+    assert pe(None, 0, None, None, 5, 0, None, None, None, None, None, 0, None) == 0
+    assert pe(None, 10, None, None, 0, 0, None, None, None, None, None, 0, None) == 0
+    assert L.sgp4_strerror(E["SGP4_E_WORKSPACE"]).decode().startswith("workspace")
+    px = L.sgp4_propagate_ex
+    FLAT = 0x80000
+    for cfg in (256 | FLAT | 0x10000, 256 | FLAT | 0x40000 | 0x10000, 256 | FLAT | 0x20000 | (2 << 20), 96 | FLAT):
+        assert px(fake, 10, fake, 10, 0, fake, fake, fake, cfg, None) == E["SGP4_E_ARG"], hex(cfg)
+    assert px(fake, 2**31 - 1, fake, 2**9, 0, fake, fake, fake, 64 | FLAT, None) == E["SGP4_E_SIZE"]
