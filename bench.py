@@ -430,6 +430,21 @@ def main():
         del e5
         torch.cuda.empty_cache()
 
+    if not args.no_short and not args.only:
+        # Ingestion: 200,000 synthetic two-line element sets (3LE, 32 MB of
+        # text) parsed on the host by the library's native parser.
+        from synth import text as stx
+        el6 = synth.shell_elements(200_000, 6)
+        txt = stx.tle_text(el6, three_line=True).encode()
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            sg.parse_text(txt, "tle", ref_jd=stx.REF_JD, threads=16)
+            best = min(best, time.perf_counter() - t0)
+        paths["ingest_tle_200k"] = {"parse_ms": best * 1e3, "records_per_s": 200_000 / best, "threads": 16,
+                                    "text_mb": len(txt) / 1e6}
+        log(f"[bench] parse 200k TLE ({len(txt) / 1e6:.0f} MB): {best * 1e3:.1f} ms, {200_000 / best:.3e} rec/s")
+
     if not args.no_ragged and not args.only:
         c3 = synth.config3()
         rec3 = sg.init(torch.from_numpy(c3.elem).to(dev))

@@ -133,6 +133,46 @@ int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, c
                             int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- ingestion --
+ * Element-set text to the elements sgp4_init takes, on the host.  Formats:
+ *   SGP4_TEXT_TLE       two-line element sets, optionally with a name line
+ *                       before each pair (3LE); a record is a line "1 ..."
+ *                       of at least 69 columns followed by a line "2 ...";
+ *   SGP4_TEXT_OMM_KVN   CCSDS Orbit Mean-elements Messages, "KEY = value"
+ *                       lines; a record starts at CCSDS_OMM_VERS or where a
+ *                       key repeats;
+ *   SGP4_TEXT_OMM_CSV   a header line of OMM keywords, one record per line;
+ *   SGP4_TEXT_OMM_JSON  an array of flat objects keyed by OMM keywords.
+ * OMM records need EPOCH, MEAN_MOTION, ECCENTRICITY, INCLINATION,
+ * RA_OF_ASC_NODE, ARG_OF_PERICENTER, MEAN_ANOMALY and BSTAR (NORAD_CAT_ID
+ * optional).  Units in: rev/day, degrees, 1/earth radii; out: rad/min, rad
+ * (mean motion divided by 1440 / 2 pi, angles times pi / 180).
+ * The epoch row (row 7) is days after the reference ref_jd = {whole, frac}
+ * (host, a two-part Julian date; NULL = J2000.0, {2451545.0, 0.0}), computed
+ * as (JD0 - ref[0]) + (f - ref[1]) with JD0 the Julian date at 0h of the
+ * epoch's day and f its day fraction from the text's digits, so the epoch
+ * keeps the text's resolution (1e-8 day for TLE, 1 ns for OMM); section 4 of
+ * the paper traces precision loss to a 32-bit Julian-date epoch. */
+enum { SGP4_TEXT_TLE = 1, SGP4_TEXT_OMM_KVN = 2, SGP4_TEXT_OMM_CSV = 3, SGP4_TEXT_OMM_JSON = 4 };
+/* Per-record status bits: checksum of a TLE line wrong or missing; the two
+ * TLE lines carry different catalogue numbers; a field missing or not a
+ * number (that record's elements are written as NaN: do not initialise it). */
+enum { SGP4_REC_CHECKSUM = 1, SGP4_REC_MISMATCH = 2, SGP4_REC_FIELD = 4 };
+
+/* Number of records in text[0, len) (host memory).  SGP4_E_ARG for an unknown
+ * format, a null n_out, or JSON that is not an array of flat objects. */
+int sgp4_text_count(const char* text, size_t len, int format, int64_t* n_out);
+
+/* Parse the n records of the text (n must equal sgp4_text_count's result,
+ * else SGP4_E_SIZE).  elem: host float64 [8][n], rows as for sgp4_init.
+ * satnum: host int64 [n] or NULL (catalogue number, alpha-5 TLE numbers
+ * decoded; -1 when absent).  status: host int32 [n] or NULL (SGP4_REC_*
+ * bits).  threads: worker threads for TLE text (0 = one per hardware thread,
+ * at most 64; texts under ~1 MB use one).  Record order is text order.  Never
+ * touches the GPU. */
+int sgp4_text_parse(const char* text, size_t len, int format, int64_t n, const double* ref_jd, double* elem,
+                    int64_t* satnum, int32_t* status, int threads);
+
 /* Opaque ragged-propagation plan (host object owning device tile tables and
  * a captured HIP graph). */
 typedef struct sgp4_plan sgp4_plan;

@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _native
-from ._native import SGP4Error, PLAN_AUTOTUNE, PLAN_GRAPH
+from ._native import SGP4Error, PLAN_AUTOTUNE, PLAN_GRAPH, REC_CHECKSUM, REC_MISMATCH, REC_FIELD
 
 __all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "SGP4Function", "PRECISIONS",
            "SGP4Error", "consts_bytes"]
@@ -203,6 +203,31 @@ def propagate_elements(elem: torch.Tensor, t: torch.Tensor, precision="fp64", gr
             g, n, _ptr(elem), _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err), _ptr(flags), _ptr(workspace), ws_bytes,
             _stream(elem.device)), "sgp4_propagate_elements")
     return r, v, err
+
+
+def parse_text(text, fmt="tle", ref_jd=None, threads=0):
+    """Element-set text (str or bytes; fmt "tle", "omm_kvn", "omm_csv" or
+    "omm_json") to host numpy arrays: elem float64 [8, n] (rows as for init,
+    epoch in days after ref_jd = (whole, frac), default J2000.0), satnum int64
+    [n] and status int32 [n] (REC_* bits; elements NaN where REC_FIELD is set).
+    Parsed by the library's native parser (sgp4_text_count / sgp4_text_parse)."""
+    import numpy as np
+    if fmt not in _native.TEXT_FORMATS:
+        raise ValueError(f"unknown text format {fmt!r}")
+    f = _native.TEXT_FORMATS[fmt]
+    data = text.encode() if isinstance(text, str) else bytes(text)
+    L = _native.lib()
+    n = ctypes.c_int64(0)
+    _native.check(L.sgp4_text_count(data, len(data), f, ctypes.byref(n)), "sgp4_text_count")
+    n = int(n.value)
+    elem = np.empty((8, n), dtype=np.float64)
+    satnum = np.empty(n, dtype=np.int64)
+    status = np.empty(n, dtype=np.int32)
+    ref = None if ref_jd is None else (ctypes.c_double * 2)(float(ref_jd[0]), float(ref_jd[1]))
+    _native.check(L.sgp4_text_parse(data, len(data), f, n, ref, ctypes.c_void_p(elem.ctypes.data),
+                                    ctypes.c_void_p(satnum.ctypes.data), ctypes.c_void_p(status.ctypes.data),
+                                    int(threads)), "sgp4_text_parse")
+    return elem, satnum, status
 
 
 def propagate_ragged(rec: Record, offsets: torch.Tensor, t: torch.Tensor, precision="fp64",

@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, "libsgp4mi.so")
 
 SGP4_FP64, SGP4_FP32, SGP4_FP32_MIXED = 0, 1, 2
 PLAN_AUTOTUNE, PLAN_GRAPH = 1, 2
+TEXT_FORMATS = {"tle": 1, "omm_kvn": 2, "omm_csv": 3, "omm_json": 4}
+REC_CHECKSUM, REC_MISMATCH, REC_FIELD = 1, 2, 4
 ERRORS = {0: "SGP4_OK", -1: "SGP4_E_ARG", -2: "SGP4_E_SIZE", -3: "SGP4_E_OFFSETS", -4: "SGP4_E_PRECISION",
           -5: "SGP4_E_HIP", -6: "SGP4_E_GRAVITY", -7: "SGP4_E_PLAN", -8: "SGP4_E_WORKSPACE"}
 
@@ -27,6 +29,8 @@ SIGNATURES = [
     ("sgp4_propagate_ex", _int, [_vp, _i64, _vp, _i64, _int, _vp, _vp, _vp, _int, _vp]),
     ("sgp4_propagate_elements", _int, [_dp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                        _vp]),
+    ("sgp4_text_count", _int, [ctypes.c_char_p, ctypes.c_size_t, _int, ctypes.POINTER(_i64)]),
+    ("sgp4_text_parse", _int, [ctypes.c_char_p, ctypes.c_size_t, _int, _i64, _dp, _vp, _vp, _vp, _int]),
     ("sgp4_propagate_ragged", _int, [_vp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp]),
     ("sgp4_plan_create", _int, [ctypes.POINTER(_vp), _vp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp,
                                 ctypes.c_uint, _vp]),

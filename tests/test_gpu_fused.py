@@ -167,3 +167,22 @@ def test_flat_dense_mapping(n, T, block):
     rt, vt, et, _ = two_stage(elem, t, "mixed", block=512 | 0x10000 | 0x40000)
     assert np.array_equal(em, et)
     assert close(rm, rt, TOL["mixed"][0]) and close(vm, vt, TOL["mixed"][1])
+
+
+@pytest.mark.parametrize("fmt", ["tle", "omm_kvn"])
+def test_text_to_states_pipeline(fmt):
+    """Element-set text -> native parser -> elements on the device ->
+    sgp4_propagate_elements, against the oracle propagating the oracle
+    parser's elements of the same text (FP64 bar)."""
+    from oracle import ingest as oi
+    from synth import text as stx
+    elem = synth.shell_elements(700, 61)
+    text = stx.tle_text(elem, three_line=True) if fmt == "tle" else stx.omm_kvn(elem)
+    say(f"[gpu] text -> states {fmt} n=700")
+    e, _, status = sg.parse_text(text, fmt, ref_jd=stx.REF_JD)
+    assert np.all(status == 0)
+    t = np.linspace(-720.0, 2880.0, 9)
+    r, v, err = fused(e, t, "fp64", ws=False)
+    eo = oi.parse_tle(text, ref=stx.REF_JD)[0] if fmt == "tle" else oi.parse_omm(text, "kvn", ref=stx.REF_JD)[0]
+    ro, vo, co = oracle.propagate(eo, t)
+    check_fp64(r, v, err, ro, vo, co)
