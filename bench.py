@@ -43,7 +43,7 @@ def log(msg):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dense_9341x1000_hbm_traffic.md")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "dense_9341x1000_instruction_mix.md")
-KERNEL_SOURCES = ("sgp4mi_common.h", "sgp4mi_math.h", "sgp4mi_point.h", "sgp4mi_prop.hip")
+KERNEL_SOURCES = ("sgp4mi_common.h", "sgp4mi_math.h", "sgp4mi_point.h", "sgp4mi_out.h", "sgp4mi_prop.hip")
 
 
 def profile_values(path):
@@ -88,14 +88,19 @@ def executed_flop_per_point(path_name):
 
 
 class LaunchTimer:
-    """HIP events recorded on the launch stream around one kernel launch of each
-    timed step; mean() is that launch's average duration over the timed region."""
+    """HIP events recorded on the launch stream around one kernel launch of every
+    `every`-th timed step; mean() is that launch's average duration over the
+    sampled steps of the timed region.  Sampling keeps the event packets from
+    stretching every step (events around every launch add ~3 us per step)."""
 
-    def __init__(self, torch):
-        self.torch, self.on, self.pairs = torch, False, []
+    def __init__(self, torch, every=5):
+        self.torch, self.on, self.pairs, self.every, self.count = torch, False, [], every, 0
 
     def __call__(self, launch):
         if not self.on:
+            return launch()
+        self.count += 1
+        if (self.count - 1) % self.every:
             return launch()
         s = self.torch.cuda.current_stream()
         a, b = self.torch.cuda.Event(enable_timing=True), self.torch.cuda.Event(enable_timing=True)
@@ -236,8 +241,8 @@ def calibrate(torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-c2", action="store_true", help="skip the 100k x 1440 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ragged", action="store_true", help="skip the 1M-satellite ragged catalogue")
