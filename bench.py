@@ -401,6 +401,35 @@ def main():
         del jac
         torch.cuda.empty_cache()
 
+    if not args.no_vjp and not args.only:
+        # Conjunction screening of the 9,341 x 1,000 mixed output (float positions,
+        # codes given), D = 10 km: one workgroup per sample time.
+        import ctypes
+        from paper_2603_27830_amd import _native
+        rec = sg.init(elem)
+        r_s, _, e_s = sg.propagate(rec, t, "mixed")
+        cap = 1 << 20
+        pairs = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        dist = torch.empty(cap, dtype=torch.float64, device=dev)
+        cnt = torch.empty(1, dtype=torch.int64, device=dev)
+        wsb = int(_native.lib().sgp4_screen_workspace_bytes(cat.n, cat.T))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        vp = lambda x: ctypes.c_void_p(x.data_ptr())  # noqa: E731
+
+        def screen_launch():
+            _native.check(_native.lib().sgp4_screen(
+                vp(r_s), _native.SGP4_FP32_MIXED, vp(e_s), cat.n, cat.T, 10.0, cap, vp(pairs), vp(dist), vp(cnt),
+                vp(ws), wsb, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "sgp4_screen")
+
+        ks = kernel_time(screen_launch, torch, reps=10)
+        events = int(cnt.item())
+        paths["screen_9341x1000"] = {"dist_km": 10.0, "events": events, "ms": ks * 1e3,
+                                     "satellite_times_per_s": P / ks,
+                                     "pairs_per_s_brute_force_equivalent": cat.n * (cat.n - 1) / 2 * cat.T / ks}
+        log(f"[bench] screen 9341 x 1000 (10 km): {ks * 1e3:.3f} ms, {events} events")
+        del r_s, e_s, pairs, dist, ws
+        torch.cuda.empty_cache()
+
     if not args.no_short and not args.only:
         # Short time lists over the 1M-satellite catalogue's elements: the fused
         # elements-to-states launch against the two-stage path's parts (init;

@@ -133,6 +133,35 @@ int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, c
                             int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- screening --
+ * Conjunction screening of a dense propagation output (the catalogue-wide use
+ * the paper motivates batching with, sections 1 and 6; the paper defines no
+ * screening algorithm, so this is the definition): at every sample time k,
+ * every pair of satellites i < j whose points are both valid and whose
+ * distance is below dist_km is an event (i, j, k, d), where
+ *   d^2 = (dx*dx + dy*dy) + dz*dz,  dx = x_j - x_i, ... formed in double from
+ * the stored positions (no fused multiply-add), d = sqrt(d^2), and the test is
+ * d^2 < dist_km * dist_km (in double).  A point is valid when its three
+ * position components are finite and, when err is given, its code is 0 or 6.
+ *   r: device [3][n*T], double for SGP4_FP64 else float, laid out as
+ *      sgp4_propagate writes it (r[c * n*T + i*T + k]);
+ *   err: device uint8 [n*T] or NULL;
+ *   pairs: device int32 [capacity][3] (i, j, k), dist: device double
+ *      [capacity] (km); events land in unspecified order;
+ *   count: device int64, set to the number of events found (which may exceed
+ *      capacity: only the first `capacity` found are written).
+ *   ws: device scratch of at least sgp4_screen_workspace_bytes(n, T) bytes
+ *      (8 n T: float x, y per point, time-major), else SGP4_E_WORKSPACE
+ *      (not needed when n < 2 or T = 0); its contents are not kept.
+ * Enqueues a clear of count, a packing pass into ws and one screening launch
+ * (one workgroup per sample time).  0 <= n <= 12288 (each time's points are
+ * bucket-sorted in on-chip memory, else SGP4_E_SIZE); dist_km finite and > 0
+ * (else SGP4_E_ARG). */
+size_t sgp4_screen_workspace_bytes(int64_t n, int64_t T);
+int sgp4_screen(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
+                int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
+                void* stream);
+
 /* ---------------------------------------------------------------- ingestion --
  * Element-set text to the elements sgp4_init takes, on the host.  Formats:
  *   SGP4_TEXT_TLE       two-line element sets, optionally with a name line

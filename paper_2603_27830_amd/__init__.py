@@ -205,6 +205,35 @@ def propagate_elements(elem: torch.Tensor, t: torch.Tensor, precision="fp64", gr
     return r, v, err
 
 
+def screen(r: torch.Tensor, dist_km: float, err: Optional[torch.Tensor] = None, capacity: int = 1 << 20):
+    """Conjunction screening of a dense output r [3, n, T] (float64 or float32,
+    device): every pair i < j closer than dist_km at a common time index
+    (sgp4_screen).  Returns (pairs int32 [m, 3] of (i, j, k), dist float64 [m]
+    km, total) with m = min(total, capacity); event order is unspecified."""
+    if r.dim() != 3 or r.shape[0] != 3:
+        raise ValueError("r must have shape [3, n, T]")
+    if r.dtype not in (torch.float64, torch.float32):
+        raise TypeError("r must be float64 or float32")
+    _need(r, r.dtype, "r")
+    n, T = int(r.shape[1]), int(r.shape[2])
+    if err is not None:
+        _need(err, torch.uint8, "err", r.device)
+    cap = int(capacity)
+    pairs = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=r.device)
+    dist = torch.empty(max(cap, 1), dtype=torch.float64, device=r.device)
+    count = torch.empty(1, dtype=torch.int64, device=r.device)
+    L = _native.lib()
+    wsb = int(L.sgp4_screen_workspace_bytes(n, T))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=r.device)
+    prec = _native.SGP4_FP64 if r.dtype == torch.float64 else _native.SGP4_FP32
+    with torch.cuda.device(r.device):
+        _native.check(L.sgp4_screen(_ptr(r), prec, _ptr(err), n, T, float(dist_km), cap, _ptr(pairs), _ptr(dist),
+                                    _ptr(count), _ptr(ws), wsb, _stream(r.device)), "sgp4_screen")
+    total = int(count.item())
+    m = min(total, cap)
+    return pairs[:m], dist[:m], total
+
+
 def parse_text(text, fmt="tle", ref_jd=None, threads=0):
     """Element-set text (str or bytes; fmt "tle", "omm_kvn", "omm_csv" or
     "omm_json") to host numpy arrays: elem float64 [8, n] (rows as for init,
