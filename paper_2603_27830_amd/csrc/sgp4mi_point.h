@@ -158,7 +158,8 @@ struct PointState {
 // codes 0 and 6 only.
 //
 // Reformulations relative to the textbook order, each an identity up to
-// rounding: sin M from sin/cos of the drag-free M by a small rotation; the
+// rounding: sin M from sin/cos of the drag-free M by a small rotation (FP64;
+// the float paths take the hardware sine of M); the
 // Kepler iteration carries psi - U and rotates (sin psi, cos psi) by each
 // Newton step; the argument of latitude u never leaves its (sin, cos) pair
 // (no atan2: the short-period correction is a rotation of the normalised
@@ -192,8 +193,9 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
     argp = argpdf - dMa;
     const TS t3 = t2 * t, t4 = t3 * t;
     A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
-    if (vabs(dMa) <= TS(kRotMax)) rotate_small(&sM, &cM, TP(dMa));
-    else TR::sc_damped(M, &sM, &cM);
+    // Float paths: one hardware sine of M costs less than the rotation.
+    if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
+    else rotate_small(&sM, &cM, TP(dMa));
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
     Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
   }
