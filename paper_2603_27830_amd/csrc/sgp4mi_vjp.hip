@@ -54,8 +54,9 @@ __device__ __forceinline__ uint32_t point_vjp(const SatC<TS, TP>& c, const Grav&
     A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
     sM = sMdf;
     cM = cMdf;
-    if (vabs(dMa) <= TS(kRotMax)) rotate_small(&sM, &cM, TP(dMa));
-    else TR::sc_damped(M, &sM, &cM);
+    // As the forward kernel: float paths take the hardware sine and cosine of M.
+    if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
+    else rotate_small(&sM, &cM, TP(dMa));
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
     Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
   }
