@@ -60,7 +60,8 @@ enum {
   SGP4_E_HIP = -5,       /* HIP runtime or launch failure */
   SGP4_E_GRAVITY = -6,   /* gravity model rejected */
   SGP4_E_PLAN = -7,      /* plan does not match the call's buffers */
-  SGP4_E_WORKSPACE = -8  /* workspace missing or too small */
+  SGP4_E_WORKSPACE = -8, /* workspace missing or too small */
+  SGP4_E_HOST = -9       /* host memory or threads could not be obtained */
 };
 
 /* Library version (integer, increases with ABI changes). */

@@ -16,7 +16,8 @@ PLAN_AUTOTUNE, PLAN_GRAPH = 1, 2
 TEXT_FORMATS = {"tle": 1, "omm_kvn": 2, "omm_csv": 3, "omm_json": 4}
 REC_CHECKSUM, REC_MISMATCH, REC_FIELD = 1, 2, 4
 ERRORS = {0: "SGP4_OK", -1: "SGP4_E_ARG", -2: "SGP4_E_SIZE", -3: "SGP4_E_OFFSETS", -4: "SGP4_E_PRECISION",
-          -5: "SGP4_E_HIP", -6: "SGP4_E_GRAVITY", -7: "SGP4_E_PLAN", -8: "SGP4_E_WORKSPACE"}
+          -5: "SGP4_E_HIP", -6: "SGP4_E_GRAVITY", -7: "SGP4_E_PLAN", -8: "SGP4_E_WORKSPACE",
+          -9: "SGP4_E_HOST"}
 
 # (name, restype, argtypes) for every symbol the public header declares.
 _vp, _i64, _int, _dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)

@@ -201,6 +201,7 @@ const char* sgp4_strerror(int code) {
     case SGP4_E_GRAVITY: return "gravity model rejected";
     case SGP4_E_PLAN: return "plan does not match the call";
     case SGP4_E_WORKSPACE: return "workspace missing or too small";
+    case SGP4_E_HOST: return "host resources exhausted (memory or threads)";
   }
   return "unknown error code";
 }
@@ -332,7 +333,13 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
   for (int64_t i = 0; i < n; ++i)
     if (off[size_t(i) + 1] < off[size_t(i)]) return SGP4_E_OFFSETS;
 
-  sgp4_plan* p = new sgp4_plan;
+  // Owned until it is handed out: every early return (and a host allocation
+  // failure in the tables below) frees the plan and its device memory.
+  struct Owner {
+    sgp4_plan* p;
+    ~Owner() { plan_free(p); }
+  } own{new sgp4_plan};
+  sgp4_plan* p = own.p;
   p->precision = precision; p->consts = consts; p->n = n; p->nnz = nnz; p->offsets = offsets; p->t = t;
   p->r = r; p->v = v; p->err = err;
 
@@ -369,7 +376,7 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
             hipMemcpyAsync(p->chunk_sat, csat.data(), csat.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
-  if (!ok) { plan_free(p); return SGP4_E_HIP; }
+  if (!ok) return SGP4_E_HIP;
 
   const int cus = compute_units();
   auto grid_for = [&](int mode, int block, int per_cu) {
@@ -406,8 +413,11 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
       p->grid = std::min(g, grid_for(m, b, 1 << 30));
       p->from_cache = true;
     } else {
-      hipEvent_t e0, e1;
-      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { plan_free(p); return SGP4_E_HIP; }
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SGP4_E_HIP;
+      }
       const int blocks[] = {128, 256, 512};
       // waves per CU for the persistent grid; 0 = one wavefront per tile/chunk (no loop)
       const int per_cu[] = {4, 8, 16, 0};
@@ -434,7 +444,7 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       // nothing of the candidates must stay owned by the copies
-      if (p->ncandidates == 0) { plan_free(p); return SGP4_E_HIP; }
+      if (p->ncandidates == 0) return SGP4_E_HIP;
       p->best_us = best;
       cache_store(key, p->mode, p->block, p->grid, best);
     }
@@ -442,7 +452,7 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
 
   if (flags & SGP4_PLAN_GRAPH) {
     hipStream_t cs;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { plan_free(p); return SGP4_E_HIP; }
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SGP4_E_HIP;
     bool gok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (gok) {
       const hipError_t le = plan_launch_direct(p, cs);
@@ -451,22 +461,32 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
             hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
     }
     (void)hipStreamDestroy(cs);
-    if (!gok) { plan_free(p); return SGP4_E_HIP; }
+    if (!gok) return SGP4_E_HIP;
   }
+  own.p = nullptr;
   *out = p;
   return SGP4_OK;
 }
 
 int sgp4_plan_create(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
                      int64_t nnz, int precision, void* r, void* v, uint8_t* err, unsigned flags, void* stream) {
-  return plan_build(out, consts, n, offsets, t, nnz, precision, r, v, err, flags, -1, 0, 0, stream);
+  try {
+    return plan_build(out, consts, n, offsets, t, nnz, precision, r, v, err, flags, -1, 0, 0, stream);
+  } catch (...) {  // host allocation failure: nothing may unwind through the C ABI
+    return SGP4_E_HOST;
+  }
 }
 
 int sgp4_plan_create_config(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
                             int64_t nnz, int precision, void* r, void* v, uint8_t* err, int mode, int block,
                             int waves_per_cu, unsigned flags, void* stream) {
   if (mode < 0) return SGP4_E_ARG;
-  return plan_build(out, consts, n, offsets, t, nnz, precision, r, v, err, flags, mode, block, waves_per_cu, stream);
+  try {
+    return plan_build(out, consts, n, offsets, t, nnz, precision, r, v, err, flags, mode, block, waves_per_cu,
+                      stream);
+  } catch (...) {
+    return SGP4_E_HOST;
+  }
 }
 
 int sgp4_plan_launch(const sgp4_plan* plan, void* stream) {

@@ -13,10 +13,12 @@
 // Decimal fields are converted with std::from_chars (correctly rounded,
 // locale-independent).  Unit conversions: mean motion rev/day -> rad/min by
 // division by 1440 / (2 pi); degrees -> radians by multiplication by pi / 180.
+#include <atomic>
 #include <charconv>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -261,6 +263,35 @@ void tle_scan(const char* from, const char* to, const char* end, std::vector<con
   }
 }
 
+// fn(k) for k in [0, parts) on worker threads; a part whose thread cannot be
+// started runs on the calling thread, every started thread is joined, and a
+// failure inside a worker is rethrown on the calling thread as bad_alloc.
+template <class F>
+void run_parts(int parts, F fn) {
+  std::atomic<bool> failed{false};
+  auto body = [&](int k) {
+    try {
+      fn(k);
+    } catch (...) {
+      failed = true;
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    pool.reserve(size_t(parts));
+  } catch (...) {
+  }
+  for (int k = 0; k < parts; ++k) {
+    try {
+      pool.emplace_back(body, k);
+    } catch (...) {
+      body(k);
+    }
+  }
+  for (auto& th : pool) th.join();
+  if (failed) throw std::bad_alloc();
+}
+
 // Line-aligned chunk boundaries of the text for `parts` workers.
 std::vector<const char*> chunks(const char* text, size_t len, int parts) {
   std::vector<const char*> cut{text};
@@ -296,9 +327,7 @@ std::vector<const char*> tle_records(const char* text, size_t len, int threads) 
     if (parts == 1) tle_scan(cut[0], cut[1], end, &all);
     return all;
   }
-  std::vector<std::thread> pool;
-  for (int k = 0; k < parts; ++k) pool.emplace_back([&, k] { tle_scan(cut[k], cut[k + 1], end, &found[k]); });
-  for (auto& th : pool) th.join();
+  run_parts(parts, [&](int k) { tle_scan(cut[k], cut[k + 1], end, &found[size_t(k)]); });
   std::vector<const char*> all;
   for (auto& v : found) all.insert(all.end(), v.begin(), v.end());
   return all;
@@ -601,12 +630,7 @@ void store(const Fields& f, int64_t i, int64_t n, const double ref[2], double* e
 
 constexpr double kJ2000[2] = {2451545.0, 0.0};
 
-}  // namespace
-
-extern "C" {
-
-int sgp4_text_count(const char* text, size_t len, int format, int64_t* n_out) {
-  if (!n_out) return SGP4_E_ARG;
+int text_count(const char* text, size_t len, int format, int64_t* n_out) {
   *n_out = 0;
   if (!text && len) return SGP4_E_ARG;
   if (format == SGP4_TEXT_TLE) {
@@ -620,9 +644,8 @@ int sgp4_text_count(const char* text, size_t len, int format, int64_t* n_out) {
   return SGP4_OK;
 }
 
-int sgp4_text_parse(const char* text, size_t len, int format, int64_t n, const double* ref_jd, double* elem,
-                    int64_t* satnum, int32_t* status, int threads) {
-  if (n < 0) return SGP4_E_SIZE;
+int text_parse(const char* text, size_t len, int format, int64_t n, const double* ref_jd, double* elem,
+               int64_t* satnum, int32_t* status, int threads) {
   if ((!text && len) || (n > 0 && !elem)) return SGP4_E_ARG;
   const double* ref = ref_jd ? ref_jd : kJ2000;
   if (!std::isfinite(ref[0]) || !std::isfinite(ref[1])) return SGP4_E_ARG;
@@ -644,9 +667,7 @@ int sgp4_text_parse(const char* text, size_t len, int format, int64_t n, const d
     if (parts <= 1 || n < 4096) {
       work(0, n);
     } else {
-      std::vector<std::thread> pool;
-      for (int k = 0; k < parts; ++k) pool.emplace_back(work, n * k / parts, n * (k + 1) / parts);
-      for (auto& th : pool) th.join();
+      run_parts(parts, [&](int k) { work(n * k / parts, n * (k + 1) / parts); });
     }
     return SGP4_OK;
   }
@@ -660,6 +681,31 @@ int sgp4_text_parse(const char* text, size_t len, int format, int64_t n, const d
     store(f, i, n, ref, elem, satnum, status);
   }
   return SGP4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Host allocations and worker threads may fail; no exception crosses the C ABI.
+int sgp4_text_count(const char* text, size_t len, int format, int64_t* n_out) {
+  if (!n_out) return SGP4_E_ARG;
+  try {
+    return text_count(text, len, format, n_out);
+  } catch (...) {
+    *n_out = 0;
+    return SGP4_E_HOST;
+  }
+}
+
+int sgp4_text_parse(const char* text, size_t len, int format, int64_t n, const double* ref_jd, double* elem,
+                    int64_t* satnum, int32_t* status, int threads) {
+  if (n < 0) return SGP4_E_SIZE;
+  try {
+    return text_parse(text, len, format, n, ref_jd, elem, satnum, status, threads);
+  } catch (...) {
+    return SGP4_E_HOST;
+  }
 }
 
 }  // extern "C"
