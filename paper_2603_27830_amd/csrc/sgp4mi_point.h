@@ -217,10 +217,11 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
 
   // Kepler: psi - axn sin psi + ayn cos psi = U, Newton from psi = U with the
   // step clamped to +-0.95; dpsi = psi - U.  A lane is done once its step is
-  // below the tolerance or once the quadratic-convergence bound on the next
-  // step, eL / (2 (1 - eL)) * step^2 with eL <= |axn| + |ayn|, is below it (the
-  // step that would follow changes psi by less than the tolerance).  The loop
-  // ends when every lane of the wavefront is done (at most 10 steps).
+  // below the tolerance or once a bound on the next step is: Newton's next
+  // step is at most eL / (2 (1 - eL)) * step^2 with eL <= |axn| + |ayn|, itself
+  // at most eL * step^2 while eL < 1/2 (so the step that would follow changes
+  // psi by less than the tolerance).  The loop ends when every lane of the
+  // wavefront is done (at most 10 steps).
   // U = L_T - node, with the mean longitude L = M + argp + node and its J3
   // long-period correction L_T = L + tau L_cof a_xN: node cancels.
   const TS U = M + argp + TS(tau * c.Lcof * axn);
@@ -228,7 +229,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TR::sc(U, &sp, &cp);
   TP dpsi = TP(0);
   const TP eb = vabs(axn) + vabs(ayn);
-  const TP quad = eb < TP(0.5) ? TP(0.5) * eb * rcp(TP(1) - eb) : TP(1.0e30);
+  const TP quad = eb < TP(0.5) ? eb : TP(1.0e30);
   for (int k = 0; k < 10; ++k) {
     TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
     step = clamp_step(step);

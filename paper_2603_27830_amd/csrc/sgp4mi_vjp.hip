@@ -79,7 +79,7 @@ __device__ __forceinline__ uint32_t point_vjp(const SatC<TS, TP>& c, const Grav&
   {
     TP dpsi = TP(0);
     const TP eb = vabs(axn) + vabs(ayn);
-    const TP quad = eb < TP(0.5) ? TP(0.5) * eb * rcp(TP(1) - eb) : TP(1.0e30);
+    const TP quad = eb < TP(0.5) ? eb : TP(1.0e30);
     for (int k = 0; k < 10; ++k) {
       TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
       step = clamp_step(step);
