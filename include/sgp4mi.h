@@ -122,12 +122,12 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
 /* Elements straight to states: initialisation and dense n x T propagation in
  * one call, the pipeline jaxsgp4 traces as one function (sections 2.2 and
  * 3.1).  Arguments as sgp4_init (grav, elem, sat_flags) and sgp4_propagate
- * (t, precision, r, v, err).  For T <= 16, or when ws is NULL, one fused
+ * (t, precision, r, v, err).  For T <= 32, or when ws is NULL, one fused
  * launch initialises each workgroup's 64 satellites into on-chip memory and
- * propagates them (no record in device memory; ws untouched); for T > 16 with
+ * propagates them (no record in device memory; ws untouched); for T > 32 with
  * ws (device, at least sgp4_consts_bytes(n) bytes, else SGP4_E_WORKSPACE) it
  * runs sgp4_init into ws and sgp4_propagate, and ws then holds the records.
- * A fused launch covers T <= 524,280 (else SGP4_E_WORKSPACE when ws is NULL).
+ * A fused launch covers T <= 1,048,560 (else SGP4_E_WORKSPACE when ws is NULL).
  * Results equal the two-stage path's: codes identical, states to rounding.
  * n = 0 or T = 0 writes nothing. */
 int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,

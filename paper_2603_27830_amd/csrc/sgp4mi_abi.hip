@@ -52,7 +52,7 @@ constexpr int64_t kFlatBelowT = 64;
 // Elements-to-states calls with at most this many times run the fused
 // kernel (initialisation kept on chip); longer ones, given a record
 // workspace, run initialisation and the default dense launch.
-constexpr int64_t kFusedMaxT = 16;
+constexpr int64_t kFusedMaxT = 32;
 // Default dense launch: one wavefront per 64-time tile with the satellite's
 // constants in scalar registers, in 256-wide workgroups for FP64 and 512-wide
 // for the float paths (fastest of the mapping x workgroup x residency sweep on

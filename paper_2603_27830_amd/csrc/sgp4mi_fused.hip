@@ -20,7 +20,7 @@
 
 namespace sgp4mi {
 
-constexpr int kFusedTT = 8;
+constexpr int kFusedTT = 16;
 
 struct FusedArgs {
   int64_t n, T;

@@ -50,7 +50,7 @@ template <class TR>
 __global__ void __launch_bounds__(256) screen_pack(const TR* __restrict__ r, const uint8_t* __restrict__ err, int64_t n,
                                                    int64_t T, float2* __restrict__ ws) {
   __shared__ float2 tile[64][65];
-  const int64_t i0 = int64_t(blockIdx.x) * 64, k0 = int64_t(blockIdx.y) * 64;
+  const int64_t k0 = int64_t(blockIdx.x) * 64, i0 = int64_t(blockIdx.y) * 64;  // times on x: T may be large
   const int64_t P = n * T;
   for (int e = threadIdx.x; e < 4096; e += 256) {
     const int si = e >> 6, kk = e & 63;  // consecutive lanes: consecutive times of one satellite
@@ -215,7 +215,7 @@ hipError_t launch_screen(const void* r, bool fp64, const uint8_t* err, int64_t n
   hipLaunchKernelGGL(screen_clear, dim3(1), dim3(64), 0, s, count);
   if (n < 2 || T == 0) return hipGetLastError();
   float2* w = static_cast<float2*>(ws);
-  const dim3 pg(unsigned((n + 63) / 64), unsigned((T + 63) / 64));
+  const dim3 pg(unsigned((T + 63) / 64), unsigned((n + 63) / 64));
   if (fp64)
     hipLaunchKernelGGL(screen_pack<double>, pg, dim3(256), 0, s, static_cast<const double*>(r), err, n, T, w);
   else

@@ -115,8 +115,8 @@ def test_elements_to_states_and_flat_config_reject_bad_arguments():
     assert pe(None, 10, fake, fake, 5, 0, None, fake, fake, None, None, 0, None) == E["SGP4_E_ARG"]
     small = L.sgp4_consts_bytes(10) - 1
     assert pe(None, 10, fake, fake, 5, 0, fake, fake, fake, None, fake, small, None) == E["SGP4_E_WORKSPACE"]
-    # a fused launch covers ceil(T / 8) <= 65535 workgroups in y; beyond that a workspace is required
-    assert pe(None, 10, fake, fake, 65535 * 8 + 1, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_WORKSPACE"]
+    # a fused launch covers ceil(T / 16) <= 65535 workgroups in y; beyond that a workspace is required
+    assert pe(None, 10, fake, fake, 65535 * 16 + 1, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_WORKSPACE"]
     bad = (ctypes.c_double * 5)(398600.8, -1.0, 0.0, 0.0, 0.0)
     assert pe(bad, 10, fake, fake, 5, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_GRAVITY"]
     # empty batches launch nothing and succeed, even with null buffers

@@ -57,8 +57,8 @@ SHAPES = [(1, 1), (130, 1), (64, 2), (65, 3), (7, 7), (200, 8), (129, 9), (33, 1
 @pytest.mark.parametrize("n,T", SHAPES)
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_elements_to_states_match_two_stage_path(n, T, prec):
-    """Every branch of the call: the fused launch (T <= 16; T = 1 on its own
-    kernel), the two-stage path (T > 16 with a workspace) and the fused launch
+    """Every branch of the call: the fused launch (T <= 32; T = 1 on its own
+    kernel), the two-stage path (T > 32 with a workspace) and the fused launch
     for long lists without one; ragged satellite and time counts."""
     elem = synth.shell_elements(n, 300 + n)
     t = np.sort(np.random.default_rng(T).uniform(-600.0, 8000.0, T))
@@ -78,7 +78,7 @@ def test_elements_to_states_fp64_vs_oracle(T):
     elem = cat.elem[:, :1500]
     t = np.sort(np.random.default_rng(5).uniform(0.0, 1440.0, T))
     say(f"[gpu] elements->states fp64 vs oracle n=1500 T={T}")
-    r, v, err = fused(elem, t, "fp64", ws=(T > 16))
+    r, v, err = fused(elem, t, "fp64", ws=(T > 32))
     ro, vo, eo = oracle.propagate(elem, t)
     dr, dv = check_fp64(r, v, err, ro, vo, eo)
     say(f"  max |dr| {dr:.3e} km, max |dv| {dv:.3e} km/s")
