@@ -12,7 +12,7 @@
 //
 // rotate_small: (sin x, cos x) -> (sin(x+d), cos(x+d)) by angle addition with
 // the series of sin d and cos d; used for |d| <= kRotMax, exact to rounding
-// there (double: d^9/9! < 6e-18 at |d| = 0.05).
+// there (double: d^9/9! < 6e-18 at |d| = 0.05; float: see small_sc).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -121,10 +121,11 @@ __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
   *cd = fma(pc, d2, 1.0);
 }
 
+// Float: through d^3 (sine) and d^4 (cosine); the next terms are below
+// 2.6e-9 and 2.2e-11 at |d| = 0.05, under the float rounding of the result.
 __device__ __forceinline__ void small_sc(float d, float* sd, float* cd) {
   const float d2 = d * d;
-  float ps = fmaf(d2, 8.3333333333e-3f, -1.6666666667e-1f);
-  *sd = fmaf(ps * d2, d, d);
+  *sd = fmaf(d2 * d, -1.6666666667e-1f, d);
   float pc = fmaf(d2, 4.1666666667e-2f, -0.5f);
   *cd = fmaf(pc, d2, 1.0f);
 }

@@ -276,10 +276,11 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TP ssu, csu;
   if (vabs(du) <= TP(kRotMax)) {
     // (sinu, cosu) is a unit vector up to rounding; one Newton step from 1
-    // normalises it to O(delta^2), delta = |.|^2 - 1
+    // normalises it to O(delta^2), delta = |.|^2 - 1 (float rounding leaves
+    // delta ~1e-6 at most, so the float paths need no other case)
     const TP n2 = sinu * sinu + cosu * cosu;
     TP h = TP(1.5) - TP(0.5) * n2;
-    if (vabs(n2 - TP(1)) > TP(1.0e-8)) h = rsq(n2);
+    if (sizeof(TP) == 8 && vabs(n2 - TP(1)) > TP(1.0e-8)) h = rsq(n2);
     ssu = sinu * h;
     csu = cosu * h;
     rotate_small(&ssu, &csu, du);
