@@ -371,6 +371,20 @@ def main():
                                              "hbm_gbs": BYTES_PER_POINT[name] * P2 / k2 / 1e9}
             log(f"[bench] c2 {name}: {P2 / k2:.3e} pts/s, kernel {k2 * 1e3:.3f} ms")
             del out2, rec2
+        # 7-day variant: 1,008 times at 10-minute steps
+        t7 = torch.from_numpy(synth.config2("7d").t).to(dev)
+        P7 = c2.n * int(t7.numel())
+        paths["c2_100k_x_1008_7d"] = {}
+        for name in ("fp64", "mixed"):
+            rec2 = sg.init(e2)
+            dt = torch.float64 if name == "fp64" else torch.float32
+            out7 = (torch.empty((3, c2.n, P7 // c2.n), dtype=dt, device=dev),
+                    torch.empty((3, c2.n, P7 // c2.n), dtype=dt, device=dev),
+                    torch.empty((c2.n, P7 // c2.n), dtype=torch.uint8, device=dev))
+            k7 = kernel_time(lambda: sg.propagate(rec2, t7, name, out=out7), torch, reps=5)
+            paths["c2_100k_x_1008_7d"][name] = {"propagate_only_points_per_s": P7 / k7, "kernel_ms": k7 * 1e3}
+            log(f"[bench] c2 7-day {name}: {P7 / k7:.3e} pts/s, kernel {k7 * 1e3:.3f} ms")
+            del out7, rec2
         torch.cuda.empty_cache()
 
     if not args.no_vjp and not args.only:
