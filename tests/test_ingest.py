@@ -233,3 +233,37 @@ def test_native_parser_argument_errors():
     assert L.sgp4_text_parse(txt, len(txt), 1, 1, bad_ref, buf, None, None, 1) == E["SGP4_E_ARG"]
     assert L.sgp4_text_parse(txt, len(txt), 1, 1, None, buf, None, None, 1) == 0
     assert buf[2] == 53.0 * math.pi / 180
+
+
+def test_parsed_units_agree_with_the_propagated_orbit():
+    """The parser's unit conversions checked through the physics, not its own
+    formulas: propagating the parsed elements (oracle, FP64) must give an orbit
+    whose period is 1440 / (rev/day) minutes, whose maximum |z| / r is sin i and
+    whose ascending node lies at the RAAN (to the J2 effects over one orbit),
+    and whose epoch is where the text puts it."""
+    from oracle import propagate
+    l1 = "1 00042U 25001A   25032.25000000  .00000000  00000-0  00000-0 0  999"
+    l2 = "2 00042  51.6000  80.0000 0001000  30.0000 200.0000 15.50000000   17"
+    l1, l2 = _tle(l1, l2)
+    ref = (oi.jd0(2025, 1, 1), 0.0)
+    el, _, st = sg.parse_text(l1 + "\n" + l2 + "\n", "tle", ref_jd=ref)
+    assert st[0] == 0
+    assert el[7, 0] == 31.25                              # day 32.25 of 2025 is 31.25 days after January 1, 0h
+    period = 1440.0 / 15.5
+    t = 1440.0 * el[7, 0] + np.linspace(0.0, 1.2 * period, 4001)
+    r, v, err = propagate(el, t)
+    assert np.all(err == 0)
+    x, y, z = r[0, 0], r[1, 0], r[2, 0]
+    rr = np.sqrt(x * x + y * y + z * z)
+    assert abs(np.degrees(np.arcsin(np.max(np.abs(z) / rr))) - 51.6) < 0.05
+    # consecutive ascending crossings of the equator: period and node longitude
+    up = np.flatnonzero((z[:-1] < 0) & (z[1:] >= 0))
+    assert len(up) >= 1
+    k = up[0]
+    f = -z[k] / (z[k + 1] - z[k])
+    tc = t[k] + f * (t[k + 1] - t[k])
+    xc, yc = x[k] + f * (x[k + 1] - x[k]), y[k] + f * (y[k + 1] - y[k])
+    node = math.degrees(math.atan2(yc, xc)) % 360.0
+    assert abs(node - 80.0) < 0.4                          # nodal regression ~5 deg/day: < 0.35 deg in an orbit
+    # the satellite starts at u = 30 + 200 deg from the node; it reaches the node after (360 - 230)/360 of an orbit
+    assert abs((tc - t[0]) - period * (360.0 - 230.0) / 360.0) < 0.01 * period
