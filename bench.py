@@ -370,6 +370,28 @@ def main():
             paths["c2_100k_x_1440"][name] = {"propagate_only_points_per_s": P2 / k2, "kernel_ms": k2 * 1e3,
                                              "hbm_gbs": BYTES_PER_POINT[name] * P2 / k2 / 1e9}
             log(f"[bench] c2 {name}: {P2 / k2:.3e} pts/s, kernel {k2 * 1e3:.3f} ms")
+            if name == "mixed":
+                # Conjunction screening of the whole 100k x 1,440 output at 10 km
+                # (device-memory buckets: beyond the on-chip size).
+                import ctypes
+                from paper_2603_27830_amd import _native
+                L = _native.lib()
+                wsb = int(L.sgp4_screen_workspace_bytes(c2.n, c2.T))
+                ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+                cap = 1 << 22
+                pairs = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+                dist = torch.empty(cap, dtype=torch.float64, device=dev)
+                cnt = torch.empty(1, dtype=torch.int64, device=dev)
+                vp = lambda x: ctypes.c_void_p(x.data_ptr())  # noqa: E731
+                st = lambda: ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)  # noqa: E731
+                ksc = kernel_time(lambda: _native.check(L.sgp4_screen(
+                    vp(out2[0]), _native.SGP4_FP32_MIXED, vp(out2[2]), c2.n, c2.T, 10.0, cap, vp(pairs), vp(dist),
+                    vp(cnt), vp(ws), wsb, st()), "sgp4_screen"), torch, reps=3)
+                events = int(cnt.item())
+                paths["c2_100k_x_1440"]["screen_10km"] = {"ms": ksc * 1e3, "events": events,
+                                                         "satellite_times_per_s": P2 / ksc}
+                log(f"[bench] screen 100k x 1440 (10 km): {ksc * 1e3:.3f} ms, {events} events")
+                del ws, pairs, dist
             del out2, rec2
         # 7-day variant: 1,008 times at 10-minute steps
         t7 = torch.from_numpy(synth.config2("7d").t).to(dev)

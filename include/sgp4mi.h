@@ -152,16 +152,26 @@ int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, c
  *   count: device int64, set to the number of events found (which may exceed
  *      capacity: only the first `capacity` found are written).
  *   ws: device scratch of at least sgp4_screen_workspace_bytes(n, T) bytes
- *      (8 n T: float x, y per point, time-major), else SGP4_E_WORKSPACE
- *      (not needed when n < 2 or T = 0); its contents are not kept.
- * Enqueues a clear of count, a packing pass into ws and one screening launch
- * (one workgroup per sample time).  0 <= n <= 12288 (each time's points are
- * bucket-sorted in on-chip memory, else SGP4_E_SIZE); dist_km finite and > 0
- * (else SGP4_E_ARG). */
+ *      (about 12 n T + 4 T n / 4: sorted float x, y and satellite index per
+ *      point and bucket offsets per time), else SGP4_E_WORKSPACE (not needed
+ *      when n < 2 or T = 0); its contents are not kept.
+ * Each time's valid points are bucket-sorted by x (buckets at least D wide)
+ * and every point is tested against the rest of its bucket and the next one.
+ * For n <= 12288 this happens in on-chip memory, one workgroup per time (a
+ * packing pass, then one launch); larger batches keep the buckets in ws (a
+ * range reduction, a histogram, a scan per time, a placement and a sweep).
+ * dist_km finite and > 0 (else SGP4_E_ARG); n * T within 2^31 * 256 (else
+ * SGP4_E_SIZE). */
 size_t sgp4_screen_workspace_bytes(int64_t n, int64_t T);
 int sgp4_screen(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
                 int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
                 void* stream);
+/* As sgp4_screen with the path chosen: mode 0 as sgp4_screen, 1 the on-chip
+ * path (n <= 12288, else SGP4_E_SIZE), 2 the device-memory path; both give
+ * the same events. */
+int sgp4_screen_ex(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
+                   int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
+                   int mode, void* stream);
 
 /* ---------------------------------------------------------------- ingestion --
  * Element-set text to the elements sgp4_init takes, on the host.  Formats:

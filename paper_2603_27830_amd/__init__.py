@@ -205,11 +205,13 @@ def propagate_elements(elem: torch.Tensor, t: torch.Tensor, precision="fp64", gr
     return r, v, err
 
 
-def screen(r: torch.Tensor, dist_km: float, err: Optional[torch.Tensor] = None, capacity: int = 1 << 20):
+def screen(r: torch.Tensor, dist_km: float, err: Optional[torch.Tensor] = None, capacity: int = 1 << 20,
+           mode: int = 0):
     """Conjunction screening of a dense output r [3, n, T] (float64 or float32,
     device): every pair i < j closer than dist_km at a common time index
     (sgp4_screen).  Returns (pairs int32 [m, 3] of (i, j, k), dist float64 [m]
-    km, total) with m = min(total, capacity); event order is unspecified."""
+    km, total) with m = min(total, capacity); event order is unspecified.
+    mode: 0 automatic, 1 the on-chip path (n <= 12288), 2 the device-memory path."""
     if r.dim() != 3 or r.shape[0] != 3:
         raise ValueError("r must have shape [3, n, T]")
     if r.dtype not in (torch.float64, torch.float32):
@@ -227,8 +229,9 @@ def screen(r: torch.Tensor, dist_km: float, err: Optional[torch.Tensor] = None, 
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=r.device)
     prec = _native.SGP4_FP64 if r.dtype == torch.float64 else _native.SGP4_FP32
     with torch.cuda.device(r.device):
-        _native.check(L.sgp4_screen(_ptr(r), prec, _ptr(err), n, T, float(dist_km), cap, _ptr(pairs), _ptr(dist),
-                                    _ptr(count), _ptr(ws), wsb, _stream(r.device)), "sgp4_screen")
+        _native.check(L.sgp4_screen_ex(_ptr(r), prec, _ptr(err), n, T, float(dist_km), cap, _ptr(pairs),
+                                       _ptr(dist), _ptr(count), _ptr(ws), wsb, int(mode), _stream(r.device)),
+                      "sgp4_screen")
     total = int(count.item())
     m = min(total, cap)
     return pairs[:m], dist[:m], total

@@ -27,9 +27,10 @@ hipError_t launch_fused(int precision, const double g[5], int64_t n, const doubl
                         void* r, void* v, uint8_t* err, uint8_t* user_flags, hipStream_t s);
 int64_t fused_max_T();
 hipError_t launch_screen(const void* r, bool fp64, const uint8_t* err, int64_t n, int64_t T, double D, int64_t cap,
-                         int32_t* pairs, double* dist, unsigned long long* count, void* ws, hipStream_t s);
+                         int32_t* pairs, double* dist, unsigned long long* count, void* ws, int mode, hipStream_t s);
 int screen_max_n();
 size_t screen_ws_bytes(int64_t n, int64_t T);
+bool screen_global_fits(int64_t n, int64_t T);
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
@@ -272,22 +273,30 @@ int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, c
 }
 
 size_t sgp4_screen_workspace_bytes(int64_t n, int64_t T) {
-  if (n < 0 || T < 0 || mul_overflows(n, T) || mul_overflows(n * T, 8)) return 0;
+  if (n < 0 || T < 0 || mul_overflows(n, T) || mul_overflows(n * T, 16)) return 0;
   return screen_ws_bytes(n, T);
 }
 
-int sgp4_screen(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
-                int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
-                void* stream) {
-  if (n < 0 || T < 0 || n > screen_max_n() || T > 0x7ffffff0LL || mul_overflows(n, T) || capacity < 0)
+int sgp4_screen_ex(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
+                   int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
+                   int mode, void* stream) {
+  if (mode < 0 || mode > 2) return SGP4_E_ARG;
+  if (n < 0 || T < 0 || T > 0x7ffffff0LL || mul_overflows(n, T) || mul_overflows(n * T, 16) || capacity < 0)
     return SGP4_E_SIZE;
+  if ((mode == 1 && n > screen_max_n()) || !screen_global_fits(n, T)) return SGP4_E_SIZE;
   if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
   if (!(dist_km > 0.0) || !std::isfinite(dist_km)) return SGP4_E_ARG;
   if (!count || (capacity > 0 && (!pairs || !dist)) || (n > 0 && T > 0 && !r)) return SGP4_E_ARG;
   if (n >= 2 && T > 0 && (!ws || ws_bytes < screen_ws_bytes(n, T))) return SGP4_E_WORKSPACE;
   return hip_status(launch_screen(r, precision == SGP4_FP64, err, n, T, dist_km, capacity, pairs, dist,
-                                  reinterpret_cast<unsigned long long*>(count), ws,
+                                  reinterpret_cast<unsigned long long*>(count), ws, mode,
                                   static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_screen(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
+                int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
+                void* stream) {
+  return sgp4_screen_ex(r, precision, err, n, T, dist_km, capacity, pairs, dist, count, ws, ws_bytes, 0, stream);
 }
 
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,

@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace sgp4mi {
 
 constexpr int kScreenMaxN = 12288;
@@ -208,12 +210,246 @@ static size_t screen_lds_bytes(int64_t n) {
   return size_t(n) * 8 + size_t((n + 1) & ~int64_t(1)) * 2 + size_t(kScreenBuckets + 1) * 4;
 }
 
-size_t screen_ws_bytes(int64_t n, int64_t T) { return size_t(n) * size_t(T) * sizeof(float2); }
+// ------------------------------------------------------- any-n (global) path --
+// The same bucket sort and sweep with the buckets in device memory, for
+// batches whose points do not fit one workgroup's LDS.  Buckets of x span a
+// range [-R, R] with R the largest |x| of any valid point (one reduction over
+// the batch), nb = n / 4 of them at most, width w >= D plus the rounding
+// margin of R (fewer, wider buckets when the range is small).  Per time k:
+// counts[k][b] (histogram, then offsets by an in-place scan, then ends after
+// placement), and the sorted (x, y) and satellite index of the valid points.
+struct GHeader {
+  unsigned int rbits;  // largest valid |x| as float bits (non-negative floats order as integers)
+  int32_t nb;          // buckets in use per time
+  double x0, inv_w;    // bucket b = (x - x0) * inv_w
+};
 
+struct GLayout {
+  GHeader* hdr;
+  int32_t* counts;  // [T][nbmax + 1]
+  float2* sxy;      // [T][n]
+  int32_t* sidx;    // [T][n]
+  int64_t nbmax;
+};
+
+static int64_t screen_global_buckets(int64_t n) {
+  int64_t nb = n / 4;
+  if (nb < 16) nb = 16;
+  if (nb > (int64_t(1) << 20)) nb = int64_t(1) << 20;
+  return nb;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static GLayout global_layout(void* ws, int64_t n, int64_t T) {
+  GLayout L;
+  L.nbmax = screen_global_buckets(n);
+  char* b = static_cast<char*>(ws);
+  L.hdr = reinterpret_cast<GHeader*>(b);
+  b += align256(sizeof(GHeader));
+  L.counts = reinterpret_cast<int32_t*>(b);
+  b += align256(size_t(T) * size_t(L.nbmax + 1) * 4);
+  L.sxy = reinterpret_cast<float2*>(b);
+  b += align256(size_t(T) * size_t(n) * 8);
+  L.sidx = reinterpret_cast<int32_t*>(b);
+  return L;
+}
+
+static size_t global_ws_bytes(int64_t n, int64_t T) {
+  const int64_t nbmax = screen_global_buckets(n);
+  return align256(sizeof(GHeader)) + align256(size_t(T) * size_t(nbmax + 1) * 4) + align256(size_t(T) * size_t(n) * 8) +
+         size_t(T) * size_t(n) * 4;
+}
+
+template <class TR>
+__device__ __forceinline__ bool valid_point(const TR* __restrict__ r, const uint8_t* __restrict__ err, int64_t P,
+                                            int64_t p, float* x, float* y) {
+  const TR vx = r[p], vy = r[P + p], vz = r[2 * P + p];
+  bool ok = isfinite(double(vx)) && isfinite(double(vy)) && isfinite(double(vz));
+  if (err) ok = ok && (err[p] == 0 || err[p] == 6);
+  *x = float(vx);
+  *y = float(vy);
+  return ok;
+}
+
+// Clear the header and the counts (a fill kernel, so the launch sequence can
+// be captured in a graph).
+__global__ void gscreen_clear(GLayout L, int64_t T) {
+  const int64_t total = T * (L.nbmax + 1);
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < total; q += int64_t(gridDim.x) * blockDim.x)
+    L.counts[q] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    L.hdr->rbits = 0u;
+    L.hdr->nb = 0;
+  }
+}
+
+template <class TR>
+__global__ void __launch_bounds__(256) gscreen_range(const TR* __restrict__ r, const uint8_t* __restrict__ err,
+                                                     int64_t P, GLayout L) {
+  float m = 0.0f;
+  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256) {
+    float x, y;
+    if (valid_point(r, err, P, p, &x, &y)) m = fmaxf(m, fabsf(x));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(&L.hdr->rbits, __float_as_uint(m));
+}
+
+__global__ void gscreen_buckets(GLayout L, double D) {
+  if (threadIdx.x != 0) return;
+  const double R = double(__uint_as_float(L.hdr->rbits));
+  const double span = 2.0 * R;
+  const double w = fmax((D + 2.4e-7 * R) * (1.0 + 1.0e-6), span / double(L.nbmax - 1));
+  int64_t nb = int64_t(span / w) + 1;
+  if (nb > L.nbmax) nb = L.nbmax;
+  L.hdr->nb = int32_t(nb);
+  L.hdr->x0 = -R;
+  L.hdr->inv_w = 1.0 / w;
+}
+
+__device__ __forceinline__ int32_t gbucket(const GHeader& h, float x) {
+  const int32_t b = int32_t((double(x) - h.x0) * h.inv_w);
+  return b < h.nb - 1 ? b : h.nb - 1;
+}
+
+template <class TR>
+__global__ void __launch_bounds__(256) gscreen_count(const TR* __restrict__ r, const uint8_t* __restrict__ err,
+                                                     int64_t T, int64_t P, GLayout L) {
+  const GHeader h = *L.hdr;
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= P) return;
+  float x, y;
+  if (!valid_point(r, err, P, p, &x, &y)) return;
+  const int64_t k = p % T;
+  atomicAdd(&L.counts[k * (L.nbmax + 1) + gbucket(h, x) + 1], 1);
+}
+
+// Inclusive scan of counts[k][1..nb] per time (one workgroup per time, 256
+// lanes, chunks of 256 buckets with a running carry).
+__global__ void __launch_bounds__(256) gscreen_scan(GLayout L) {
+  __shared__ int32_t part[4];
+  __shared__ int32_t carry_s;
+  const int32_t nb = L.hdr->nb;
+  int32_t* c = L.counts + int64_t(blockIdx.x) * (L.nbmax + 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t carry = 0;
+  for (int32_t base = 1; base <= nb; base += 256) {
+    const int32_t b = base + int32_t(threadIdx.x);
+    int32_t v = b <= nb ? c[b] : 0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) part[wave] = v;
+    __syncthreads();
+    int32_t before = carry;
+    for (int q = 0; q < wave; ++q) before += part[q];
+    if (b <= nb) c[b] = before + v;
+    if (threadIdx.x == 255) carry_s = before + v;
+    __syncthreads();
+    carry = carry_s;
+    __syncthreads();
+  }
+}
+
+template <class TR>
+__global__ void __launch_bounds__(256) gscreen_place(const TR* __restrict__ r, const uint8_t* __restrict__ err,
+                                                     int64_t n, int64_t T, GLayout L) {
+  const GHeader h = *L.hdr;
+  const int64_t P = n * T;
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= P) return;
+  float x, y;
+  if (!valid_point(r, err, P, p, &x, &y)) return;
+  const int64_t i = p / T, k = p - (p / T) * T;
+  const int32_t q = atomicAdd(&L.counts[k * (L.nbmax + 1) + gbucket(h, x)], 1);
+  L.sxy[k * n + q] = make_float2(x, y);
+  L.sidx[k * n + q] = int32_t(i);
+}
+
+template <class TR>
+__global__ void __launch_bounds__(256)
+    gscreen_sweep(const TR* __restrict__ r, int64_t n, int64_t T, double D, double D2, GLayout L, int64_t cap,
+                  int32_t* __restrict__ pairs, double* __restrict__ dist, unsigned long long* __restrict__ count) {
+  const GHeader h = *L.hdr;
+  const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= n * T) return;
+  const int64_t k = g / n, q = g - (g / n) * n;
+  const int32_t* c = L.counts + k * (L.nbmax + 1);
+  if (q >= c[h.nb - 1]) return;  // after placement c[b] is the end of bucket b
+  const float2* sxy = L.sxy + k * n;
+  const int32_t* sidx = L.sidx + k * n;
+  const int64_t P = n * T;
+  const float2 vi = sxy[q];
+  const int32_t i = sidx[q];
+  const int32_t b = gbucket(h, vi.x);
+  const int32_t end = b + 1 < h.nb ? c[b + 1] : c[b];
+  const double xi = vi.x, yi = vi.y;
+  const int64_t pi = int64_t(i) * T + k;
+  for (int32_t q2 = int32_t(q) + 1; q2 < end; ++q2) {
+    const float2 vj = sxy[q2];
+    const double xj = vj.x, yj = vj.y;
+    if (!(fabs(xj - xi) < D + 1.2e-7 * (fabs(xi) + fabs(xj)))) continue;
+    if (!(fabs(yj - yi) < D + 1.2e-7 * (fabs(yi) + fabs(yj)))) continue;
+    const int32_t j = sidx[q2];
+    const int64_t pj = int64_t(j) * T + k;
+    const double d2 = dist2(r, P, pi, pj);
+    if (d2 < D2) {
+      const unsigned long long e = atomicAdd(count, 1ull);
+      if (int64_t(e) < cap) {
+        pairs[3 * e] = i < j ? i : j;
+        pairs[3 * e + 1] = i < j ? j : i;
+        pairs[3 * e + 2] = int32_t(k);
+        dist[e] = sqrt(d2);
+      }
+    }
+  }
+}
+
+template <class TR>
+static hipError_t screen_global(const TR* r, const uint8_t* err, int64_t n, int64_t T, double D, int64_t cap,
+                                int32_t* pairs, double* dist, unsigned long long* count, void* ws, hipStream_t s) {
+  const GLayout L = global_layout(ws, n, T);
+  const int64_t P = n * T;
+  const unsigned gp = unsigned((P + 255) / 256);
+  const int64_t cells = T * (L.nbmax + 1);
+  hipLaunchKernelGGL(gscreen_clear, dim3(unsigned(std::min<int64_t>((cells + 255) / 256, 65536))), dim3(256), 0, s,
+                     L, T);
+  hipLaunchKernelGGL(gscreen_range<TR>, dim3(unsigned(std::min<int64_t>((P + 255) / 256, 16384))), dim3(256), 0, s,
+                     r, err, P, L);
+  hipLaunchKernelGGL(gscreen_buckets, dim3(1), dim3(64), 0, s, L, D);
+  hipLaunchKernelGGL(gscreen_count<TR>, dim3(gp), dim3(256), 0, s, r, err, T, P, L);
+  hipLaunchKernelGGL(gscreen_scan, dim3(unsigned(T)), dim3(256), 0, s, L);
+  hipLaunchKernelGGL(gscreen_place<TR>, dim3(gp), dim3(256), 0, s, r, err, n, T, L);
+  hipLaunchKernelGGL(gscreen_sweep<TR>, dim3(gp), dim3(256), 0, s, r, n, T, D, D * D, L, cap, pairs, dist, count);
+  return hipGetLastError();
+}
+
+// Workspace of the two paths: the LDS path packs 8 bytes per point; the
+// global path holds the header, the per-time bucket offsets and 12 bytes per
+// point of sorted (x, y) and satellite index.
+size_t screen_ws_bytes(int64_t n, int64_t T) {
+  const size_t lds = size_t(n) * size_t(T) * sizeof(float2);
+  const size_t glob = global_ws_bytes(n, T);
+  return lds > glob ? lds : glob;  // enough for either path
+}
+
+// Largest n * T the global path indexes (grids of 256-lane workgroups).
+bool screen_global_fits(int64_t n, int64_t T) {
+  return n <= 0x7fffffff && n * T <= int64_t(0x7fffffff) * 256 && T <= 0x7fffffff;
+}
+
+// mode 0: the LDS path when n <= kScreenMaxN, else the global path; 1: LDS
+// path (the caller checks n); 2: global path.
 hipError_t launch_screen(const void* r, bool fp64, const uint8_t* err, int64_t n, int64_t T, double D, int64_t cap,
-                         int32_t* pairs, double* dist, unsigned long long* count, void* ws, hipStream_t s) {
+                         int32_t* pairs, double* dist, unsigned long long* count, void* ws, int mode, hipStream_t s) {
   hipLaunchKernelGGL(screen_clear, dim3(1), dim3(64), 0, s, count);
   if (n < 2 || T == 0) return hipGetLastError();
+  if (mode == 2 || (mode == 0 && n > kScreenMaxN)) {
+    if (fp64) return screen_global(static_cast<const double*>(r), err, n, T, D, cap, pairs, dist, count, ws, s);
+    return screen_global(static_cast<const float*>(r), err, n, T, D, cap, pairs, dist, count, ws, s);
+  }
   float2* w = static_cast<float2*>(ws);
   const dim3 pg(unsigned((T + 63) / 64), unsigned((n + 63) / 64));
   if (fp64)

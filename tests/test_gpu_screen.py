@@ -32,8 +32,8 @@ def shell_points(n, T, seed, planted=40, radius=6900.0, thick=40.0):
     return r
 
 
-def gpu_events(r, D, err=None, cap=1 << 20):
-    pairs, dist, total = sg.screen(dev(r), D, None if err is None else dev(err), capacity=cap)
+def gpu_events(r, D, err=None, cap=1 << 20, mode=0):
+    pairs, dist, total = sg.screen(dev(r), D, None if err is None else dev(err), capacity=cap, mode=mode)
     torch.cuda.synchronize()
     p = pairs.cpu().numpy().astype(np.int64)
     d = dist.cpu().numpy()
@@ -41,8 +41,8 @@ def gpu_events(r, D, err=None, cap=1 << 20):
     return p[order], d[order], total
 
 
-def check(r, D, err=None, times=None):
-    ev, d, total = gpu_events(r, D, err)
+def check(r, D, err=None, times=None, mode=0):
+    ev, d, total = gpu_events(r, D, err, mode=mode)
     eo, do = osc.screen(r, D, err=err, times=None if times is None else sorted(times))
     if times is not None:
         keep = np.isin(ev[:, 2], np.asarray(list(times)))
@@ -54,16 +54,19 @@ def check(r, D, err=None, times=None):
     return len(eo)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n,T", [(2, 3), (63, 5), (3000, 16), (1025, 9)])
-def test_shell_points_match_oracle(n, T, dtype):
+def test_shell_points_match_oracle(n, T, dtype, mode):
+    """Both paths: on-chip buckets (mode 1) and device-memory buckets (mode 2)."""
     r = shell_points(n, T, seed=n + T).astype(dtype)
-    say(f"[gpu] screen shell n={n} T={T} {np.dtype(dtype).name}")
-    m = check(r, 25.0)
+    say(f"[gpu] screen shell n={n} T={T} {np.dtype(dtype).name} mode={mode}")
+    m = check(r, 25.0, mode=mode)
     say(f"  events {m}")
 
 
-def test_invalid_points_excluded():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_invalid_points_excluded(mode):
     n, T = 2000, 6
     r = shell_points(n, T, seed=9, planted=200)
     err = np.zeros((n, T), np.uint8)
@@ -71,8 +74,8 @@ def test_invalid_points_excluded():
     err[rng.random((n, T)) < 0.1] = 4
     err[rng.random((n, T)) < 0.05] = 6          # decayed points still count
     r[:, rng.random(n) < 0.03, :] = np.nan      # NaN states without a code
-    say("[gpu] screen with codes and NaN states")
-    m = check(r, 25.0, err=err)
+    say(f"[gpu] screen with codes and NaN states mode={mode}")
+    m = check(r, 25.0, err=err, mode=mode)
     assert m > 100
 
 
@@ -84,9 +87,10 @@ def test_lattice_closed_form_counts(m):
     nn, face, body = 3 * m * m * (m - 1), 6 * m * (m - 1) ** 2, 4 * (m - 1) ** 3
     say(f"[gpu] screen lattice m={m}")
     for D, want in ((4.04, nn), (6.0, nn + face), (7.2, nn + face + body)):
-        ev, _, total = gpu_events(r, D)
-        assert total == 2 * want and len(ev) == 2 * want
-        check(r, D)
+        for mode in (1, 2):
+            ev, _, total = gpu_events(r, D, mode=mode)
+            assert total == 2 * want and len(ev) == 2 * want
+            check(r, D, mode=mode)
 
 
 def test_capacity_smaller_than_the_events():
@@ -123,3 +127,30 @@ def test_catalogue_propagated_by_the_oracle_sampled_times():
         total = gpu_events(r.astype(dtype), 10.0, err=e)[2]
         say(f"  {np.dtype(dtype).name}: {m} events at the sampled times, {total} over all 1,000")
         assert m > 0 and total > m
+
+
+def test_beyond_on_chip_size_matches_oracle():
+    """20,000 satellites (over the on-chip limit, so the automatic choice takes
+    the device-memory path), float32 storage, every event against the oracle."""
+    r = shell_points(20000, 3, seed=77, planted=200).astype(np.float32)
+    say("[gpu] screen n=20000 T=3 (device-memory buckets)")
+    m = check(r, 15.0)
+    assert m > 200
+
+
+def test_mega_constellation_snapshot_sound_and_complete_on_a_subset():
+    """100,000 satellites at 2 times: every reported event is a true event
+    (distance recomputed from the positions), and on the first 15,000
+    satellites the events are exactly the oracle's."""
+    n, D = 100_000, 8.0
+    r = shell_points(n, 2, seed=99, planted=500)
+    say("[gpu] screen n=100000 T=2")
+    ev, d, total = gpu_events(r, D)
+    assert total == len(ev) and total > 500
+    i, j, k = ev[:, 0], ev[:, 1], ev[:, 2]
+    dd = np.sqrt(((r[:, j, k] - r[:, i, k]) ** 2).sum(axis=0))
+    assert np.all(i < j) and np.all(dd < D) and np.allclose(dd, d, rtol=1e-12)
+    sub = 15000
+    eo, _ = osc.screen(r[:, :sub, :], D)
+    mine = ev[(i < sub) & (j < sub)]
+    assert np.array_equal(mine, eo)

@@ -71,7 +71,10 @@ def test_screen_argument_errors():
     E = {v: k for k, v in _native.ERRORS.items()}
     fake = ctypes.c_void_p(0x1000)
     sc = L.sgp4_screen
-    assert sc(fake, 0, None, 12289, 10, 5.0, 10, fake, fake, fake, fake, 1 << 40, None) == E["SGP4_E_SIZE"]
+    sx = L.sgp4_screen_ex
+    assert sx(fake, 0, None, 12289, 10, 5.0, 10, fake, fake, fake, fake, 1 << 40, 1, None) == E["SGP4_E_SIZE"]
+    assert sx(fake, 0, None, 100, 10, 5.0, 10, fake, fake, fake, fake, 1 << 40, 3, None) == E["SGP4_E_ARG"]
+    assert sx(fake, 0, None, 2**31, 2**20, 5.0, 10, fake, fake, fake, fake, 1 << 62, 2, None) == E["SGP4_E_SIZE"]
     assert sc(fake, 0, None, -1, 10, 5.0, 10, fake, fake, fake, fake, 1 << 40, None) == E["SGP4_E_SIZE"]
     assert sc(fake, 0, None, 10, 10, 5.0, -1, fake, fake, fake, fake, 1 << 40, None) == E["SGP4_E_SIZE"]
     assert sc(fake, 5, None, 10, 10, 5.0, 10, fake, fake, fake, fake, 1 << 40, None) == E["SGP4_E_PRECISION"]
@@ -81,5 +84,7 @@ def test_screen_argument_errors():
     assert sc(fake, 0, None, 10, 10, 5.0, 10, None, fake, fake, fake, 1 << 40, None) == E["SGP4_E_ARG"]
     assert sc(None, 0, None, 10, 10, 5.0, 10, fake, fake, fake, fake, 1 << 40, None) == E["SGP4_E_ARG"]
     assert sc(fake, 0, None, 10, 10, 5.0, 10, fake, fake, fake, None, 0, None) == E["SGP4_E_WORKSPACE"]
-    assert sc(fake, 0, None, 10, 10, 5.0, 10, fake, fake, fake, fake, 799, None) == E["SGP4_E_WORKSPACE"]
-    assert L.sgp4_screen_workspace_bytes(10, 10) == 800
+    need = L.sgp4_screen_workspace_bytes(10, 10)
+    assert need >= 12 * 10 * 10
+    assert sc(fake, 0, None, 10, 10, 5.0, 10, fake, fake, fake, fake, need - 1, None) == E["SGP4_E_WORKSPACE"]
+    assert L.sgp4_screen_workspace_bytes(-1, 10) == 0
