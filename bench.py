@@ -262,8 +262,8 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (3 launches), the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(propagation shards by satellite with no exchange step: see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported (propagation would shard by blocks of "
+              "satellites with no exchange step, each GPU running this same single-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import torch
