@@ -1,6 +1,7 @@
 """The C-ABI library loads, exports every symbol its header declares, and its
 host-side argument checks reject bad calls before touching a GPU."""
 import ctypes
+import math
 import os
 import re
 
@@ -128,3 +129,21 @@ def test_elements_to_states_and_flat_config_reject_bad_arguments():
     for cfg in (256 | FLAT | 0x10000, 256 | FLAT | 0x40000 | 0x10000, 256 | FLAT | 0x20000 | (2 << 20), 96 | FLAT):
         assert px(fake, 10, fake, 10, 0, fake, fake, fake, cfg, None) == E["SGP4_E_ARG"], hex(cfg)
     assert px(fake, 2**31 - 1, fake, 2**9, 0, fake, fake, fake, 64 | FLAT, None) == E["SGP4_E_SIZE"]
+
+
+def test_double_sincos_table_is_correctly_rounded():
+    """The device table of sin and cos at j pi / 64 (j = -64 .. 64) holds the
+    doubles nearest the exact values (checked in 50-digit arithmetic)."""
+    import mpmath
+    src = open(os.path.join(os.path.dirname(_native.__file__), "csrc", "sgp4mi_math.h")).read()
+    body = src[src.index("kSinCos64[258] = {"):]
+    body = body[body.index("{") + 1:body.index("};")]
+    vals = [float(x) for x in body.replace("\n", " ").split(",") if x.strip()]
+    assert len(vals) == 258
+    mpmath.mp.dps = 50
+    for j in range(-64, 65):
+        a = mpmath.mpf(j) * mpmath.pi / 64
+        s_exact, c_exact = mpmath.sin(a), mpmath.cos(a)
+        s_tab, c_tab = vals[2 * (j + 64)], vals[2 * (j + 64) + 1]
+        assert abs(mpmath.mpf(s_tab) - s_exact) <= abs(mpmath.mpf(math.ulp(s_tab))) / 2 + mpmath.mpf(10) ** -45, j
+        assert abs(mpmath.mpf(c_tab) - c_exact) <= abs(mpmath.mpf(math.ulp(c_tab))) / 2 + mpmath.mpf(10) ** -45, j
