@@ -189,12 +189,21 @@ __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
   *cd = fma(pc, d2, 1.0);
 }
 
+// A float constant held in a scalar register.  gfx9 three-operand
+// instructions take no literal, so a fused multiply-add with a literal factor
+// and a second constant costs an extra vector move; with the factor in a
+// scalar register (set by a scalar move) it is one instruction.
+__device__ __forceinline__ float sgpr_const(float x) {
+  asm("" : "+s"(x));
+  return x;
+}
+
 // Float: through d^3 (sine) and d^4 (cosine); the next terms are below
 // 2.6e-9 and 2.2e-11 at |d| = 0.05, under the float rounding of the result.
 __device__ __forceinline__ void small_sc(float d, float* sd, float* cd) {
   const float d2 = d * d;
   *sd = fmaf(d2 * d, -1.6666666667e-1f, d);
-  float pc = fmaf(d2, 4.1666666667e-2f, -0.5f);
+  float pc = fmaf(d2, sgpr_const(4.1666666667e-2f), -0.5f);
   *cd = fmaf(pc, d2, 1.0f);
 }
 

@@ -19,13 +19,17 @@ struct Out {
   int64_t P;
   __device__ __forceinline__ void put(int64_t p, uint32_t code, const PointState<TP>& s) const {
     // Codes 1, 2, 4 and 7 carry no state: such lanes (rare, and usually whole
-    // satellites) take their own store path instead of a select per component.
-    if (code != 0 && code != 6) {
+    // satellites) overwrite the values with NaN in their own block, so the
+    // common path copies nothing.
+    TP x0 = s.r[0], x1 = s.r[1], x2 = s.r[2], y0 = s.v[0], y1 = s.v[1], y2 = s.v[2];
+    if (!s.ok) {
+      // The empty asm keeps the branch around this block: the block is then
+      // skipped whenever no lane of the wavefront takes it.
+      asm volatile("");
       const TP q = TP(__builtin_nan(""));
-      store(p, code, q, q, q, q, q, q);
-    } else {
-      store(p, code, s.r[0], s.r[1], s.r[2], s.v[0], s.v[1], s.v[2]);
+      x0 = q; x1 = q; x2 = q; y0 = q; y1 = q; y2 = q;
     }
+    store(p, code, x0, x1, x2, y0, y1, y2);
   }
   __device__ __forceinline__ void store(int64_t p, uint32_t code, TP x0, TP x1, TP x2, TP y0, TP y1, TP y2) const {
     if (kOff32) {

@@ -49,11 +49,20 @@ __device__ __forceinline__ GSlot lane_slot(const Slot* p) {
   return (GSlot)((uint64_t(hi) << 32) | lo);
 }
 
+// Constant-address-space view of a slot.  The record is never written while a
+// propagation kernel runs; loads through this view stay scalar loads even
+// after the kernel's own stores, which the compiler cannot otherwise prove do
+// not alias the record (a wavefront that stores and then reads the next
+// point's constants would get vector loads into VGPRs).
+typedef const __attribute__((address_space(4))) Slot* CSlot;
+
 template <class T, class P> __device__ __forceinline__ T rec_val(P sp, int k);
 template <> __device__ __forceinline__ double rec_val<double, const Slot*>(const Slot* sp, int k) { return sp->d[k]; }
 template <> __device__ __forceinline__ float rec_val<float, const Slot*>(const Slot* sp, int k) { return sp->f[k]; }
 template <> __device__ __forceinline__ double rec_val<double, GSlot>(GSlot sp, int k) { return sp->d[k]; }
 template <> __device__ __forceinline__ float rec_val<float, GSlot>(GSlot sp, int k) { return sp->f[k]; }
+template <> __device__ __forceinline__ double rec_val<double, CSlot>(CSlot sp, int k) { return sp->d[k]; }
+template <> __device__ __forceinline__ float rec_val<float, CSlot>(CSlot sp, int k) { return sp->f[k]; }
 
 // Secular constants (and the info word) through sp, periodic constants
 // through pp (the same slot, possibly seen through another address space).
@@ -82,16 +91,19 @@ __device__ __forceinline__ SatC<TS, TP> load_sat(const RecordView& rv, int64_t i
     const GSlot v = lane_slot(rv.slots + i);
     return load_from<TS, TP, GSlot, GSlot>(v, v);
   }
-  return load_from<TS, TP, const Slot*, const Slot*>(rv.slots + i, rv.slots + i);
+  const CSlot cp = (CSlot)(rv.slots + i);
+  return load_from<TS, TP, CSlot, CSlot>(cp, cp);
 }
 
 __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
   Grav g;
-  g.ke = rv.hdr[kHKe];
-  g.radius = rv.hdr[kHRadius];
-  g.vkms = rv.hdr[kHVkms];
-  g.k2 = rv.hdr[kHK2];
-  const float* f = reinterpret_cast<const float*>(rv.hdr + kHF32);
+  typedef const __attribute__((address_space(4))) double* CHdr;  // read-only while kernels run
+  const CHdr h = (CHdr)rv.hdr;
+  g.ke = h[kHKe];
+  g.radius = h[kHRadius];
+  g.vkms = h[kHVkms];
+  g.k2 = h[kHK2];
+  const __attribute__((address_space(4))) float* f = (const __attribute__((address_space(4))) float*)(h + kHF32);
   g.radius_f = f[0];
   g.vkms_f = f[1];
   g.k2_f = f[2];
@@ -145,17 +157,35 @@ template <> __device__ __forceinline__ float kepler_tol<float>() { return 1.0e-7
 
 // Newton step clamped to [-0.95, 0.95] (one median-of-three in float).  A NaN
 // step (possible only when e_L >= 1, where the point's code is 4 and its state
-// is not used) comes out finite here.
+// is not used) comes out finite here.  hi = 0.95 comes from step_bound: in
+// float it is held in a vector register for the whole iteration (the
+// median-of-three takes at most one scalar-register operand), instead of a
+// move per step.
+template <class T> __device__ __forceinline__ T step_bound();
+template <> __device__ __forceinline__ double step_bound<double>() { return 0.95; }
+template <> __device__ __forceinline__ float step_bound<float>() {
+  float x = 0.95f;
+  asm("" : "+v"(x));
+  return x;
+}
 __device__ __forceinline__ double clamp_step(double x) { return fmax(fmin(x, 0.95), -0.95); }
 __device__ __forceinline__ float clamp_step(float x) { return __builtin_amdgcn_fmed3f(x, -0.95f, 0.95f); }
+__device__ __forceinline__ double clamp_step(double x, double hi) { return fmax(fmin(x, hi), -hi); }
+__device__ __forceinline__ float clamp_step(float x, float hi) {
+  return __builtin_amdgcn_fmed3f(x, sgpr_const(-0.95f), hi);
+}
 
+// ok: whether r and v hold a state (codes 0 and 6).  Set from the control
+// flow, it stays a lane mask in scalar registers: the writer branches on it
+// without comparing the code.
 template <class TP>
 struct PointState {
   TP r[3], v[3];
+  bool ok;
 };
 
-// Returns the point's code (0, 1, 2, 4, 6 or 7).  r and v are written for
-// codes 0 and 6 only.
+// Returns the point's code (0, 1, 2, 4, 6 or 7).  r and v are written, and ok
+// set, for codes 0 and 6 only.
 //
 // Reformulations relative to the textbook order, each an identity up to
 // rounding: sin M from sin/cos of the drag-free M by a small rotation (FP64;
@@ -168,6 +198,7 @@ struct PointState {
 template <class TS, class TP>
 __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav& g, double t_abs, PointState<TP>& out) {
   using TR = Trig<TS, TP>;
+  out.ok = false;
   const uint32_t scode = c.info & kInfoCodeMask;
   if (scode) return scode;
 
@@ -230,9 +261,10 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TP dpsi = TP(0);
   const TP eb = vabs(axn) + vabs(ayn);
   const TP quad = eb < TP(0.5) ? eb : TP(1.0e30);
+  const TP hi = step_bound<TP>();
   for (int k = 0; k < 10; ++k) {
     TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
-    step = clamp_step(step);
+    step = clamp_step(step, hi);
     dpsi = dpsi + step;
     if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
     else TR::sc(U + TS(dpsi), &sp, &cp);
@@ -302,6 +334,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   out.v[0] = vk * (mvt * ux + rvdot * vx);
   out.v[1] = vk * (mvt * uy + rvdot * vy);
   out.v[2] = vk * (mvt * uz + rvdot * vz);
+  out.ok = true;
   return (mrt < TP(1)) ? 6u : 0u;
 }
 

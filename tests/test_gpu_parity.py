@@ -420,7 +420,7 @@ def test_ragged_long_lists_every_mapping(prec):
     one wavefront per tile, the persistent tile loop and the flat mapping match
     the oracle, and the two tile mappings (same 64-point chunks) agree to the
     Kepler tolerance."""
-    lens = [0, 1, 63, 64, 65, 1023, 1024, 1025, 2047, 2048, 2049, 3000, 4096, 5000, 0, 700]
+    lens = [0, 1, 63, 64, 65, 127, 128, 129, 1023, 1024, 1025, 2047, 2048, 2049, 3000, 4096, 5000, 0, 700]
     n = len(lens)
     el = synth.shell_elements(n, 31)
     off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
