@@ -197,6 +197,10 @@ __device__ __forceinline__ float sgpr_const(float x) {
   asm("" : "+s"(x));
   return x;
 }
+__device__ __forceinline__ double sgpr_const(double x) {
+  asm("" : "+s"(x));
+  return x;
+}
 
 // Float: through d^3 (sine) and d^4 (cosine); the next terms are below
 // 2.6e-9 and 2.2e-11 at |d| = 0.05, under the float rounding of the result.

@@ -145,6 +145,8 @@ __device__ __forceinline__ double sq_root(double x) { return sqrt(x); }
 __device__ __forceinline__ float sq_root(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double vmax(double x, double y) { return fmax(x, y); }
+__device__ __forceinline__ float vmax(float x, float y) { return fmaxf(x, y); }
 __device__ __forceinline__ double vabs(double x) { return fabs(x); }
 __device__ __forceinline__ float vabs(float x) { return fabsf(x); }
 __device__ __forceinline__ double arctan2(double y, double x) { return atan2(y, x); }
@@ -178,6 +180,29 @@ __device__ __forceinline__ float clamp_step(float x, float hi) {
 // ok: whether r and v hold a state (codes 0 and 6).  Set from the control
 // flow, it stays a lane mask in scalar registers: the writer branches on it
 // without comparing the code.
+// Kepler exit test for a step of size as (see the iteration in sgp4_point):
+// as < tol, or quad * as^2 < tol with quad = eb while eb < 1/2.  Double
+// evaluates it as written.  Float folds both into one comparison with a
+// per-point threshold, as < max(tol, sqrt(tol / eb)) while eb < 1/2, else
+// as < tol (the same test up to the rounding of the threshold, which can
+// only decide whether a step of about the tolerance is taken).
+template <class TP> struct KeplerExit;
+template <> struct KeplerExit<double> {
+  double quad;
+  __device__ __forceinline__ explicit KeplerExit(double eb) : quad(eb < 0.5 ? eb : 1.0e30) {}
+  __device__ __forceinline__ bool operator()(double as) const {
+    return as < kepler_tol<double>() || quad * as * as < kepler_tol<double>();
+  }
+};
+template <> struct KeplerExit<float> {
+  float thr;
+  __device__ __forceinline__ explicit KeplerExit(float eb) {
+    const float t = 3.16227766e-4f * rsq(eb);  // sqrt(1e-7 / eb)
+    thr = fmaxf(eb < 0.5f ? t : 0.0f, kepler_tol<float>());
+  }
+  __device__ __forceinline__ bool operator()(float as) const { return as < thr; }
+};
+
 template <class TP>
 struct PointState {
   TP r[3], v[3];
@@ -233,7 +258,9 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TS a_s = c.a0pp * A * A;
   TS e_s = c.e0 - Ed;
   if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
-  if (e_s < TS(1.0e-6)) e_s = TS(1.0e-6);
+  // e_s is not NaN here, so the maximum is the clamp (one instruction, the
+  // bound in scalar registers, instead of a compare and two selects)
+  e_s = vmax(e_s, sgpr_const(TS(1.0e-6)));
   // Angles stay unreduced: every one of them only enters through sin/cos,
   // whose own reduction handles any size met here.
   M = M + c.n0pp * Ld;
@@ -260,16 +287,15 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   TR::sc(U, &sp, &cp);
   TP dpsi = TP(0);
   const TP eb = vabs(axn) + vabs(ayn);
-  const TP quad = eb < TP(0.5) ? eb : TP(1.0e30);
+  const KeplerExit<TP> done(eb);
   const TP hi = step_bound<TP>();
   for (int k = 0; k < 10; ++k) {
     TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
     step = clamp_step(step, hi);
-    dpsi = dpsi + step;
+    dpsi = sizeof(TP) == 4 && k == 0 ? step : dpsi + step;  // float: no 0 + step
     if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
     else TR::sc(U + TS(dpsi), &sp, &cp);
-    const TP as = vabs(step);
-    if (__all(as < kepler_tol<TP>() || quad * as * as < kepler_tol<TP>())) break;
+    if (__all(done(vabs(step)))) break;
   }
 
   // Short-period preliminaries.
