@@ -145,6 +145,15 @@ __device__ __forceinline__ double sq_root(double x) { return sqrt(x); }
 __device__ __forceinline__ float sq_root(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// a + b t for per-satellite constants a and b.  Double keeps the product and
+// the sum apart: fused, the instruction would read both constants from scalar
+// registers, one more than it can take, and a two-register move would come
+// first.  Float fuses (one move of one register).
+__device__ __forceinline__ double lin(double a, double b, double t) {
+#pragma clang fp contract(off)
+  return a + b * t;
+}
+__device__ __forceinline__ float lin(float a, float b, float t) { return fmaf(b, t, a); }
 __device__ __forceinline__ double vmax(double x, double y) { return fmax(x, y); }
 __device__ __forceinline__ float vmax(float x, float y) { return fmaxf(x, y); }
 __device__ __forceinline__ double vabs(double x) { return fabs(x); }
@@ -230,8 +239,8 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   // Secular gravity.
   const TS t = TS(t_abs - c.epoch_min);
   const TS t2 = t * t;
-  const TS Mdf = c.M0 + c.Mdot * t;
-  const TS argpdf = c.argp0 + c.argpdot * t;
+  const TS Mdf = lin(c.M0, c.Mdot, t);
+  const TS argpdf = lin(c.argp0, c.argpdot, t);
   TS node = c.node0 + c.nodedot * t + c.nodecf * t2;
   // Secular drag.
   TS A = TS(1) - c.C1 * t;
@@ -253,20 +262,21 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
     if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
     else rotate_small(&sM, &cM, TP(dMa));
     Ed = Ed + c.bC5 * TS(sM - c.sinM0);
-    Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
+    Ld = Ld + c.t3cof * t3 + t4 * lin(c.t4cof, c.t5cof, t);
   }
   const TS a_s = c.a0pp * A * A;
-  TS e_s = c.e0 - Ed;
+  const TS e_s = c.e0 - Ed;
   if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
-  // e_s is not NaN here, so the maximum is the clamp (one instruction, the
-  // bound in scalar registers, instead of a compare and two selects)
-  e_s = vmax(e_s, sgpr_const(TS(1.0e-6)));
   // Angles stay unreduced: every one of them only enters through sin/cos,
   // whose own reduction handles any size met here.
   M = M + c.n0pp * Ld;
 
   // Long-period periodics (J3).
-  const TP a = TP(a_s), e = TP(e_s);
+  // Eccentricity floor 1e-6, taken after the rounding to TP (rounding is
+  // monotonic, so this equals rounding the floored value).  e_s is not NaN
+  // here, so the maximum is the floor: one instruction in float instead of a
+  // compare and two selects.
+  const TP a = TP(a_s), e = vmax(TP(e_s), TP(1.0e-6));
   TP sw, cw;
   TR::sc_damped(argp, &sw, &cw);
   const TP axn = e * cw;
