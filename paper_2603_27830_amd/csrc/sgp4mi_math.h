@@ -129,6 +129,19 @@ __constant__ double kSinCos64[258] = {
     0.0, -1.0,
 };
 
+// A constant held in a scalar register.  gfx9 three-operand
+// instructions take no literal, so a fused multiply-add with a literal factor
+// and a second constant costs an extra vector move; with the factor in a
+// scalar register (set by a scalar move) it is one instruction.
+__device__ __forceinline__ float sgpr_const(float x) {
+  asm("" : "+s"(x));
+  return x;
+}
+__device__ __forceinline__ double sgpr_const(double x) {
+  asm("" : "+s"(x));
+  return x;
+}
+
 // Double: y = x - 2 pi n as above, then y = j pi / 64 + b with |b| <= pi / 128
 // (a two-part pi / 64), the table's sin and cos of j pi / 64 and the series of
 // sin b through b^7 and cos b through b^6 (the next terms are below 4e-19 and
@@ -146,10 +159,18 @@ __device__ __forceinline__ void sincos_rr(double x, double* s, double* c) {
   j = j < 0 ? 0 : (j > 128 ? 128 : j);
   const double sa = kSinCos64[2 * j], ca = kSinCos64[2 * j + 1];
   const double b2 = b * b;
-  double p = fma(b2, -1.98412698412698412698e-4, 8.33333333333333333333e-3);
-  p = fma(p, b2, -1.66666666666666666667e-1);
+  // Coefficients in scalar registers (an instruction reads at most one); the
+  // first step of each polynomial holds two of them, so it is a product and a
+  // sum instead of a fused multiply-add that would need one moved into vector
+  // registers first.
+  double p, q;
+  {
+#pragma clang fp contract(off)
+    p = b2 * sgpr_const(-1.98412698412698412698e-4) + sgpr_const(8.33333333333333333333e-3);
+    q = b2 * sgpr_const(-1.38888888888888888889e-3) + sgpr_const(4.16666666666666666667e-2);
+  }
+  p = fma(p, b2, sgpr_const(-1.66666666666666666667e-1));
   const double sb = fma(p * b2, b, b);
-  double q = fma(b2, -1.38888888888888888889e-3, 4.16666666666666666667e-2);
   q = fma(q, b2, -0.5);
   const double cb = fma(q, b2, 1.0);
   *s = fma(sa, cb, ca * sb);
@@ -187,19 +208,6 @@ __device__ __forceinline__ void small_sc(double d, double* sd, double* cd) {
   pc = fma(pc, d2, k[18]);            // 1/4!
   pc = fma(pc, d2, -0.5);
   *cd = fma(pc, d2, 1.0);
-}
-
-// A float constant held in a scalar register.  gfx9 three-operand
-// instructions take no literal, so a fused multiply-add with a literal factor
-// and a second constant costs an extra vector move; with the factor in a
-// scalar register (set by a scalar move) it is one instruction.
-__device__ __forceinline__ float sgpr_const(float x) {
-  asm("" : "+s"(x));
-  return x;
-}
-__device__ __forceinline__ double sgpr_const(double x) {
-  asm("" : "+s"(x));
-  return x;
 }
 
 // Float: through d^3 (sine) and d^4 (cosine); the next terms are below
