@@ -157,7 +157,15 @@ __device__ __forceinline__ void sincos_rr(double x, double* s, double* c) {
   b = fma(-jd, 1.9135106236677394e-18, b);         // pi / 64 minus that
   int j = int(jd) + 64;
   j = j < 0 ? 0 : (j > 128 ? 128 : j);
-  const double sa = kSinCos64[2 * j], ca = kSinCos64[2 * j + 1];
+  // The clamped index is non-negative: read the pair at a 32-bit byte offset
+  // from the table's base, seen in the global address space (the load then
+  // takes the base from scalar registers and needs no 64-bit address).
+  uint32_t off = uint32_t(j) * 16u;
+  asm("" : "+v"(off));
+  typedef const __attribute__((address_space(1))) char* GBytes;
+  typedef const __attribute__((address_space(1))) double* GDouble;
+  const GDouble e = (GDouble)((GBytes)(const char*)kSinCos64 + off);
+  const double sa = e[0], ca = e[1];
   const double b2 = b * b;
   // Coefficients in scalar registers (an instruction reads at most one); the
   // first step of each polynomial holds two of them, so it is a product and a
