@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(64 * kFusedTT) fused_kernel(FusedArgs a, Out<T
   const SatC<TS, TP> c = sat_of<TS, TP>(x, linfo[sl]);
   PointState<TP> s;
   const uint32_t code = sgp4_point<TS, TP>(c, g, a.t[j], s);
-  out.put(i * a.T + j, code, s);
+  // kOff32: every point index is below 2^30 and fits 32-bit arithmetic
+  out.put(kOff32 ? int64_t(uint32_t(i) * uint32_t(a.T) + uint32_t(j)) : i * a.T + j, code, s);
 }
 
 template <class TP>

@@ -43,7 +43,10 @@ struct Out {
       st_nt(reinterpret_cast<TP*>(vb + off), y0);
       st_nt(reinterpret_cast<TP*>(vb + stride + off), y1);
       st_nt(reinterpret_cast<TP*>(vb + 2 * stride + off), y2);
-      st_nt(err + uint32_t(p), uint8_t(code));
+      // the code array seen in the global address space: the store then takes
+      // its base from scalar registers and the 32-bit offset as it is
+      typedef __attribute__((address_space(1))) uint8_t* GByte;
+      __builtin_nontemporal_store(uint8_t(code), (GByte)err + uint32_t(p));
     } else {
       st_nt(r + p, x0);
       st_nt(r + P + p, x1);

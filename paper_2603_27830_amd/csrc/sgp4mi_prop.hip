@@ -58,7 +58,10 @@ __global__ void __launch_bounds__(kBlock) dense_tile_kernel(RecordView rv, const
   const Grav g = load_grav(rv);
   PointState<TP> s;
   const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
-  out.put(int64_t(sat) * T + j, code, s);
+  // kOff32: every point index is below 2^30, so the index is formed in 32 bits
+  // (the satellite's row start on the scalar unit, one vector add)
+  const int64_t p = kOff32 ? int64_t(uint32_t(sat) * uint32_t(T) + uint32_t(j)) : int64_t(sat) * T + j;
+  out.put(p, code, s);
 }
 
 // Flat variant for short time lists: lane p -> satellite p / T, time p % T,
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) tile_once_kernel(RecordView rv, const 
   if (lane >= len) return;
   const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, sat);
   const Grav g = load_grav(rv);
-  const int64_t p = start + lane;
+  const int64_t p = kOff32 ? int64_t(uint32_t(start) + uint32_t(lane)) : start + lane;  // kOff32: p < 2^30
   PointState<TP> s;
   const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
   out.put(p, code, s);
