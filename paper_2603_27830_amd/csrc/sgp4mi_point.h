@@ -154,6 +154,8 @@ __device__ __forceinline__ double lin(double a, double b, double t) {
   return a + b * t;
 }
 __device__ __forceinline__ float lin(float a, float b, float t) { return fmaf(b, t, a); }
+__device__ __forceinline__ double vfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double vmax(double x, double y) { return fmax(x, y); }
 __device__ __forceinline__ float vmax(float x, float y) { return fmaxf(x, y); }
 __device__ __forceinline__ double vabs(double x) { return fabs(x); }
@@ -241,7 +243,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TS t2 = t * t;
   const TS Mdf = lin(c.M0, c.Mdot, t);
   const TS argpdf = lin(c.argp0, c.argpdot, t);
-  TS node = c.node0 + c.nodedot * t + c.nodecf * t2;
+  TS node = lin(c.node0, c.nodedot, t) + c.nodecf * t2;
   // Secular drag.
   TS A = TS(1) - c.C1 * t;
   TS Ed = c.bC4 * t;
@@ -333,12 +335,15 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP k1 = grav_k2<TP>(g) * inv_pl;
   const TP k2 = k1 * inv_pl;
   const TP nk = ra * ra * ra;  // n / ke = a^-3/2
-  const TP mrt = rl * (TP(1) - TP(1.5) * k2 * betal * c.c41) + TP(0.5) * k1 * c.x1 * cos2u;
+  // 1.5 c41 as c41 + c41 / 2 (one instruction reading one scalar register
+  // twice; 1.5 is no inline constant); the same single rounding of 1.5 c41
+  const TP c41h = vfma(c.c41, TP(0.5), c.c41);
+  const TP mrt = rl * (TP(1) - k2 * betal * c41h) + TP(0.5) * k1 * c.x1 * cos2u;
   const TP du = TP(-0.25) * k2 * c.x7 * sin2u;
   const TP dnode = TP(1.5) * k2 * c.cosi * sin2u;
   const TP dinc = TP(1.5) * k2 * c.cosi * c.sini * cos2u;
   const TP mvt = rdotl - nk * k1 * c.x1 * sin2u;
-  const TP rvdot = rvdotl + nk * k1 * (c.x1 * cos2u + TP(1.5) * c.c41);
+  const TP rvdot = rvdotl + nk * k1 * vfma(c.x1, cos2u, c41h);
 
   // Orientation: sin/cos of u_k = u + du, i_k = i0 + dinc, node_k = node + dnode.
   TP ssu, csu;
