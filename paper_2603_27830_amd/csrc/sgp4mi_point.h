@@ -208,7 +208,7 @@ template <> struct KeplerExit<double> {
 template <> struct KeplerExit<float> {
   float thr;
   __device__ __forceinline__ explicit KeplerExit(float eb) {
-    const float t = 3.16227766e-4f * rsq(eb);  // sqrt(1e-7 / eb)
+    const float t = __builtin_sqrtf(kepler_tol<float>()) * rsq(eb);  // sqrt(tol / eb); the root folds to a constant
     thr = fmaxf(eb < 0.5f ? t : 0.0f, kepler_tol<float>());
   }
   __device__ __forceinline__ bool operator()(float as) const { return as < thr; }
