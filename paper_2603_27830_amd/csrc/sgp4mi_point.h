@@ -188,9 +188,6 @@ __device__ __forceinline__ float clamp_step(float x, float hi) {
   return __builtin_amdgcn_fmed3f(x, sgpr_const(-0.95f), hi);
 }
 
-// ok: whether r and v hold a state (codes 0 and 6).  Set from the control
-// flow, it stays a lane mask in scalar registers: the writer branches on it
-// without comparing the code.
 // Kepler exit test for a step of size as (see the iteration in sgp4_point):
 // as < tol, or quad * as^2 < tol with quad = eb while eb < 1/2.  Double
 // evaluates it as written.  Float folds both into one comparison with a
@@ -214,6 +211,9 @@ template <> struct KeplerExit<float> {
   __device__ __forceinline__ bool operator()(float as) const { return as < thr; }
 };
 
+// ok: whether r and v hold a state (codes 0 and 6).  Set from the control
+// flow, it stays a lane mask in scalar registers: the writer branches on it
+// without comparing the code.
 template <class TP>
 struct PointState {
   TP r[3], v[3];
