@@ -35,12 +35,23 @@
 //  * J3/J2 is taken as 0 when J3 == 0 (two-body configuration); J3 != 0 with
 //    J2 == 0 is rejected.
 //
-// Agreement of these coefficients with the published model is parity
-// unpinned: no verification vectors are available.  The structure is pinned by
-// the CPU tests (two-body closed form, node equivariance, Kepler residual,
-// finite differences, radius bounds, first-order J2 rates, numerical
-// integration of the J2 field over one orbit, term-group toggles, crafted
-// error codes).
+// What pins it (CPU tests, each against something other than this file): the
+// two-body closed form, node equivariance, Kepler residuals, finite
+// differences, radius bounds, first-order J2 rates and Brouwer's second-order
+// (J2^2) secular rates in the near-circular limit, the J2 field integrated over
+// one orbit and the node over days, Lagrange's equations for the J4 rates and
+// the J3 long-period terms, the drag coefficients as the power-law decay series
+// and as Gauss-equation orbit averages (C2, C4, C5, the periodic drag term of M
+// and w, the J3-drag perigee rate), the node drag term along the decaying
+// orbit, the mean elements at epoch, term-group toggles, crafted error codes
+// and a hand count of the operations.
+//
+// Parity unpinned (model definitions no available pin reaches): the J2 bracket
+// of C4, the eccentricity factor (beta0^2) of the drag node term, the
+// low-perigee density parameter (156 km / 98 km branch), the 220 km
+// simplified-drag switch, the e0 > 1e-4 gate and the 1.5e-12 guard; and, as a
+// whole, numeric agreement with the published model's own verification
+// vectors, which are not available here.
 //
 // The scalar type is a template parameter: double for values, Dual (seven
 // forward-mode tangents) for the derivative oracle, OpCount to count the

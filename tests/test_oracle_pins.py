@@ -424,6 +424,31 @@ def test_eccentric_drag_coefficients_are_orbit_averages(alt, e):
     assert abs(ci["C4"][0] / C4 - 1) < 1e-12
 
 
+@pytest.mark.parametrize("alt,e,inc", [(500.0, 1e-3, 0.3), (500.0, 0.01, 0.93), (800.0, 0.05, 1.2),
+                                        (1500.0, 0.08, 1.7), (400.0, 1e-4, 0.0), (300.0, 2e-3, 2.5)])
+def test_drag_j2_term_is_the_density_at_the_shifted_mean_radius(alt, e, inc):
+    """With J2 on, the model's short-period radius correction has a secular part,
+    -1.5 k2 beta c41 r (k2 = J2 / (2 p^2)), so the mean radius sits lower by
+    dr = 0.75 J2 beta c41 a / p^2 and the density there is higher.  The J2 term of
+    C2 (C2 with J2 minus the J2-free orbit average, itself pinned above) must be
+    the first-order change of the orbit-averaged density <((q0-s)/(r + dr - s))^4>
+    times n a Q4 xi^4 (the derivative taken numerically in dr), to O(e^2)."""
+    a0 = (RE + alt) / RE
+    el = np.array([[KE * a0 ** -1.5], [e], [inc], [0.1], [0.2], [0.3], [1e-4], [0.0]])
+    ci = oracle.init_constants(el)
+    a, n, xi, eta, q4, s = (ci[k][0] for k in ("a0pp", "n0pp", "xi", "eta", "q4", "s"))
+    assert ci["isimp"][0] == 0
+    c41 = 3 * math.cos(inc) ** 2 - 1
+    b = math.sqrt(1 - e * e)
+    p = a * b * b
+    C2_free = n * a * q4 * xi ** 4 * _orbit_average(lambda E: (1 - eta * np.cos(E)) ** -4 * (1 + 2 * e * np.cos(E)))
+    dr = -0.75 * J2 * c41 * b * a / p ** 2
+    h = 1e-4
+    dens = lambda E, x: ((a - s) / (a * (1 - e * np.cos(E)) + x - s)) ** 4
+    lin = n * a * q4 * xi ** 4 * (_orbit_average(lambda E: dens(E, h * dr)) - _orbit_average(lambda E: dens(E, 0.0))) / h
+    assert abs((ci["C2"][0] - C2_free) / lin - 1) <= 2 * e * e + 1e-4
+
+
 @pytest.mark.parametrize("e", [1e-4, 3e-4, 1e-3])
 def test_periodic_drag_coefficient_leading_order(e):
     """C5 multiplies sin M in the drag change of e, so C5 n must be the cos M
@@ -458,6 +483,219 @@ def test_drag_decay_applied_in_propagation():
     assert np.max(np.abs(dM)) < 1e-9
     A = 1 - ci["C1"][sat] * t - ci["D2"][sat] * t ** 2 - ci["D3"][sat] * t ** 3 - ci["D4"][sat] * t ** 4
     assert np.allclose(d["a"], ci["a0pp"][sat] * A * A, rtol=1e-14)
+
+
+# -------------------------------------------- second-order secular rates --
+def _brouwer_second_order_rates(n, a, e, inc):
+    """Brouwer's (1959) secular rates of the mean anomaly, argument of perigee and
+    node to second order in J2 (J3 = J4 = 0), in his variables: eta = sqrt(1 - e^2),
+    theta = cos i, g2 = J2 / (2 p^2), p = a eta^2 (earth radii), n the mean motion:
+      l' = n [1 + 3/2 g2 eta (3 th^2 - 1)
+              + 3/32 g2^2 eta (-15 + 16 eta + 25 eta^2 + (30 - 96 eta - 90 eta^2) th^2
+                               + (105 + 144 eta + 25 eta^2) th^4)]
+      g' = n [3/2 g2 (5 th^2 - 1)
+              + 3/32 g2^2 (-35 + 24 eta + 25 eta^2 + (90 - 192 eta - 126 eta^2) th^2
+                           + (385 + 360 eta + 45 eta^2) th^4)]
+      h' = n [-3 g2 th + 3/8 g2^2 ((-5 + 12 eta + 9 eta^2) th + (-35 - 36 eta - 5 eta^2) th^3)]"""
+    eta = math.sqrt(1 - e * e)
+    th = math.cos(inc)
+    g2 = J2 / (2 * (a * eta * eta) ** 2)
+    ldot = n * (1 + 1.5 * g2 * eta * (3 * th ** 2 - 1)
+                + 3 / 32 * g2 ** 2 * eta * (-15 + 16 * eta + 25 * eta ** 2 + (30 - 96 * eta - 90 * eta ** 2) * th ** 2
+                                             + (105 + 144 * eta + 25 * eta ** 2) * th ** 4))
+    gdot = n * (1.5 * g2 * (5 * th ** 2 - 1)
+                + 3 / 32 * g2 ** 2 * (-35 + 24 * eta + 25 * eta ** 2 + (90 - 192 * eta - 126 * eta ** 2) * th ** 2
+                                      + (385 + 360 * eta + 45 * eta ** 2) * th ** 4))
+    hdot = n * (-3 * g2 * th + 3 / 8 * g2 ** 2 * ((-5 + 12 * eta + 9 * eta ** 2) * th
+                                                   + (-35 - 36 * eta - 5 * eta ** 2) * th ** 3))
+    return ldot, gdot, hdot, n * g2 * g2
+
+
+@pytest.mark.parametrize("inc", [0.1, 0.5, 0.96, 1.1, 1.5, 1.9, 2.6, 3.0])
+@pytest.mark.parametrize("alt", [300.0, 800.0, 2500.0])
+def test_j2_squared_secular_rates_are_brouwers_near_circular_limit(inc, alt):
+    """J2 alone: the model's secular rates of M, the argument of perigee and the node
+    are Brouwer's first- plus second-order (J2^2) secular rates taken at eta -> 1
+    (the near-circular limit the model's polynomials in cos i keep).  At e = 1e-6
+    the eta-dependence is below 1e-11 of the J2^2 parts, so each rate must agree
+    to 1e-7 of its J2^2 part (a 10% change of any J2^2 coefficient is 1e-2)."""
+    grav = (MU, RE, J2, 0.0, 0.0)
+    a0 = (RE + alt) / RE
+    el = np.array([[KE * a0 ** -1.5], [1e-6], [inc], [0.3], [0.7], [0.1], [0.0], [0.0]])
+    ci = oracle.init_constants(el, grav)
+    n, a, e = ci["n0pp"][0], ci["a0pp"][0], 1e-6
+    ldot, gdot, hdot, scale = _brouwer_second_order_rates(n, a, e, inc)
+    assert abs(ci["Mdot"][0] - ldot) <= 1e-7 * scale
+    assert abs(ci["argpdot"][0] - gdot) <= 1e-7 * scale
+    assert abs(ci["nodedot"][0] - hdot) <= 1e-7 * scale
+
+
+def _j2_rhs_many(_, y):
+    """J2-only equations of motion of several independent orbits stacked in y (km, km/s)."""
+    Y = y.reshape(-1, 6)
+    x, yy, z = Y[:, 0], Y[:, 1], Y[:, 2]
+    r2 = x * x + yy * yy + z * z
+    r = np.sqrt(r2)
+    zr2 = z * z / r2
+    k = 1.5 * J2 * MU * RE * RE / (r2 * r2 * r)
+    out = np.empty_like(Y)
+    out[:, :3] = Y[:, 3:]
+    out[:, 3] = -MU * x / (r2 * r) - k * x * (1 - 5 * zr2)
+    out[:, 4] = -MU * yy / (r2 * r) - k * yy * (1 - 5 * zr2)
+    out[:, 5] = -MU * z / (r2 * r) - k * z * (3 - 5 * zr2)
+    return out.ravel()
+
+
+def _osculating_node(r, v):
+    h = np.cross(r, v, axis=0)
+    return np.unwrap(np.arctan2(h[0], -h[1]))
+
+
+def test_j2_squared_node_rate_follows_the_j2_field():
+    """Integrate the J2-only equations of motion for five days from the model's epoch
+    state (near-circular LEO, four inclinations) and follow the orbit plane: the
+    osculating node of the integrated orbit and of the model drift apart by less
+    than 3% of what the model's J2^2 node term accumulates (measured: under 1%);
+    the term itself is ~1e-3 of the node rate and moves the node by 0.2-2 km over
+    the five days, so a 10% change of its coefficients shows."""
+    grav = (MU, RE, J2, 0.0, 0.0)
+    incs = [0.3, 0.93, 1.2, 1.7]
+    n0 = math.sqrt(MU / (RE + 550.0) ** 3) * 60.0
+    el = np.zeros((8, len(incs)))
+    el[0], el[1], el[2], el[3], el[4], el[5] = n0, 2e-4, incs, 0.3, 1.0, 0.5
+    ts = np.linspace(0.0, 5 * 1440.0, 1001)
+    r, v, err = oracle.propagate(el, ts, grav)
+    assert np.all(err == 0)
+    y0 = np.concatenate([r[:, :, 0].T, v[:, :, 0].T], axis=1).ravel()
+    sol = solve_ivp(_j2_rhs_many, (0.0, ts[-1] * 60.0), y0, method="DOP853", rtol=1e-12, atol=1e-9,
+                    t_eval=ts * 60.0)
+    Y = sol.y.reshape(len(incs), 6, -1)
+    ci = oracle.init_constants(el, grav)
+    A = np.vstack([np.ones_like(ts), ts]).T
+    for k, inc in enumerate(incs):
+        d = _osculating_node(Y[k, :3], Y[k, 3:]) - _osculating_node(r[:, k, :], v[:, k, :])
+        drift = np.linalg.lstsq(A, d, rcond=None)[0][1]
+        th, p, n = math.cos(inc), ci["a0pp"][k] * (1 - 2e-4 ** 2), ci["n0pp"][k]
+        T1 = 1.5 * J2 * n / p ** 2
+        j22 = 0.5 * (0.5 * T1 * J2 / p ** 2) * (4 - 19 * th * th) * th  # Brouwer's J2^2 node term at eta = 1
+        assert abs(drift) < 0.03 * abs(j22), (inc, drift / j22)
+
+
+# ------------------------------------------------------------- epoch state --
+def test_mean_elements_at_epoch_are_the_element_set():
+    """At the epoch (time since epoch 0) every secular, drag and drag-periodic term
+    vanishes: the propagated mean anomaly, argument of perigee, node, eccentricity
+    and semi-major axis are the element set's (M0, w0, node0, e0, a0''), exactly.
+    This fixes the epoch offsets of the drag periodics (dM0 = (1 + eta cos M0)^3,
+    sin M0) and the sign of every term that must cancel there."""
+    el = synth.shell_elements(64, 21, epoch_days=0.0)
+    el[6] = np.where(np.arange(64) % 2 == 0, 3e-4, -2e-4)
+    el[1] = np.linspace(2e-4, 0.02, 64)
+    ci = oracle.init_constants(el)
+    assert np.all(ci["isimp"] == 0) and np.all(ci["Mcof"] != 0)
+    _, _, err, d = oracle.propagate_points(el, np.arange(64), np.zeros(64), detail=True)
+    assert np.all(err == 0)
+    assert np.array_equal(d["M"], el[5])
+    assert np.array_equal(d["argp"], el[4])
+    assert np.array_equal(d["node"], el[3])
+    assert np.array_equal(d["e"], el[1])
+    assert np.array_equal(d["a"], ci["a0pp"])
+
+
+# ------------------------------------------------- drag on the perigee --
+def _gauss_drag_average(a, e, s, q4, bstar, f, N=4096):
+    """Mean over the mean anomaly of f(M, E, true anomaly, r, v, D) on a uniform M
+    grid, for drag along the velocity with the model's power-law density
+    D = B* ((q0 - s)/(r - s))^4 (lengths in earth radii, time in minutes)."""
+    M = np.arange(N) * (2 * math.pi / N)
+    E = M.copy()
+    for _ in range(60):
+        E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+    r = a * (1 - e * np.cos(E))
+    nu = 2 * np.arctan2(math.sqrt(1 + e) * np.sin(E / 2), math.sqrt(1 - e) * np.cos(E / 2))
+    vel = np.sqrt(KE * KE * (2 / r - 1 / a))
+    D = bstar * q4 / (r - s) ** 4
+    return float(np.mean(f(M, E, nu, r, vel, D)))
+
+
+@pytest.mark.parametrize("alt,e", [(400.0, 2e-4), (400.0, 5e-4), (500.0, 1e-3), (300.0, 1e-3), (600.0, 2e-3)])
+def test_drag_perigee_periodic_follows_gauss_equations(alt, e):
+    """J2 = J3 = J4 = 0: drag along the velocity turns the perigee by Gauss's
+    dw/dt = 2 sin(f) T / (e v), T = -D v^2, an odd function of M whose integral over
+    the orbit is the model's periodic drag term: the model moves w by -dM and M by
+    +dM, dM = Mcof ((1 + eta cos M)^3 - (1 + eta cos M0)^3).  The cos M Fourier
+    coefficient of the model's -dM(M), read from the propagated argument of perigee
+    over one orbit, times a0'' must equal that of the integrated Gauss rate to
+    O(eta^2, e).  (The published coefficient carries the earth radius where the
+    averaged equations carry the semi-major axis: a reading of the model.)"""
+    grav = (MU, RE, 0.0, 0.0, 0.0)
+    a0 = (RE + alt) / RE
+    bstar = 1e-4
+    el = np.array([[KE * a0 ** -1.5], [e], [0.9], [0.1], [0.2], [0.3], [bstar], [0.0]])
+    ci = oracle.init_constants(el, grav)
+    a, n, eta, s, q4 = ci["a0pp"][0], ci["n0pp"][0], ci["eta"][0], ci["s"][0], ci["q4"][0]
+    assert ci["isimp"][0] == 0
+    N = 512
+    Mk = 0.3 + 2 * math.pi * np.arange(N) / N
+    _, _, err, d = oracle.propagate_points(el, np.zeros(N, dtype=np.int64), (Mk - 0.3) / n, grav=grav, detail=True)
+    assert np.all(err == 0)
+    dw_model = -((0.2 - d["argp"] + math.pi) % (2 * math.pi) - math.pi)  # -dM
+    A1_model = 2 * np.mean(dw_model * np.cos(Mk))
+    # the Gauss rate per unit mean anomaly, dw/dM = -2 D v sin f / (e n); its integral's
+    # cos M coefficient is minus the rate's sin M coefficient
+    b1 = 2 * _gauss_drag_average(a, e, s, q4, bstar,
+                                 lambda M, E, nu, r, vel, D: -2 * D * vel * np.sin(nu) / (e * n) * np.sin(M))
+    assert abs(A1_model * a / (-b1) - 1) <= 3 * eta ** 2 + 2 * e, A1_model * a / (-b1)
+
+
+@pytest.mark.parametrize("alt,e,inc", [(300.0, 1e-3, 0.93), (400.0, 1e-3, 1.7), (400.0, 5e-4, 1.2),
+                                        (500.0, 2e-3, 0.4)])
+def test_drag_perigee_rate_from_the_j3_eccentricity_offset(alt, e, inc):
+    """The model's secular drag rotation of the perigee, -B* C3 cos w0 (C3 ~ J3/J2):
+    J3's long-period term offsets the orbit's eccentricity vector from the mean one
+    by (0, delta), delta = aycof / p (pinned by the J3 tests), and drag shrinks the
+    orbit's own eccentricity vector along itself at Gauss's orbit-averaged rate
+    de/dt = <-2 D v (e + cos f)>.  The mean vector then turns at
+    dw/dt = (e_mean x de/dt) / e^2, which must equal the model's rate times a0''
+    (the same earth-radius reading as the periodic term) to 3%; the difference is
+    the decay's velocity-factor part and its O(eta^2) terms, which the published
+    coefficient omits (~1-2% here), whereas a 10% coefficient change or a sign,
+    sin i or cos w mistake fails."""
+    a0 = (RE + alt) / RE
+    bstar = 1e-4
+    for w in (0.0, 0.7, 2.5, 4.0):
+        el = np.array([[KE * a0 ** -1.5], [e], [inc], [0.1], [w], [0.3], [bstar], [0.0]])
+        ci = oracle.init_constants(el)
+        a, s, q4 = ci["a0pp"][0], ci["s"][0], ci["q4"][0]
+        assert ci["isimp"][0] == 0
+        delta = ci["aycof"][0] / (a * (1 - e * e))
+        kx, ky = e * math.cos(w), e * math.sin(w) + delta
+        ek = math.hypot(kx, ky)
+        edot = _gauss_drag_average(a, ek, s, q4, bstar, lambda M, E, nu, r, vel, D: -2 * D * vel * (ek + np.cos(nu)))
+        wdot = (e * math.cos(w) * edot * ky / ek - e * math.sin(w) * edot * kx / ek) / (e * e)
+        model = -ci["argpcof"][0]
+        assert abs(wdot / (model * a) - 1) < 0.03, (w, wdot / (model * a))
+
+
+def test_drag_perigee_rotation_leaves_the_mean_longitude():
+    """The J3-drag term turns the perigee, not the satellite: with J3 on and off the
+    propagated mean longitude L = M + w + node is the same (the term enters M and w
+    with opposite signs), while w differs by a rate constant in time."""
+    el = synth.shell_elements(16, 23, epoch_days=0.0)
+    el[1] = 2e-3
+    el[6] = 5e-4
+    no_j3 = (MU, RE, J2, 0.0, J4)
+    sat = np.repeat(np.arange(16), 3)
+    t = np.tile([600.0, 1800.0, 3600.0], 16)
+    _, _, e1, d1 = oracle.propagate_points(el, sat, t, detail=True)
+    _, _, e0, d0 = oracle.propagate_points(el, sat, t, grav=no_j3, detail=True)
+    assert np.all(e1 == 0) and np.all(e0 == 0)
+    dL = (d1["L"] - d0["L"] + math.pi) % (2 * math.pi) - math.pi
+    assert np.max(np.abs(dL)) < 1e-12
+    dw = ((d1["argp"] - d0["argp"] + math.pi) % (2 * math.pi) - math.pi) / t
+    rate = dw.reshape(16, 3)
+    assert np.all(np.abs(rate - rate[:, :1]) <= 1e-9 * np.abs(rate[:, :1]) + 1e-18)
+    assert np.all(rate[:, 0] != 0)
 
 
 # ------------------------------------------------- numerical-integration pin --
@@ -530,6 +768,47 @@ def test_long_period_j3_term_follows_the_zonal_field(inc_deg):
                     method="DOP853", rtol=1e-11, atol=1e-8, t_eval=ts * 60.0)
     dr = np.abs(np.linalg.norm(sol.y[:3], axis=0) - np.linalg.norm(r[:, 0, 1:], axis=0)).max()
     assert dr < 0.15, dr
+
+
+# ------------------------------------------------------- operation count --
+# Operations of one point of the model (full drag, K Kepler iterations), counted by
+# hand from the steps P1-P9: (add/sub, mul, div, sqrt, sin/cos, atan2, floor).
+# Products of the time since epoch with itself are not model operations on the
+# state and are not counted; a reduction mod 2 pi is one floor, two products and a
+# difference; negation is free.
+_HAND_COUNT = {
+    "P1 secular M, w, node (+ node t^2)": (4, 4, 0, 0, 0, 0, 0),
+    "P2 drag: A, Ed, Ld, dw, dM (1 cos), M, w, D2-D4, C5 (1 sin), t3-t5 cofs": (15, 17, 0, 0, 2, 0, 0),
+    "P3 a = a0 A^2, n = ke / a^1.5, e = e0 - Ed": (1, 3, 1, 1, 0, 0, 0),
+    "P4 M + n0 Ld, L = M + w + node, three reductions": (6, 7, 0, 0, 0, 0, 3),
+    "P5 axN, tau, ayN, L_T": (3, 7, 1, 0, 2, 0, 0),
+    "P6 U (one reduction) and the final sin/cos of psi": (2, 2, 0, 0, 2, 0, 1),
+    "P7 ecE, esE, eL^2, pL, r, rdot, rfdot, betaL, w, sin u, cos u, u, sin 2u, cos 2u": (12, 17, 5, 3, 0, 1, 0),
+    "P8 k1, k2 and the six short-period corrections": (8, 24, 4, 0, 0, 0, 0),
+    "P9 orientation (6 sin/cos), r and v": (7, 27, 0, 0, 6, 0, 0),
+}
+_HAND_PER_KEPLER_STEP = (6, 4, 1, 0, 2, 0, 0)  # sin psi, cos psi, the Newton step, psi + step
+
+
+@pytest.mark.parametrize("n0,e", [(0.0654, 1.5e-4), (0.0654, 1e-3), (0.0654, 0.05), (0.04, 0.3)])
+def test_operation_count_matches_a_hand_count(n0, e):
+    """The operation count the benchmark's algorithmic-rate figure comes from (the
+    oracle run with a counting scalar) equals the hand count of the model's steps
+    for the number of Kepler iterations the point takes (233 operations, not
+    counting the 4 floors, at 3 iterations)."""
+    el = np.array([n0, e, 0.93, 0.4, 1.1, 2.0, 2e-4, 0.0])
+    ci = oracle.init_constants(el[:, None])
+    assert ci["isimp"][0] == 0
+    _, _, err, d = oracle.propagate_points(el[:, None], np.zeros(1, dtype=np.int64), np.array([777.0]), detail=True)
+    assert err[0] == 0
+    K = int(d["iters"][0])
+    want = np.sum(np.array(list(_HAND_COUNT.values())), axis=0) + K * np.array(_HAND_PER_KEPLER_STEP)
+    got = oracle.count_ops(el, 777.0)
+    keys = ["add", "mul", "div", "sqrt", "trig", "atan2", "floor"]
+    assert [int(got[k]) for k in keys] == [int(x) for x in want], (K, got)
+    assert int(got["cbrt"]) == 0
+    if K == 3:
+        assert sum(int(got[k]) for k in keys[:6]) == 233
 
 
 # ------------------------------------------------------------- error codes --
