@@ -32,8 +32,10 @@
  *   - Point codes: 0 ok; 1 mean eccentricity outside [-0.001, 1) (or outside
  *     [0, 1) at epoch); 2 recovered mean motion not positive; 4 semi-latus
  *     rectum negative; 6 decayed (radius below one earth radius; the state is
- *     still written); 7 deep-space element set, not propagated.  Codes 1, 2, 4
- *     and 7 write NaN to r and v.
+ *     still written); 7 deep-space element set, not propagated; 8 ragged
+ *     point that the offsets place in no satellite's list (malformed offsets
+ *     given to sgp4_propagate_ragged without a plan).  Codes 1, 2, 4, 7 and 8
+ *     write NaN to r and v.
  */
 #ifndef SGP4MI_H
 #define SGP4MI_H
@@ -101,16 +103,20 @@ int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, in
  *                           (workgroups of independent wavefronts); needs
  *                           SGP4_CFG_SCALAR_CONSTS and no SGP4_CFG_PERSISTENT
  *                           (else SGP4_E_ARG), and n * ceil(T / 64) < 2^32
- *                           (else SGP4_E_SIZE);
+ *                           tiles in a grid of fewer than 2^32 lanes (else
+ *                           SGP4_E_SIZE);
  *   SGP4_CFG_FLAT           one lane per point in point order, whatever T, so
  *                           short time lists leave no lane idle; each lane
  *                           reads its satellite's constants (vector loads);
  *                           excludes the three flags above (else SGP4_E_ARG)
- *                           and needs ceil(n * T / block) < 2^31 (else
- *                           SGP4_E_SIZE).
+ *                           and needs ceil(n * T / block) < 2^31 workgroups
+ *                           and fewer than 2^32 lanes (else SGP4_E_SIZE).
+ * Without TILES, PERSISTENT or FLAT the grid is satellites x time blocks and
+ * needs n * block < 2^32 (else SGP4_E_SIZE): a dispatch spans at most 2^32 - 1
+ * lanes per grid dimension.
  * The default is FLAT with 256-wide workgroups for T < 64, else TILES with
- * scalar constants (256-wide for FP64, 512 for the float paths), else the
- * satellite-by-time grid.  Codes are identical for every configuration and
+ * scalar constants (256-wide for FP64, 512 for the float paths) while they
+ * fit, else PERSISTENT with 512-wide workgroups, four per compute unit.  Codes are identical for every configuration and
  * states agree to rounding (the Kepler loop ends when all lanes of a
  * wavefront have converged). */
 enum { SGP4_CFG_SCALAR_CONSTS = 0x10000, SGP4_CFG_PERSISTENT = 0x20000, SGP4_CFG_TILES = 0x40000,
@@ -127,7 +133,8 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
  * propagates them (no record in device memory; ws untouched); for T > 32 with
  * ws (device, at least sgp4_consts_bytes(n) bytes, else SGP4_E_WORKSPACE) it
  * runs sgp4_init into ws and sgp4_propagate, and ws then holds the records.
- * A fused launch covers T <= 1,048,560 (else SGP4_E_WORKSPACE when ws is NULL).
+ * A fused launch covers T <= 1,048,560 and n * min(T, 16) < 2^32 (else
+ * SGP4_E_WORKSPACE when ws is NULL and T is too large, SGP4_E_SIZE when n is).
  * Results equal the two-stage path's: codes identical, states to rounding.
  * n = 0 or T = 0 writes nothing. */
 int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
@@ -223,10 +230,17 @@ enum { SGP4_PLAN_AUTOTUNE = 1, SGP4_PLAN_GRAPH = 2 };
  * offsets: device int64 [n+1] with offsets[0] = 0, non-decreasing,
  * offsets[n] = nnz.  t: device float64 [nnz].  r, v: [3][nnz]; err: [nnz].
  * plan: NULL (one launch, a wavefront per 64 consecutive points, whose lanes
- * locate their satellites by binary search of the offsets; the offsets are not
- * checked on the host) or
- * a plan created for exactly these buffers (launches its tuned kernel
- * directly, without the graph). */
+ * locate their satellites by a search of the offsets) or a plan created for
+ * exactly these buffers (launches its tuned kernel directly, without the
+ * graph; the offsets must be those the plan checked).
+ * Without a plan the offsets are not read on the host, so malformed offsets
+ * are not reported as SGP4_E_OFFSETS.  They never cause a read outside
+ * offsets[0..n], t[0..nnz) or the record, nor a write outside the outputs:
+ * every point p is propagated with a satellite i whose list holds it
+ * (offsets[i] <= p < offsets[i+1]; the only one for well-formed offsets), or,
+ * where the search finds none (offsets[0] > p, offsets[n] <= p, or a
+ * decreasing step the search lands on), gets code 8 and NaN.  A plan checks
+ * the offsets once and returns SGP4_E_OFFSETS for malformed ones. */
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,
                           int precision, void* r, void* v, uint8_t* err, const sgp4_plan* plan, void* stream);
 
@@ -271,7 +285,8 @@ void sgp4_plan_destroy(sgp4_plan* plan);
  * consts); gr and gv device [3][n*T] of double
  * (FP64) or float (FP32_MIXED), gv nullable (zero).  Points with codes 1, 2,
  * 4, 7 contribute nothing.  gelem: device float64 [7][n].  FP32 is rejected
- * (SGP4_E_PRECISION). */
+ * (SGP4_E_PRECISION).  One 256-lane workgroup per satellite: n < 2^24 (else
+ * SGP4_E_SIZE). */
 int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
              const void* gr, const void* gv, double* gelem, void* stream);
 
@@ -282,7 +297,7 @@ int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t,
  * jac: device float64 [6][7][n*T], written in full; NaN where the point's
  * code is 1, 2, 4 or 7.  elem, consts, t as for sgp4_vjp.  Computed by one
  * reverse sweep per state component, so it costs about six VJPs.  FP32 is
- * rejected (SGP4_E_PRECISION). */
+ * rejected (SGP4_E_PRECISION).  n < 2^24 as for sgp4_vjp. */
 int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
                   double* jac, void* stream);
 

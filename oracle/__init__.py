@@ -54,6 +54,7 @@ def lib():
         L.oracle_propagate.argtypes = [_dp, ctypes.c_int64, _dp, _dp, ctypes.c_int64, _dp, _dp, _u8p, ctypes.c_int]
         L.oracle_propagate_ragged.argtypes = [_dp, ctypes.c_int64, _dp, _i64p, _dp, ctypes.c_int64, _dp, _dp, _u8p,
                                               ctypes.c_int]
+        L.oracle_codes_ragged.argtypes = [_dp, ctypes.c_int64, _dp, _i64p, _dp, ctypes.c_int64, _u8p, ctypes.c_int]
         L.oracle_propagate_points.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _i64p, _dp, _dp, _dp, _u8p, _dp]
         L.oracle_init.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
         L.oracle_jacobian_points.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, _u8p]
@@ -102,6 +103,17 @@ def propagate_ragged(elem, offsets, t, grav=None, nthreads=1):
     _check(lib().oracle_propagate_ragged(_p(g), n, _p(elem), _p(offsets, _i64p), _p(t), nnz, _p(r), _p(v),
                                          _p(err, _u8p), int(nthreads)))
     return r, v, err
+
+
+def codes_ragged(elem, offsets, t, grav=None, nthreads=1):
+    """CSR lists, codes only: err[nnz] (states computed and dropped)."""
+    elem = _f64(elem); t = _f64(t); g = _grav(grav)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n, nnz = elem.shape[1], t.shape[0]
+    err = np.empty(nnz, np.uint8)
+    _check(lib().oracle_codes_ragged(_p(g), n, _p(elem), _p(offsets, _i64p), _p(t), nnz, _p(err, _u8p),
+                                     int(nthreads)))
+    return err
 
 
 def propagate_points(elem, sat, t, grav=None, detail=False):

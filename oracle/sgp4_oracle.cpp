@@ -516,6 +516,29 @@ int oracle_propagate_ragged(const double* grav, int64_t n, const double* elem, c
   return 0;
 }
 
+// Codes only, over CSR lists (the same definition as oracle_propagate_ragged;
+// the states are computed and dropped), for code checks of batches whose
+// states would not fit in host memory.
+int oracle_codes_ragged(const double* grav, int64_t n, const double* elem, const int64_t* offsets,
+                        const double* t, int64_t nnz, uint8_t* err, int nthreads) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  if (n < 0 || nnz < 0 || offsets[0] != 0 || offsets[n] != nnz) return -3;
+  for (int64_t i = 0; i < n; ++i) if (offsets[i + 1] < offsets[i]) return -3;
+  parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      double el[kNElem], epoch;
+      load_elements(elem, n, i, el, &epoch);
+      Sat<double> c = sgp4_init<double>(g, el, epoch);
+      for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p) {
+        double rr[3], vv[3];
+        err[p] = uint8_t(sgp4_point(g, c, t[p] - 1440.0 * epoch, rr, vv, nullptr));
+      }
+    }
+  });
+  return 0;
+}
+
 // Individual (satellite, time) points: sat[k] indexes the n element sets, t[k]
 // is minutes after the reference.  Optional detail[k][kD_COUNT] intermediates.
 int oracle_propagate_points(const double* grav, int64_t n, const double* elem, int64_t npts, const int64_t* sat,

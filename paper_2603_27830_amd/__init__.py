@@ -264,7 +264,8 @@ def parse_text(text, fmt="tle", ref_jd=None, threads=0):
 
 def propagate_ragged(rec: Record, offsets: torch.Tensor, t: torch.Tensor, precision="fp64",
                      plan: Optional[RaggedPlan] = None, out=None):
-    """CSR lists: returns r [3, nnz], v [3, nnz], err [nnz]."""
+    """CSR lists: returns r [3, nnz], v [3, nnz], err [nnz].  Without a plan the
+    offsets are not checked: a point they place in no list gets code 8."""
     p = _prec(precision)
     _need(offsets, torch.int64, "offsets", rec.device)
     _need(t, torch.float64, "t", rec.device)

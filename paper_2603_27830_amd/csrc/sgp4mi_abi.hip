@@ -21,7 +21,9 @@ hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* c
                        hipStream_t s);
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
                         uint8_t* err, int block, bool vec, unsigned grid, bool tiles, bool flat, hipStream_t s);
-bool dense_tiles_fit(int64_t n, int64_t T);
+bool dense_tiles_fit(int64_t n, int64_t T, int block);
+bool dense_grid_fits(int64_t n, int block);
+bool fused_fits(int64_t n, int64_t T);
 bool dense_flat_fits(int64_t n, int64_t T, int block);
 hipError_t launch_fused(int precision, const double g[5], int64_t n, const double* elem, const double* t, int64_t T,
                         void* r, void* v, uint8_t* err, uint8_t* user_flags, hipStream_t s);
@@ -54,15 +56,19 @@ constexpr int64_t kFlatBelowT = 64;
 // kernel (initialisation kept on chip); longer ones, given a record
 // workspace, run initialisation and the default dense launch.
 constexpr int64_t kFusedMaxT = 32;
+// Workgroup size of the VJP and Jacobian kernels (one workgroup per satellite).
+constexpr uint64_t kVjpLanes = 256;
 // Default dense launch: one wavefront per 64-time tile with the satellite's
 // constants in scalar registers, in 256-wide workgroups for FP64 and 512-wide
 // for the float paths (fastest of the mapping x workgroup x residency sweep on
 // MI355X at 9,341 x 1,000); the satellite-by-time grid where the tiles do not
-// fit 32-bit indices.
+// fit the launch limits, and beyond that a persistent grid of 512-wide
+// workgroups (four per compute unit) looping over the tiles.
 int default_dense(int precision, int64_t n, int64_t T) {
   if (T < kFlatBelowT && dense_flat_fits(n, T, 256)) return 256 | SGP4_CFG_FLAT;
-  if (!dense_tiles_fit(n, T)) return 512 | SGP4_CFG_SCALAR_CONSTS;
-  return (precision == SGP4_FP64 ? 256 : 512) | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_TILES;
+  const int block = precision == SGP4_FP64 ? 256 : 512;
+  if (!dense_tiles_fit(n, T, block)) return 512 | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | SGP4_CFG_PER_CU(4);
+  return block | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_TILES;
 }
 
 int check_gravity(const double* g) {
@@ -236,8 +242,9 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
   if (flat && (persistent || tiles || scalar || per_cu != 0)) return SGP4_E_ARG;
   if (n == 0 || T == 0) return SGP4_OK;
   if (!consts || !t || !r || !v || !err) return SGP4_E_ARG;
-  if (tiles && !dense_tiles_fit(n, T)) return SGP4_E_SIZE;
+  if (tiles && !dense_tiles_fit(n, T, block)) return SGP4_E_SIZE;
   if (flat && !dense_flat_fits(n, T, block)) return SGP4_E_SIZE;
+  if (!tiles && !flat && !persistent && !dense_grid_fits(n, block)) return SGP4_E_SIZE;
   unsigned grid = 0;
   if (persistent) {
     const int64_t tiles = n * ((T + 63) / 64);
@@ -266,6 +273,7 @@ int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, c
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (T <= kFusedMaxT || !ws) {
     if (T > fused_max_T()) return SGP4_E_WORKSPACE;
+    if (!fused_fits(n, T)) return ws ? SGP4_E_WORKSPACE : SGP4_E_SIZE;
     return hip_status(launch_fused(precision, g, n, elem, t, T, r, v, err, sat_flags, s));
   }
   if (int rc = hip_status(launch_init(g, n, elem, ws, sat_flags, s))) return rc;
@@ -317,7 +325,7 @@ int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets,
   // never waits for them); the grid is capped at 2^31 - 1 workgroups, beyond
   // which the wavefronts loop.
   const int64_t nchunks = (nnz + 63) / 64;
-  const unsigned grid = unsigned(std::min<int64_t>((nchunks + 3) / 4, 0x7fffffff));
+  const unsigned grid = unsigned(std::min<int64_t>((nchunks + 3) / 4, int64_t(0xffffffffu / 256)));
   return hip_status(launch_ragged(precision, 1, consts, n, offsets, t, nnz, nullptr, nullptr, nchunks, r, v, err, 256,
                                   std::max(grid, 1u), s));
 }
@@ -392,8 +400,9 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
     const int64_t work = mode == 0 ? p->ntiles : p->nchunks;
     const int64_t waves_needed = work;
     const int64_t blocks_needed = (waves_needed + block / 64 - 1) / (block / 64);
-    constexpr int64_t kMaxGrid = 0x7fffffff;  // a smaller grid makes the kernels loop
-    return unsigned(std::max<int64_t>(1, std::min({blocks_needed, int64_t(cus) * per_cu, kMaxGrid})));
+    // at most 2^32 - 1 work-items per dispatch; a smaller grid makes the kernels loop
+    const int64_t max_grid = std::min<int64_t>(0x7fffffff, int64_t(0xffffffffu) / block);
+    return unsigned(std::max<int64_t>(1, std::min({blocks_needed, int64_t(cus) * per_cu, max_grid})));
   };
   // default choice: one wavefront per tile, 256-wide workgroups (fastest on
   // MI355X for the 1M-satellite catalogue in every precision); or the caller's
@@ -522,6 +531,7 @@ int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t,
              const void* gr, const void* gv, double* gelem, void* stream) {
   if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
   if (precision != SGP4_FP64 && precision != SGP4_FP32_MIXED) return SGP4_E_PRECISION;
+  if (!grid_fits(uint64_t(n), kVjpLanes)) return SGP4_E_SIZE;  // one workgroup per satellite
   if (n == 0) return SGP4_OK;
   if (!elem || !consts || !gelem || (T > 0 && (!t || !gr))) return SGP4_E_ARG;
   return hip_status(launch_vjp(precision, n, elem, consts, t, T, gr, gv, gelem, static_cast<hipStream_t>(stream)));
@@ -531,6 +541,7 @@ int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const doubl
                   double* jac, void* stream) {
   if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 42)) return SGP4_E_SIZE;
   if (precision != SGP4_FP64 && precision != SGP4_FP32_MIXED) return SGP4_E_PRECISION;
+  if (!grid_fits(uint64_t(n), kVjpLanes)) return SGP4_E_SIZE;  // one workgroup per satellite
   if (n == 0 || T == 0) return SGP4_OK;
   if (!elem || !consts || !t || !jac) return SGP4_E_ARG;
   return hip_status(launch_jacobian(precision, n, elem, consts, t, T, jac, static_cast<hipStream_t>(stream)));

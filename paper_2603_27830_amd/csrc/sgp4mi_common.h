@@ -36,6 +36,10 @@ constexpr double kMagic = 20260331.0;
 constexpr uint32_t kInfoCodeMask = 0xffu;
 constexpr uint32_t kInfoIsimp = 0x100u;
 
+// Point code of a ragged point that the offsets place in no satellite's list
+// (malformed offsets given to the plan-less ragged call); r and v are NaN.
+constexpr uint32_t kCodeUnowned = 8u;
+
 constexpr int kSlotBytes = 512;
 constexpr int kSlotF32 = kNRec * 8;            // byte offset of the float copies
 constexpr int kSlotInfo = kSlotF32 + kNRec * 4;  // byte offset of the info word
@@ -48,6 +52,10 @@ struct alignas(16) Slot {
   uint32_t pad[(kSlotBytes - kSlotInfo - 4) / 4];
 };
 static_assert(sizeof(Slot) == kSlotBytes, "slot size");
+
+// A dispatch's extent in work-items is a 32-bit number per grid dimension:
+// groups * block must stay below 2^32 (not only groups below 2^31).
+inline bool grid_fits(uint64_t groups, uint64_t block) { return groups * block <= 0xffffffffull; }
 
 inline int64_t npad_of(int64_t n) { return (n + 63) / 64 * 64; }
 inline size_t record_bytes(int64_t n) { return size_t(kHCount) * 8 + size_t(kSlotBytes) * size_t(n > 0 ? n : 0); }

@@ -161,6 +161,13 @@ static void fused_t(const FusedArgs& a, void* r, void* v, uint8_t* err, hipStrea
 // Largest T the fused grid covers (ceil(T / tt) workgroups in y).
 int64_t fused_max_T() { return int64_t(65535) * kFusedTT; }
 
+// Whether the fused grid's x extent (ceil(n / 64) workgroups of 64 tt lanes)
+// fits a dispatch's 2^32 work-items.
+bool fused_fits(int64_t n, int64_t T) {
+  const uint64_t tt = uint64_t(T < kFusedTT ? T : kFusedTT);
+  return grid_fits(uint64_t((n + 63) / 64), 64 * (tt > 0 ? tt : 1));
+}
+
 hipError_t launch_fused(int precision, const double g[5], int64_t n, const double* elem, const double* t, int64_t T,
                         void* r, void* v, uint8_t* err, uint8_t* user_flags, hipStream_t s) {
   FusedArgs a;

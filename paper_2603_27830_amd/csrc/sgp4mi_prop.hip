@@ -12,6 +12,7 @@
 // Outputs are component-major SoA, r[c * P + p], written with non-temporal
 // stores; codes 1, 2, 4 and 7 write NaN states.
 #include "sgp4mi_out.h"
+#include "sgp4mi_search.h"
 
 namespace sgp4mi {
 
@@ -168,7 +169,12 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const doub
 
 // ------------------------------------------------------------- ragged flat --
 // chunk_sat[k]: satellite whose list contains point 64*k.  When chunk_sat is
-// null the wavefront finds it by a uniform binary search of the offsets.
+// null the wavefront finds it by a 64-way search of the offsets (each round
+// every lane probes one of 64 evenly spaced offsets of [lo, hi) and a ballot
+// keeps the piece holding q).  The offsets are then unchecked caller data: the
+// search and the walk read only offsets[0..n] and yield a satellite in [0, n)
+// whatever they hold, and a point outside that satellite's list (possible only
+// for malformed offsets) gets code 8 and NaN instead of a state.
 template <class TS, class TP, int kBlock, bool kOff32>
 __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64_t* __restrict__ offsets, int64_t n,
                                                       const double* __restrict__ t, int64_t nnz,
@@ -180,36 +186,23 @@ __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64
   const int64_t nwaves = int64_t(gridDim.x) * kWaves;
   const Grav g = load_grav(rv);
   for (int64_t k = wave0; k < nchunks; k += nwaves) {
-    int64_t first;
-    if (chunk_sat) {
-      first = chunk_sat[k];
-    } else {
-      // 64-way search by the whole wavefront: each round every lane probes one
-      // of 64 evenly spaced offsets of [lo, hi) and a ballot keeps the piece
-      // holding q.  offsets[lo] <= q < offsets[hi] holds throughout
-      // (offsets[0] = 0 <= q < nnz = offsets[n]); offsets are non-decreasing,
-      // so the probes that pass form a prefix of the lanes, lane 0 always.
-      const int64_t q = k * 64;
-      int64_t lo = 0, hi = n;
-      while (hi - lo > 1) {
-        const int64_t step = (hi - lo + 63) >> 6;
-        const int64_t idx = lo + step * lane;
-        const bool pass = idx < hi && offsets[idx] <= q;
-        const uint64_t ballot = __ballot(pass);
-        const int last = 63 - __builtin_clzll(ballot);
-        const int64_t nlo = lo + step * last;
-        hi = nlo + step < hi ? nlo + step : hi;
-        lo = nlo;
-      }
-      first = lo;
-    }
-    const int64_t p = k * 64 + lane;
+    const int64_t q = k * 64;
+    const int64_t first = chunk_sat ? int64_t(chunk_sat[k])
+                                    : wave_search(n, [&](int64_t lo, int64_t step, int64_t hi) {
+                                        const int64_t idx = lo + step * lane;
+                                        return uint64_t(__ballot(idx < hi && offsets[idx] <= q));
+                                      });
+    const int64_t p = q + lane;
     if (p < nnz) {
-      int64_t sat = first;
-      while (sat + 1 < n && offsets[sat + 1] <= p) ++sat;
-      const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, sat);
+      bool owned;
+      const int64_t sat = point_owner(offsets, n, first, p, &owned);
       PointState<TP> s;
-      const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
+      s.ok = false;
+      uint32_t code = kCodeUnowned;
+      if (owned) {
+        const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, sat);
+        code = sgp4_point<TS, TP>(c, g, t[p], s);
+      }
       out.put(p, code, s);
     }
   }
@@ -354,17 +347,25 @@ static hipError_t flat_t(const RecordView& rv, int64_t n, const double* t, int64
 }
 
 // Whether the flat dense grid (one lane per point, ceil(n T / block)
-// workgroups) fits the launch limit of 2^31 - 1 workgroups.
+// workgroups) fits the launch limits: fewer than 2^31 workgroups and 2^32
+// work-items.
 bool dense_flat_fits(int64_t n, int64_t T, int block) {
-  return n * T <= int64_t(0x7fffffff) * block;
+  const int64_t groups = (n * T + block - 1) / block;
+  return groups <= int64_t(0x7fffffff) && grid_fits(uint64_t(groups), uint64_t(block));
 }
 
-// Number of 64-time tiles of an n x T batch, and whether the tile kernel can
-// index them (32-bit tile indices).
-bool dense_tiles_fit(int64_t n, int64_t T) {
+// Whether the one-wavefront-per-64-time-tile grid of an n x T batch fits:
+// 32-bit tile indices, and ceil(tiles / (block / 64)) workgroups of block
+// lanes within the 2^32 work-item extent of a dispatch.
+bool dense_tiles_fit(int64_t n, int64_t T, int block) {
   const int64_t tps = (T + 63) / 64;
-  return n <= INT64_MAX / (tps > 0 ? tps : 1) && n * tps <= 0xffffffffLL;
+  if (!(n <= INT64_MAX / (tps > 0 ? tps : 1) && n * tps <= 0xffffffffLL)) return false;
+  const int64_t groups = (n * tps + block / 64 - 1) / (block / 64);
+  return grid_fits(uint64_t(groups), uint64_t(block));
 }
+
+// Whether the satellite-by-time grid (n workgroups in x) fits.
+bool dense_grid_fits(int64_t n, int block) { return grid_fits(uint64_t(n), uint64_t(block)); }
 
 // block: workgroup size; vec: constants through vector loads (else scalar);
 // grid > 0 selects the persistent kernel with that many workgroups; tiles

@@ -131,6 +131,28 @@ def test_elements_to_states_and_flat_config_reject_bad_arguments():
     assert px(fake, 2**31 - 1, fake, 2**9, 0, fake, fake, fake, 64 | FLAT, None) == E["SGP4_E_SIZE"]
 
 
+def test_launch_extent_limits_are_checked_on_the_host():
+    """A dispatch spans fewer than 2^32 lanes per grid dimension: calls whose
+    grid would exceed it return SGP4_E_SIZE before any launch."""
+    L = _native.lib()
+    E = {v: k for k, v in _native.ERRORS.items()}
+    fake = ctypes.c_void_p(0x1000)
+    SCALAR, TILES, FLAT = 0x10000, 0x40000, 0x80000
+    px = L.sgp4_propagate_ex
+    # one 256-lane workgroup per satellite: n < 2^24
+    assert L.sgp4_vjp(2**24, fake, fake, fake, 1, 0, fake, None, fake, None) == E["SGP4_E_SIZE"]
+    assert L.sgp4_jacobian(2**24, fake, fake, fake, 1, 0, fake, None) == E["SGP4_E_SIZE"]
+    # 2^26 tiles of 64 lanes = 2^32 lanes
+    assert px(fake, 2**26, fake, 64, 0, fake, fake, fake, 256 | SCALAR | TILES, None) == E["SGP4_E_SIZE"]
+    # satellite-by-time grid: n workgroups of 256 lanes
+    assert px(fake, 2**24, fake, 10, 0, fake, fake, fake, 256 | SCALAR, None) == E["SGP4_E_SIZE"]
+    # flat grid: 2^32 points in 256-lane workgroups
+    assert px(fake, 2**22, fake, 2**10, 0, fake, fake, fake, 256 | FLAT, None) == E["SGP4_E_SIZE"]
+    # fused grid: ceil(n / 64) workgroups of 64 x 16 lanes
+    pe = L.sgp4_propagate_elements
+    assert pe(None, 2**28, fake, fake, 16, 0, fake, fake, fake, None, None, 0, None) == E["SGP4_E_SIZE"]
+
+
 def test_double_sincos_table_is_correctly_rounded():
     """The device table of sin and cos at j pi / 64 (j = -64 .. 64) holds the
     doubles nearest the exact values (checked in 50-digit arithmetic)."""
