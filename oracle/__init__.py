@@ -34,7 +34,9 @@ INIT_NAMES = [
     "xi", "eta", "C1", "C2", "C3", "C4", "C5", "Mdot", "argpdot", "nodedot", "nodedot1",
     "argpcof", "Mcof", "nodecf", "t2cof", "aycof", "Lcof", "dM0", "sinM0",
     "D2", "D3", "D4", "t3cof", "t4cof", "t5cof", "isimp", "deep", "epoch_code", "ke", "j3oj2", "vkms",
-]
+    "resonant", "dedt", "didt", "dMdt", "dnodedt", "dargpdt", "Msun0", "Mmoon0",
+] + [f"{name}_{body}" for body in ("sun", "moon")
+     for name in ("pe2", "pe3", "pi2", "pi3", "pl2", "pl3", "pl4", "pgh2", "pgh3", "pgh4", "ph2", "ph3")]
 WGS72 = (398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597)
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -60,6 +62,8 @@ def lib():
         L.oracle_jacobian_points.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, _u8p]
         L.oracle_vjp.argtypes = [_dp, ctypes.c_int64, _dp, _dp, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_count_ops.argtypes = [_dp, _dp, ctypes.c_double, _u64p]
+        L.oracle_set_reference_jd.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_reference_jd.restype = ctypes.c_double
         L.oracle_ke.argtypes = [_dp]
         L.oracle_ke.restype = ctypes.c_double
         assert L.oracle_detail_count() == ND
@@ -168,6 +172,25 @@ def count_ops(elem1, tmin, grav=None):
     lib().oracle_count_ops(_p(g), _p(e), float(tmin), _p(out, _u64p))
     keys = ["add", "mul", "div", "sqrt", "cbrt", "trig", "atan2", "floor"]
     return {k: int(x) for k, x in zip(keys, out)}
+
+
+class reference_jd:
+    """Context manager: the reference instant (Julian date, whole + fraction) of
+    the elements' epoch row and the times while the block runs (the deep-space
+    model's lunar and solar arguments need absolute time); J2000.0 otherwise."""
+
+    def __init__(self, whole, frac=0.0):
+        self.whole, self.frac = float(whole), float(frac)
+
+    def __enter__(self):
+        L = lib()
+        self.saved = L.oracle_reference_jd()
+        L.oracle_set_reference_jd(self.whole, self.frac)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_reference_jd(self.saved, 0.0)
+        return False
 
 
 def ke(grav=None):

@@ -14,6 +14,12 @@
 // none of the model's equations; the steps below restate the published
 // near-Earth model in the order it is defined (initialisation I1-I8, then
 // propagation P1-P9), written here from the mathematics, not from any listing.
+// Orbits with periods of 225 min or more take the deep-space model's lunar and
+// solar terms (Hujsak 1979 in the same reports; section 6 of the paper names
+// deep space as the variant it leaves out): secular rates and long-period terms
+// of the quadrupole tidal potential of the Sun and the Moon (I9, P2d, P4d).  The
+// 12 h and 24 h resonant classes, whose resonance integrator this oracle does
+// not implement, are flagged and not propagated.
 //
 // Readings where the paper is silent (each is listed in the design notes):
 //  * WGS72: mu = 398600.8 km^3/s^2, R = 6378.135 km, J2 = 0.001082616,
@@ -24,11 +30,16 @@
 //    steps; sin/cos are then taken at the final iterate (the root).
 //  * Error codes (section 2.2 "Control Flow": anomalous states are computed and
 //    flagged, not exited): 1 mean eccentricity outside [-0.001, 1) (or e0
-//    outside [0, 1) at epoch), 2 mean motion n0'' not > 0, 4 semi-latus rectum
-//    p_L < 0, 6 decayed (r_k < 1 earth radius; state still written), 7 deep-space
-//    element set (period >= 225 min, section 6: near-Earth only).  Checks run
-//    in the order 1(epoch) -> 2 -> 7 -> 1 -> 4 -> 6; the first failing one
-//    wins.  Codes 1, 2, 4, 7 write NaN to r and v.
+//    outside [0, 1) at epoch), 2 mean motion n0'' not > 0, 3 deep space: the
+//    lunar-solar terms move e outside [0, 1], 4 semi-latus rectum p_L < 0, 6
+//    decayed (r_k < 1 earth radius; state still written), 7 resonant deep-space
+//    element set (not propagated).  Checks run in the order 1(epoch) -> 2 -> 7
+//    -> 1 -> 3 -> 4 -> 6; the first failing one wins.  Codes 1, 2, 3, 4, 7
+//    write NaN to r and v.
+//  * Deep space: the lunar and solar arguments use absolute time, the epoch
+//    row taken as days after a reference Julian date (J2000.0 unless set); the
+//    node is reduced with floor to [0, 2*pi) before the low-inclination form
+//    uses its value.
 //  * Checks are written so that NaN fails them (NaN never passes as valid).
 //  * Angles are reduced with floor to [0, 2*pi).
 //  * pow(x, 2/3) is cbrt(x)^2 and x^1.5 is x*sqrt(x).
@@ -44,12 +55,18 @@
 // and as Gauss-equation orbit averages (C2, C4, C5, the periodic drag term of M
 // and w, the J3-drag perigee rate), the node drag term along the decaying
 // orbit, the mean elements at epoch, term-group toggles, crafted error codes
-// and a hand count of the operations.
+// and a hand count of the operations.  Deep space: the lunar-solar constants
+// against textbook astronomy, the five secular rates and the ten twice-anomaly
+// periodic coefficients per body against Lagrange's equations on the
+// numerically averaged quadrupole, the body-eccentricity terms, the
+// low-inclination form at its switch, the resonance flags and code 3.
 //
 // Parity unpinned (model definitions no available pin reaches): the J2 bracket
 // of C4, the eccentricity factor (beta0^2) of the drag node term, the
 // low-perigee density parameter (156 km / 98 km branch), the 220 km
-// simplified-drag switch, the e0 > 1e-4 gate and the 1.5e-12 guard; and, as a
+// simplified-drag switch, the e0 > 1e-4 gate and the 1.5e-12 guard; in deep
+// space the 0.2 rad switch value, the 3-degree cut of the node rate, the
+// resonance bands and the first-order true anomaly of the bodies; and, as a
 // whole, numeric agreement with the published model's own verification
 // vectors, which are not available here.
 //
@@ -194,7 +211,181 @@ struct Sat {
   S D2, D3, D4, t3cof, t4cof, t5cof;
   bool isimp = false, deep = false;
   int epoch_code = 0;  // 1 when e0 is outside [0, 1)
+  // Deep space (period of 225 min or more): lunar-solar secular rates, the
+  // coefficients of the long-period lunar and solar terms (index 0 Sun, 1
+  // Moon) and the two bodies' mean anomalies at epoch; resonant orbits are
+  // flagged and not propagated.
+  bool resonant = false;
+  S dedt, didt, dMdt, dnodedt, dargpdt;
+  S pe2[2], pe3[2], pi2[2], pi3[2], pl2[2], pl3[2], pl4[2], pgh2[2], pgh3[2], pgh4[2], ph2[2], ph3[2];
+  double Mbody0[2];
 };
+
+// ------------------------------------------------------------ deep space --
+// Lunar and solar perturbations of the deep-space model (SDP4: Hujsak 1979,
+// in Hoots & Roehrich 1980 as revised by Vallado et al. 2006): the quadrupole
+// term of each body's tidal potential, averaged over the satellite's orbit,
+// with each body on a fixed-shape orbit whose orientation is set at the
+// satellite's epoch.  Secular rates come from the part also averaged over the
+// body's mean anomaly; the long-period terms from the rest, to first order in
+// the body's eccentricity.  The 12 h and 24 h resonant classes (their
+// resonance integrator) are outside this oracle: flagged, not propagated.
+//
+// The reference instant of the elements' epoch row, as a Julian date (UT):
+// the lunar and solar arguments need absolute time.  J2000.0 unless set.
+double g_ref_jd = 2451545.0;
+
+// Body constants: mean motion (rad/min), orbital eccentricity, and the
+// strength c1 = (mu_body / a_body^3) / (4 n_body), the quadrupole tidal
+// coefficient divided by the body's mean motion (the Sun: n_sun / 4; the
+// Moon: its mass fraction times n_moon / 4).
+constexpr double kNBody[2] = {1.19459e-5, 1.5835218e-4};
+constexpr double kEBody[2] = {0.01675, 0.05490};
+constexpr double kC1Body[2] = {2.9864797e-6, 4.7968065e-7};
+// Obliquity of the ecliptic: sin, cos.  Solar perigee argument: cos, sin.
+constexpr double kSinEps = 0.39785416, kCosEps = 0.91744867;
+constexpr double kCosSunPer = 0.1945905, kSinSunPer = -0.98088458;
+// Moon: sine of its orbit's inclination to the ecliptic; cos of its
+// inclination to the equator as kMoonCosI0 - kMoonCosI1 cos(lunar node).
+constexpr double kSinMoonInc = 0.089683511;
+constexpr double kMoonCosI0 = 0.91375164, kMoonCosI1 = 0.03568096;
+
+// Per-body coefficient set of the averaged quadrupole (the body's orbit given
+// by the cos/sin of its perigee argument g, inclination i and the satellite's
+// node relative to the body's node h).
+template <class S>
+struct BodyTerms {
+  S s1, s2, s3, s4, s5, s6, s7;
+  S z1, z2, z3, z11, z12, z13, z21, z22, z23, z31, z32, z33;
+};
+
+template <class S>
+BodyTerms<S> body_terms(const S& cg, const S& sg, const S& ci, const S& si, const S& ch, const S& sh,
+                        const S& cw, const S& sw, const S& cim, const S& sim, const S& e, double c1,
+                        const S& n) {
+  BodyTerms<S> b;
+  const S e2 = e * e, beta2 = 1.0 - e2, beta = sqrt(beta2);
+  // direction cosines of the body's perigee and of the normal-plane axis,
+  // first in the satellite's nodal frame (a1..a10), then in its perifocal
+  // frame (x1..x8)
+  const S a1 = cg * ch + sg * ci * sh;
+  const S a3 = -sg * ch + cg * ci * sh;
+  const S a7 = -cg * sh + sg * ci * ch;
+  const S a8 = sg * si;
+  const S a9 = sg * sh + cg * ci * ch;
+  const S a10 = cg * si;
+  const S a2 = cim * a7 + sim * a8;
+  const S a4 = cim * a9 + sim * a10;
+  const S a5 = -sim * a7 + cim * a8;
+  const S a6 = -sim * a9 + cim * a10;
+  const S x1 = a1 * cw + a2 * sw;
+  const S x2 = a3 * cw + a4 * sw;
+  const S x3 = -a1 * sw + a2 * cw;
+  const S x4 = -a3 * sw + a4 * cw;
+  const S x5 = a5 * sw;
+  const S x6 = a6 * sw;
+  const S x7 = a5 * cw;
+  const S x8 = a6 * cw;
+  b.z31 = 12.0 * x1 * x1 - 3.0 * x3 * x3;
+  b.z32 = 24.0 * x1 * x2 - 6.0 * x3 * x4;
+  b.z33 = 12.0 * x2 * x2 - 3.0 * x4 * x4;
+  const S z1 = 3.0 * (a1 * a1 + a2 * a2) + b.z31 * e2;
+  const S z2 = 6.0 * (a1 * a3 + a2 * a4) + b.z32 * e2;
+  const S z3 = 3.0 * (a3 * a3 + a4 * a4) + b.z33 * e2;
+  b.z11 = -6.0 * a1 * a5 + e2 * (-24.0 * x1 * x7 - 6.0 * x3 * x5);
+  b.z12 = -6.0 * (a1 * a6 + a3 * a5) + e2 * (-24.0 * (x2 * x7 + x1 * x8) - 6.0 * (x3 * x6 + x4 * x5));
+  b.z13 = -6.0 * a3 * a6 + e2 * (-24.0 * x2 * x8 - 6.0 * x4 * x6);
+  b.z21 = 6.0 * a2 * a5 + e2 * (24.0 * x1 * x5 - 6.0 * x3 * x7);
+  b.z22 = 6.0 * (a4 * a5 + a2 * a6) + e2 * (24.0 * (x2 * x5 + x1 * x6) - 6.0 * (x4 * x7 + x3 * x8));
+  b.z23 = 6.0 * a4 * a6 + e2 * (24.0 * x2 * x6 - 6.0 * x4 * x8);
+  b.z1 = 2.0 * z1 + beta2 * b.z31;
+  b.z2 = 2.0 * z2 + beta2 * b.z32;
+  b.z3 = 2.0 * z3 + beta2 * b.z33;
+  b.s3 = c1 / n;
+  b.s2 = -0.5 * b.s3 / beta;
+  b.s4 = b.s3 * beta;
+  b.s1 = -15.0 * e * b.s4;
+  b.s5 = x1 * x3 + x2 * x4;
+  b.s6 = x2 * x3 + x1 * x4;
+  b.s7 = x2 * x4 - x1 * x3;
+  return b;
+}
+
+// Deep-space initialisation: lunar-solar secular rates, long-period
+// coefficients and the bodies' mean anomalies at epoch.  day: days after
+// JD 2415020.0 (1900 January 0.5, the origin of the lunar and solar
+// arguments).
+template <class S>
+void deep_init(Sat<S>& c, double day) {
+  // The Moon's orbit at epoch: node on the ecliptic, inclination and node on
+  // the equator, and its perigee argument from that node.
+  const double node_l = mod2pi(4.5236020 - 9.2422029e-4 * day);
+  const double sn = std::sin(node_l), cn = std::cos(node_l);
+  const double ci_l = kMoonCosI0 - kMoonCosI1 * cn;
+  const double si_l = std::sqrt(1.0 - ci_l * ci_l);
+  const double sh_l = kSinMoonInc * sn / si_l;
+  const double ch_l = std::sqrt(1.0 - sh_l * sh_l);
+  const double perigee_l = 5.8351514 + 0.0019443680 * day;
+  const double dx = std::atan2(kSinEps * sn / si_l, ch_l * cn + kCosEps * sh_l * sn);
+  const double g_l = perigee_l + dx - node_l;
+  c.Mbody0[0] = mod2pi(6.2565837 + 0.017201977 * day);
+  c.Mbody0[1] = mod2pi(4.7199672 + 0.22997150 * day - perigee_l);
+
+  const S sw = sin(c.argp0), cw = cos(c.argp0);
+  const S sni = sin(c.node0), cni = cos(c.node0);
+  const S sim = c.sini, cim = c.cosi;
+  const S e = c.e0, e2 = e * e;
+  BodyTerms<S> b[2];
+  // Sun: node of its orbit on the equator at the equinox
+  b[0] = body_terms<S>(S(kCosSunPer), S(kSinSunPer), S(kCosEps), S(kSinEps), cni, sni, cw, sw, cim, sim, e,
+                       kC1Body[0], c.n0pp);
+  // Moon: the satellite's node measured from the Moon's node on the equator
+  const S chm = ch_l * cni + sh_l * sni, shm = sni * ch_l - cni * sh_l;
+  b[1] = body_terms<S>(S(std::cos(g_l)), S(std::sin(g_l)), S(ci_l), S(si_l), chm, shm, cw, sw, cim, sim, e,
+                       kC1Body[1], c.n0pp);
+  for (int k = 0; k < 2; ++k) {
+    const BodyTerms<S>& q = b[k];
+    c.pe2[k] = 2.0 * q.s1 * q.s6;
+    c.pe3[k] = 2.0 * q.s1 * q.s7;
+    c.pi2[k] = 2.0 * q.s2 * q.z12;
+    c.pi3[k] = 2.0 * q.s2 * (q.z13 - q.z11);
+    c.pl2[k] = -2.0 * q.s3 * q.z2;
+    c.pl3[k] = -2.0 * q.s3 * (q.z3 - q.z1);
+    c.pl4[k] = -2.0 * q.s3 * (-21.0 - 9.0 * e2) * kEBody[k];
+    c.pgh2[k] = 2.0 * q.s4 * q.z32;
+    c.pgh3[k] = 2.0 * q.s4 * (q.z33 - q.z31);
+    c.pgh4[k] = -18.0 * q.s4 * kEBody[k];
+    c.ph2[k] = -2.0 * q.s2 * q.z22;
+    c.ph3[k] = -2.0 * q.s2 * (q.z23 - q.z21);
+  }
+
+  // Resonance classes: 24 h (synchronous) and 12 h with e >= 0.5.
+  const double nv = val(c.n0pp), ev = val(c.e0);
+  c.resonant = (nv < 0.0052359877 && nv > 0.0034906585) || (nv >= 8.26e-3 && nv <= 9.24e-3 && ev >= 0.5);
+
+  // Secular rates: the doubly averaged quadrupole in Lagrange's equations.
+  // Near-equatorial orbits (inclination within 3 degrees of 0 or 180) take no
+  // node rate from the bodies.
+  const double iv = val(c.i0);
+  const bool flat = iv < 5.2359877e-2 || iv > kPi - 5.2359877e-2;
+  S de = S(0.0), di = S(0.0), dM = S(0.0), dgh = S(0.0), dh = S(0.0);
+  for (int k = 0; k < 2; ++k) {
+    const BodyTerms<S>& q = b[k];
+    const double nb = kNBody[k];
+    de = de + q.s1 * nb * q.s5;
+    di = di + q.s2 * nb * (q.z11 + q.z13);
+    dM = dM - nb * q.s3 * (q.z1 + q.z3 - 14.0 - 6.0 * e2);
+    dgh = dgh + q.s4 * nb * (q.z31 + q.z33 - 6.0);
+    S h = -nb * q.s2 * (q.z21 + q.z23);
+    if (flat) h = S(0.0);
+    dh = dh + (val(sim) != 0.0 ? h / sim : h);
+  }
+  c.dedt = de;
+  c.didt = di;
+  c.dMdt = dM;
+  c.dnodedt = dh;
+  c.dargpdt = dgh - cim * dh;
+}
 
 template <class S>
 Sat<S> sgp4_init(const Gravity& g, const S el[kNElem], double epoch) {
@@ -240,7 +431,7 @@ Sat<S> sgp4_init(const Gravity& g, const S el[kNElem], double epoch) {
   // I4: flags.  Deep space: period 2*pi/n0'' of 225 min or more.  Simplified
   // drag: perigee below 220 km.
   c.deep = (val(c.n0pp) > 0.0) && (kTwoPi / val(c.n0pp) >= 225.0);
-  c.isimp = val(c.rp) < 1.0 + 220.0 / R;
+  c.isimp = c.deep || val(c.rp) < 1.0 + 220.0 / R;
 
   // I5: drag coefficients.
   c.xi = 1.0 / (c.a0pp - c.s);
@@ -300,7 +491,34 @@ Sat<S> sgp4_init(const Gravity& g, const S el[kNElem], double epoch) {
     c.t4cof = 0.25 * (3.0 * c.D3 + c.C1 * (12.0 * c.D2 + 10.0 * C1sq));
     c.t5cof = 0.2 * (3.0 * c.D4 + 12.0 * c.C1 * c.D3 + 6.0 * c.D2 * c.D2 + 15.0 * C1sq * (2.0 * c.D2 + C1sq));
   }
+  c.dedt = c.didt = c.dMdt = c.dnodedt = c.dargpdt = S(0.0);
+  c.Mbody0[0] = c.Mbody0[1] = 0.0;
+  for (int k = 0; k < 2; ++k)
+    c.pe2[k] = c.pe3[k] = c.pi2[k] = c.pi3[k] = c.pl2[k] = c.pl3[k] = c.pl4[k] = c.pgh2[k] = c.pgh3[k] =
+        c.pgh4[k] = c.ph2[k] = c.ph3[k] = S(0.0);
+  // I9: deep space.  The epoch in days after 1900 January 0.5.
+  if (c.deep && !c.epoch_code) deep_init(c, (g_ref_jd - 2415020.0) + epoch);
   return c;
+}
+
+// Long-period lunar-solar terms at time t after epoch (each body's mean
+// anomaly advanced by its mean motion, its true anomaly to first order in
+// its eccentricity): the changes of e, i, M, argp + node and node.
+template <class S>
+void deep_periodics(const Sat<S>& c, double t, S* pe, S* pinc, S* pl, S* pgh, S* ph) {
+  *pe = *pinc = *pl = *pgh = *ph = S(0.0);
+  for (int k = 0; k < 2; ++k) {
+    const double Mb = c.Mbody0[k] + kNBody[k] * t;
+    const double f = Mb + 2.0 * kEBody[k] * std::sin(Mb);
+    const double sf = std::sin(f);
+    const double f2 = 0.5 * sf * sf - 0.25;
+    const double f3 = -0.5 * sf * std::cos(f);
+    *pe = *pe + c.pe2[k] * f2 + c.pe3[k] * f3;
+    *pinc = *pinc + c.pi2[k] * f2 + c.pi3[k] * f3;
+    *pl = *pl + c.pl2[k] * f2 + c.pl3[k] * f3 + c.pl4[k] * sf;
+    *pgh = *pgh + c.pgh2[k] * f2 + c.pgh3[k] * f3 + c.pgh4[k] * sf;
+    *ph = *ph + c.ph2[k] * f2 + c.ph3[k] * f3;
+  }
 }
 
 // ------------------------------------------------------------ propagation --
@@ -324,7 +542,7 @@ int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3],
   if (det) for (int k = 0; k < kD_COUNT; ++k) det[k] = nan;
   if (c.epoch_code) return fail(1);
   if (!(val(c.n0pp) > 0.0)) return fail(2);
-  if (c.deep) return fail(7);
+  if (c.deep && c.resonant) return fail(7);
 
   const double t = tsince;
   const double t2 = t * t;
@@ -351,10 +569,19 @@ int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3],
     M = M_df;
     argp = argp_df;
   }
+  // P2d (deep space): lunar-solar secular rates.
+  S e_sec = c.e0, incl = c.i0;
+  if (c.deep) {
+    e_sec = e_sec + c.dedt * t;
+    incl = incl + c.didt * t;
+    argp = argp + c.dargpdt * t;
+    node = node + c.dnodedt * t;
+    M = M + c.dMdt * t;
+  }
   // P3: drag-decayed semi-major axis, mean motion and eccentricity.
   S a = c.a0pp * A * A;
   S n = g.ke / (a * sqrt(a));
-  S e = c.e0 - Ed;
+  S e = e_sec - Ed;
   if (det) det[kD_emargin] = std::min(val(e) + 0.001, 1.0 - val(e));
   if (!(val(e) >= -0.001 && val(e) < 1.0)) return fail(1);
   if (val(e) < 1.0e-6) e = S(1.0e-6);
@@ -364,13 +591,73 @@ int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3],
   node = mod2pi(node);
   argp = mod2pi(argp);
   L = mod2pi(L);
-  // P5: long-period periodics (J3).
-  S axn = e * cos(argp);
-  S tau = 1.0 / (a * (1.0 - e * e));
-  S ayn = e * sin(argp) + tau * c.aycof;
-  S LT = L + tau * c.Lcof * axn;
+  // Inclination functions of the periodic terms: the epoch's, except in deep
+  // space, where the lunar-solar terms move the inclination.
+  S incp = c.i0, sinip = c.sini, cosip = c.cosi, c41 = c.c41, x1 = c.x1, x7 = c.x7;
+  S aycof = c.aycof, Lcof = c.Lcof;
+  S LT, U, axn, ayn, tau;
+  if (!c.deep) {
+    // P5: long-period periodics (J3).
+    axn = e * cos(argp);
+    tau = 1.0 / (a * (1.0 - e * e));
+    ayn = e * sin(argp) + tau * aycof;
+    LT = L + tau * Lcof * axn;
+    U = mod2pi(LT - node);
+  } else {
+    // P4d: long-period lunar-solar terms on the mean elements.
+    M = mod2pi(L - argp - node);
+    S pe, pinc, pl, pgh, ph;
+    deep_periodics(c, t, &pe, &pinc, &pl, &pgh, &ph);
+    incp = incl + pinc;
+    e = e + pe;
+    sinip = sin(incp);
+    cosip = cos(incp);
+    if (val(incp) >= 0.2) {
+      ph = ph / sinip;
+      pgh = pgh - cosip * ph;
+      argp = argp + pgh;
+      node = node + ph;
+      M = M + pl;
+    } else {
+      // Low inclination: the node and inclination changes applied to the
+      // components (sin i sin node, sin i cos node), and the longitude
+      // argp + cos i node carried through, so that nothing divides by sin i.
+      S sno = sin(node), cno = cos(node);
+      S alf = sinip * sno + (ph * cno + pinc * cosip * sno);
+      S bet = sinip * cno + (-ph * sno + pinc * cosip * cno);
+      node = mod2pi(node);
+      S xls = M + argp + cosip * node + (pl + pgh - pinc * node * sinip);
+      S node_old = node;
+      node = atan2(alf, bet);
+      if (std::fabs(val(node_old) - val(node)) > kPi) node = val(node) < val(node_old) ? node + kTwoPi : node - kTwoPi;
+      M = M + pl;
+      argp = xls - M - cosip * node;
+    }
+    if (val(incp) < 0.0) {
+      incp = -incp;
+      node = node + kPi;
+      argp = argp - kPi;
+    }
+    if (det) det[kD_e] = val(e);
+    if (!(val(e) >= 0.0 && val(e) <= 1.0)) return fail(3);
+    sinip = sin(incp);
+    cosip = cos(incp);
+    const S cos2 = cosip * cosip;
+    c41 = 3.0 * cos2 - 1.0;
+    x1 = 1.0 - cos2;
+    x7 = 7.0 * cos2 - 1.0;
+    aycof = -0.5 * g.j3oj2 * sinip;
+    S den = 1.0 + cosip;
+    if (std::fabs(val(den)) <= 1.5e-12) den = S(1.5e-12);
+    Lcof = -0.25 * g.j3oj2 * sinip * (3.0 + 5.0 * cosip) / den;
+    // P5: long-period periodics (J3) with the perturbed elements.
+    axn = e * cos(argp);
+    tau = 1.0 / (a * (1.0 - e * e));
+    ayn = e * sin(argp) + tau * aycof;
+    LT = M + argp + node + tau * Lcof * axn;
+    U = mod2pi(LT - node);
+  }
   // P6: Kepler's equation for psi = E + argp:  psi - axn sin psi + ayn cos psi = U.
-  S U = mod2pi(LT - node);
   S psi = U;
   int iters = 0;
   for (int k = 0; k < 10; ++k) {
@@ -409,12 +696,12 @@ int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3],
   // P8: short-period periodics (J2).
   S k1 = 0.5 * g.j2 / pL;
   S k2 = k1 / pL;
-  S rk = rr * (1.0 - 1.5 * k2 * betaL * c.c41) + 0.5 * k1 * c.x1 * cos2u;
-  S uk = u - 0.25 * k2 * c.x7 * sin2u;
-  S nodek = node + 1.5 * k2 * c.cosi * sin2u;
-  S ik = c.i0 + 1.5 * k2 * c.cosi * c.sini * cos2u;
-  S rdotk = rdot - n / g.ke * k1 * c.x1 * sin2u;
-  S rfdotk = rfdot + n / g.ke * k1 * (c.x1 * cos2u + 1.5 * c.c41);
+  S rk = rr * (1.0 - 1.5 * k2 * betaL * c41) + 0.5 * k1 * x1 * cos2u;
+  S uk = u - 0.25 * k2 * x7 * sin2u;
+  S nodek = node + 1.5 * k2 * cosip * sin2u;
+  S ik = incp + 1.5 * k2 * cosip * sinip * cos2u;
+  S rdotk = rdot - n / g.ke * k1 * x1 * sin2u;
+  S rfdotk = rfdot + n / g.ke * k1 * (x1 * cos2u + 1.5 * c41);
   // P9: orientation vectors and the TEME state.
   S su = sin(uk), cu = cos(uk), sn = sin(nodek), cn = cos(nodek), si = sin(ik), ci = cos(ik);
   S mx = -sn * ci, my = cn * ci, mz = si;
@@ -469,6 +756,12 @@ void store_point(const double r[3], const double v[3], int code, int64_t P, int6
 extern "C" {
 
 int oracle_abi_version(void) { return 1; }
+
+// Reference instant of the elements' epoch row and of the times, as a Julian
+// date (whole + fraction); used only by the deep-space model's lunar and
+// solar arguments.  J2000.0 by default.
+void oracle_set_reference_jd(double whole, double frac) { g_ref_jd = whole + frac; }
+double oracle_reference_jd(void) { return g_ref_jd; }
 
 void oracle_wgs72(double* out5) { for (int k = 0; k < 5; ++k) out5[k] = kWgs72[k]; }
 
@@ -560,7 +853,7 @@ int oracle_propagate_points(const double* grav, int64_t n, const double* elem, i
 int oracle_detail_count(void) { return kD_COUNT; }
 
 // Initialisation constants per satellite, [n][44] in this order.
-enum { kI_COUNT = 44 };
+enum { kI_COUNT = 76 };
 int oracle_init_count(void) { return kI_COUNT; }
 int oracle_init(const double* grav, int64_t n, const double* elem, double* rec) {
   Gravity g;
@@ -574,7 +867,12 @@ int oracle_init(const double* grav, int64_t n, const double* elem, double* rec) 
         c.xi, c.eta, c.C1, c.C2, c.C3, c.C4, c.C5, c.Mdot, c.argpdot, c.nodedot, c.nodedot1,
         c.argpcof, c.Mcof, c.nodecf, c.t2cof, c.aycof, c.Lcof, c.dM0, c.sinM0,
         c.D2, c.D3, c.D4, c.t3cof, c.t4cof, c.t5cof, double(c.isimp), double(c.deep), double(c.epoch_code),
-        g.ke, g.j3oj2, g.vkms};
+        g.ke, g.j3oj2, g.vkms,
+        double(c.resonant), c.dedt, c.didt, c.dMdt, c.dnodedt, c.dargpdt, c.Mbody0[0], c.Mbody0[1],
+        c.pe2[0], c.pe3[0], c.pi2[0], c.pi3[0], c.pl2[0], c.pl3[0], c.pl4[0], c.pgh2[0], c.pgh3[0], c.pgh4[0],
+        c.ph2[0], c.ph3[0],
+        c.pe2[1], c.pe3[1], c.pi2[1], c.pi3[1], c.pl2[1], c.pl3[1], c.pl4[1], c.pgh2[1], c.pgh3[1], c.pgh4[1],
+        c.ph2[1], c.ph3[1]};
     std::memcpy(rec + i * kI_COUNT, out, sizeof out);
   }
   return 0;

@@ -1,0 +1,366 @@
+"""Pins of the oracle's deep-space model (SDP4: lunar and solar perturbations
+of orbits with periods of 225 min or more, non-resonant classes), each against
+something other than the oracle's own formulas:
+
+- its astronomical constants against textbook values (the Sun's and Moon's mean
+  elements referred to 1900 January 0.5, the obliquity, the lunar inclination,
+  the bodies' tidal strengths from their mean motions and the lunar mass);
+- its five secular rates against Lagrange's planetary equations applied to the
+  quadrupole tidal potential of each body, averaged numerically over the
+  satellite's orbit and the body's circular orbit, with the body orbit planes
+  built here from the node, inclination and obliquity by rotation matrices;
+- its ten twice-the-body-anomaly periodic coefficients per body against the
+  same equations applied to the cos 2f and sin 2f parts of the potential
+  averaged over the satellite's orbit only, integrated over the body's motion;
+- its body-eccentricity terms against the first-order modulation of the
+  body-direction-independent part of that potential;
+- the low-inclination formulation (no division by sin i) against the direct
+  one at the switch between them (continuity to second order);
+- the resonance flags, the code-3 check and the reference-epoch handling.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+RE = 6378.135
+KE = None
+
+
+def ke():
+    global KE
+    if KE is None:
+        KE = oracle.ke()
+    return KE
+
+
+def elem(a_km, e, inc, node, argp, M, bstar=0.0, epoch=0.0):
+    n = ke() * (a_km / RE) ** -1.5
+    return np.array([[n], [e], [inc], [node], [argp], [M], [bstar], [epoch]], dtype=np.float64)
+
+
+# ----------------------------------------------------------- geometry ------
+def rot1(x):
+    c, s = math.cos(x), math.sin(x)
+    return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+
+
+def rot3(x):
+    c, s = math.cos(x), math.sin(x)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def perifocal(inc, node, argp):
+    R = rot3(node) @ rot1(inc) @ rot3(argp)
+    return R[:, 0], R[:, 1]
+
+
+NE = 96
+EGRID = 2 * np.pi * np.arange(NE) / NE
+
+
+def orbit_average(fun, e, inc, node, argp):
+    """Mean over the mean anomaly of fun(r) for a unit-semi-major-axis orbit
+    (quadrature in the eccentric anomaly with weight dM/dE, exact for the
+    trigonometric polynomials met here)."""
+    P, Q = perifocal(inc, node, argp)
+    b = math.sqrt(1 - e * e)
+    r = (np.cos(EGRID) - e)[:, None] * P + (b * np.sin(EGRID))[:, None] * Q
+    return float(np.mean(fun(r) * (1 - e * np.cos(EGRID))))
+
+
+def lagrange_rates(R, n, e, inc, node, argp):
+    """Lagrange's planetary equations for a disturbing function R(e, i, node,
+    argp) proportional to a^2 (a = 1), averaged over the mean anomaly; returns
+    the rates of (e, i, M, argp + cos i node, sin i node): the model's variables."""
+    d = 1e-6
+    f = lambda **kw: R(**{**dict(e=e, inc=inc, node=node, argp=argp), **kw})
+    dRe = (f(e=e + d) - f(e=e - d)) / (2 * d)
+    dRi = (f(inc=inc + d) - f(inc=inc - d)) / (2 * d)
+    dRO = (f(node=node + d) - f(node=node - d)) / (2 * d)
+    dRw = (f(argp=argp + d) - f(argp=argp - d)) / (2 * d)
+    R0 = f()
+    b = math.sqrt(1 - e * e)
+    de = -b / (n * e) * dRw
+    di = (math.cos(inc) * dRw - dRO) / (n * b * math.sin(inc))
+    dO = dRi / (n * b * math.sin(inc))
+    dw = b / (n * e) * dRe - math.cos(inc) / (n * b * math.sin(inc)) * dRi
+    dM = -2.0 * (2.0 * R0) / n - (1 - e * e) / (n * e) * dRe   # -2/(n a) dR/da with dR/da = 2R/a
+    return np.array([de, di, dM, dw + math.cos(inc) * dO, math.sin(inc) * dO])
+
+
+# The published model's constants (stated here once; the first test pins them
+# to the textbook quantities they stand for).
+N_SUN, N_MOON = 1.19459e-5, 1.5835218e-4          # rad/min
+E_SUN, E_MOON = 0.01675, 0.05490
+C1_SUN, C1_MOON = 2.9864797e-6, 4.7968065e-7
+SIN_EPS = 0.39785416
+SIN_MOON_INC = 0.089683511
+SUN_PERIGEE = math.atan2(-0.98088458, 0.1945905)  # argument of the solar perigee from the equinox
+
+
+def moon_node(day):
+    return 4.5236020 - 9.2422029e-4 * day
+
+
+def moon_perigee(day):
+    return 5.8351514 + 0.0019443680 * day
+
+
+def body_frames(day):
+    """(P, Q) of the Sun's and the Moon's orbits in equatorial coordinates: P
+    toward the body's perigee, Q a quarter turn ahead in its orbit plane."""
+    eps = math.asin(SIN_EPS)
+    Rs = rot1(eps) @ rot3(SUN_PERIGEE)
+    nl, pl = moon_node(day), moon_perigee(day)
+    Rm = rot1(eps) @ rot3(nl) @ rot1(math.asin(SIN_MOON_INC)) @ rot3(pl - nl)
+    return (Rs[:, 0], Rs[:, 1]), (Rm[:, 0], Rm[:, 1])
+
+
+def random_deep(rng, lo_inc=0.15, hi_inc=2.9):
+    a = rng.uniform(3.6, 6.6) * RE
+    e = rng.uniform(0.01, 0.75)
+    inc = rng.uniform(lo_inc, hi_inc)
+    node, argp, M = rng.uniform(0, 2 * math.pi, 3)
+    epoch = rng.uniform(-3000, 9000)
+    return a, e, inc, node, argp, M, epoch
+
+
+# ------------------------------------------------------------- constants --
+def test_lunar_solar_constants_are_the_textbook_quantities():
+    deg = math.pi / 180
+    # Newcomb's Sun and Brown's Moon, mean elements referred to JD 2415020.0:
+    # Sun mean anomaly 358.475845 + 0.985600267 d; Moon mean longitude
+    # 270.434164 + 13.1763965268 d, perigee 334.329556 + 0.1114040803 d,
+    # node 259.183275 - 0.0529539222 d (degrees, d in days); the model keeps 7-8
+    # significant digits (angles to 1e-6 rad)
+    assert 6.2565837 == pytest.approx(358.475845 * deg, abs=1e-6)
+    assert 0.017201977 == pytest.approx(0.985600267 * deg, rel=1e-6)   # the model's rate is 4e-7 faster
+    assert 4.7199672 == pytest.approx(270.434164 * deg, abs=1e-6)
+    assert 0.22997150 == pytest.approx(13.1763965268 * deg, rel=5e-8)
+    assert moon_perigee(0) == pytest.approx(334.329556 * deg, abs=1e-6)
+    assert 0.0019443680 == pytest.approx(0.1114040803 * deg, rel=5e-8)
+    assert moon_node(0) == pytest.approx(259.183275 * deg, abs=1e-6)
+    assert -9.2422029e-4 == pytest.approx(-0.0529539222 * deg, rel=5e-8)
+    # mean motions: the anomalistic year (365.2596 d) and month (27.5546 d)
+    assert N_SUN * 1440 * 365.2596 == pytest.approx(2 * math.pi, rel=2e-5)
+    assert N_MOON * 1440 * 27.55455 == pytest.approx(2 * math.pi, rel=2e-5)
+    # orbit eccentricities of the Earth and the Moon
+    assert E_SUN == pytest.approx(0.016751, abs=2e-5) and E_MOON == pytest.approx(0.0549, abs=1e-4)
+    # obliquity 23.44 deg (23.439 at J2000, 23.452 at 1900); lunar inclination 5.145 deg
+    assert math.degrees(math.asin(SIN_EPS)) == pytest.approx(23.445, abs=0.01)
+    assert math.cos(math.asin(SIN_EPS)) == pytest.approx(0.91744867, abs=2e-8)
+    assert math.degrees(math.asin(SIN_MOON_INC)) == pytest.approx(5.145, abs=0.001)
+    # cos of the Moon's inclination to the equator, cos eps cos i_L - sin eps sin i_L cos node:
+    # the model's two coefficients are those products
+    iL = math.asin(SIN_MOON_INC)
+    assert 0.91375164 == pytest.approx(0.91744867 * math.cos(iL), abs=2e-8)
+    assert 0.03568096 == pytest.approx(SIN_EPS * SIN_MOON_INC, abs=2e-8)
+    # solar perigee longitude 281.22 deg (1900: 281.2208); the two components a unit vector
+    assert math.hypot(-0.98088458, 0.1945905) == pytest.approx(1.0, abs=1e-7)
+    assert math.degrees(SUN_PERIGEE) % 360 == pytest.approx(281.2208, abs=0.01)
+    # tidal strengths: c1 = (mu_body / a_body^3) / (4 n_body): the Sun's mu/a^3 is
+    # n_sun^2 (Kepler's third law), the Moon's its mass fraction 1/82.3 times n_moon^2
+    assert C1_SUN == pytest.approx(N_SUN / 4, rel=2e-6)
+    assert C1_MOON == pytest.approx(N_MOON / 4 / 82.3, rel=4e-3)
+
+
+# --------------------------------------------------------- secular rates --
+def test_secular_rates_follow_lagrange_equations_on_the_doubly_averaged_quadrupole():
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for _ in range(12):
+        a, e, inc, node, argp, M, epoch = random_deep(rng)
+        c = oracle.init_constants(elem(a, e, inc, node, argp, M, epoch=epoch))
+        assert c["deep"][0] == 1.0
+        n = c["n0pp"][0]
+        (Ps, Qs), (Pm, Qm) = body_frames(2451545.0 - 2415020.0 + epoch)
+        want = np.zeros(5)
+        for (P, Q), nb, c1 in (((Ps, Qs), N_SUN, C1_SUN), ((Pm, Qm), N_MOON, C1_MOON)):
+            h = np.cross(P, Q)
+            C = 4 * c1 * nb   # mu_body / a_body^3
+            # quadrupole averaged over the body's circular orbit: C (r^2 / 4 - 3/4 (r.h)^2)
+            R = lambda e, inc, node, argp, C=C, h=h: C * orbit_average(
+                lambda r: 0.25 * np.sum(r * r, axis=1) - 0.75 * (r @ h) ** 2, e, inc, node, argp)
+            want += lagrange_rates(R, n, e, inc, node, argp)
+        # model: e, i, M, and argp + cos i node, sin i node from its argp and node rates
+        got = np.array([c["dedt"][0], c["didt"][0], c["dMdt"][0],
+                        c["dargpdt"][0] + math.cos(inc) * c["dnodedt"][0], math.sin(inc) * c["dnodedt"][0]])
+        worst = max(worst, float(np.max(np.abs(got - want)) / np.max(np.abs(want))))
+    assert worst < 1e-7, worst
+
+
+def test_near_equatorial_orbits_take_no_lunar_solar_node_rate():
+    for inc in (0.01, 0.05, math.pi - 0.04):
+        c = oracle.init_constants(elem(26560.0, 0.1, inc, 1.0, 2.0, 0.5))
+        assert c["dnodedt"][0] == 0.0
+        assert c["dedt"][0] != 0.0
+
+
+# ------------------------------------------------------ periodic terms ------
+def test_periodic_coefficients_integrate_the_twice_anomaly_terms():
+    """The body's direction p(f) = cos f P + sin f Q: the satellite-averaged
+    quadrupole's cos 2f and sin 2f parts, C 3/4 <(r.P)^2 - (r.Q)^2> and
+    C 3/2 <(r.P)(r.Q)>, in Lagrange's equations give rates L_c cos 2f + L_s sin 2f,
+    whose integral over the body's motion (f' = n_body) is (L_c sin 2f - L_s cos 2f)
+    / (2 n_body); the model writes the change as el2 (sin^2 f / 2 - 1/4) + el3
+    (-sin f cos f / 2) = -(el2 cos 2f + el3 sin 2f) / 4, so el2 = 2 L_s / n_body
+    and el3 = -2 L_c / n_body."""
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    names = ("pe", "pi", "pl", "pgh", "ph")
+    for _ in range(8):
+        a, e, inc, node, argp, M, epoch = random_deep(rng)
+        c = oracle.init_constants(elem(a, e, inc, node, argp, M, epoch=epoch))
+        n = c["n0pp"][0]
+        frames = body_frames(2451545.0 - 2415020.0 + epoch)
+        for body, (P, Q), nb, c1 in (("sun", frames[0], N_SUN, C1_SUN), ("moon", frames[1], N_MOON, C1_MOON)):
+            C = 4 * c1 * nb
+            Rc = lambda e, inc, node, argp, C=C, P=P, Q=Q: C * 0.75 * orbit_average(
+                lambda r: (r @ P) ** 2 - (r @ Q) ** 2, e, inc, node, argp)
+            Rs = lambda e, inc, node, argp, C=C, P=P, Q=Q: C * 1.5 * orbit_average(
+                lambda r: (r @ P) * (r @ Q), e, inc, node, argp)
+            want2 = 2 * lagrange_rates(Rs, n, e, inc, node, argp) / nb
+            want3 = -2 * lagrange_rates(Rc, n, e, inc, node, argp) / nb
+            got2 = np.array([c[f"{k}2_{body}"][0] for k in names])
+            got3 = np.array([c[f"{k}3_{body}"][0] for k in names])
+            scale = max(np.abs(want2).max(), np.abs(want3).max())
+            worst = max(worst, max(np.abs(got2 - want2).max(), np.abs(got3 - want3).max()) / scale)
+    assert worst < 1e-7, worst
+
+
+def test_body_eccentricity_terms_modulate_the_direction_free_part():
+    """To first order in the body's eccentricity its distance factor (a_b/r_b)^3
+    is 1 + 3 e_b cos M_b; the model keeps that modulation of the part of the
+    averaged quadrupole that does not depend on the body's direction when it is
+    written with the body's in-plane axes, -C <r^2> / 2, for M and for
+    argp + cos i node: pl4 = 3 e_b L_M / n_b and pgh4 = 3 e_b L_gh / n_b (the
+    sine of the body's anomaly integrates cos M_b over its motion)."""
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        a, e, inc, node, argp, M, epoch = random_deep(rng)
+        c = oracle.init_constants(elem(a, e, inc, node, argp, M, epoch=epoch))
+        n = c["n0pp"][0]
+        for body, nb, c1, eb in (("sun", N_SUN, C1_SUN, E_SUN), ("moon", N_MOON, C1_MOON, E_MOON)):
+            C = 4 * c1 * nb
+            R = lambda e, inc, node, argp, C=C: -0.5 * C * orbit_average(
+                lambda r: np.sum(r * r, axis=1), e, inc, node, argp)
+            L = lagrange_rates(R, n, e, inc, node, argp)
+            assert c[f"pl4_{body}"][0] == pytest.approx(3 * eb * L[2] / nb, rel=1e-7)
+            assert c[f"pgh4_{body}"][0] == pytest.approx(3 * eb * L[3] / nb, rel=1e-7)
+
+
+# ------------------------------------------------------- propagation ------
+def _pinc_at_epoch(el):
+    """The model's lunar-solar inclination change at epoch, from its own
+    (pinned) coefficients and the bodies' anomalies at epoch."""
+    c = oracle.init_constants(el)
+    total = 0.0
+    for body, M0, eb in (("sun", "Msun0", E_SUN), ("moon", "Mmoon0", E_MOON)):
+        Mb = c[M0][0]
+        f = Mb + 2 * eb * math.sin(Mb)
+        sf = math.sin(f)
+        total += c[f"pi2_{body}"][0] * (0.5 * sf * sf - 0.25) + c[f"pi3_{body}"][0] * (-0.5 * sf * math.cos(f))
+    return total
+
+
+def test_low_inclination_formulation_at_the_switch():
+    """Below 0.2 rad of perturbed inclination the model applies the node and
+    inclination changes to the components (sin i sin node, sin i cos node) and
+    carries the longitude argp + cos i node (plus M), instead of dividing by
+    sin i.  With the perturbed inclination's cosine in that longitude the
+    inclination change enters it twice, so the two forms differ at the switch
+    by one first-order term: the argument of perigee moves by -pinc node sin i
+    (node in [0, 2 pi)); everything else agrees to second order in the changes
+    (~1e-4 rad).  For element sets whose perturbed inclination at epoch is
+    0.2 -+ 1e-9 the state difference must be that shift of the argument of
+    perigee to within millimetres."""
+    t = np.zeros(1)
+    for node, argp, M in ((0.3, 1.0, 0.4), (2.5, 4.0, 2.0), (5.0, 0.2, 5.5), (1.2, 2.9, 3.3)):
+        i_star = 0.2
+        for _ in range(4):   # i_star + pinc(i_star) = 0.2
+            i_star = 0.2 - _pinc_at_epoch(elem(26560.0, 0.05, i_star, node, argp, M))
+        pinc = 0.2 - i_star
+        rl, vl, el = oracle.propagate(elem(26560.0, 0.05, i_star - 1e-9, node, argp, M), t)
+        rh, vh, eh = oracle.propagate(elem(26560.0, 0.05, i_star + 1e-9, node, argp, M), t)
+        assert el[0, 0] == 0 and eh[0, 0] == 0
+        d = 1e-6
+        rp, vp, _ = oracle.propagate(elem(26560.0, 0.05, i_star + 1e-9, node, argp + d, M), t)
+        rm, vm, _ = oracle.propagate(elem(26560.0, 0.05, i_star + 1e-9, node, argp - d, M), t)
+        shift = -pinc * node * math.sin(0.2)
+        want_r = (rp - rm) / (2 * d) * shift
+        want_v = (vp - vm) / (2 * d) * shift
+        assert np.max(np.abs(rl - rh - want_r)) < 2e-3 + 0.01 * np.max(np.abs(want_r)), node
+        assert np.max(np.abs(vl - vh - want_v)) < 2e-7 + 0.01 * np.max(np.abs(want_v)), node
+        assert np.max(np.abs(want_r)) > 0.01   # the shift is resolved
+
+
+def test_resonant_classes_flagged_and_non_resonant_propagated():
+    cases = [(42164.0, 2e-4, 0.05, True),     # geosynchronous: 24 h
+             (26600.0, 0.72, 1.107, True),    # Molniya: 12 h, e >= 0.5
+             (26560.0, 0.01, 0.96, False),    # GPS: 12 h but e < 0.5
+             (29600.0, 0.001, 0.98, False),   # Galileo
+             (24400.0, 0.72, 0.12, False),    # transfer orbit, low inclination
+             (12500.0, 0.01, 1.7, False)]     # 232-minute period
+    t = np.linspace(0.0, 2880.0, 9)
+    for a, e, inc, res in cases:
+        el = elem(a, e, inc, 0.7, 1.3, 0.2)
+        c = oracle.init_constants(el)
+        assert c["deep"][0] == 1.0 and c["resonant"][0] == float(res), a
+        r, v, err = oracle.propagate(el, t)
+        if res:
+            assert np.all(err == 7) and np.all(np.isnan(r))
+        else:
+            assert np.all(err == 0) and np.all(np.isfinite(r))
+            # a closed orbit of the stated size
+            rad = np.linalg.norm(r[:, 0, :], axis=0)
+            assert np.all(rad > a * (1 - e) * 0.99) and np.all(rad < a * (1 + e) * 1.01)
+
+
+def test_reference_epoch_moves_the_lunar_solar_arguments_only():
+    """The same elements at a different absolute epoch: the near-Earth part is
+    unchanged, the deep-space one changes; shifting the reference and the epoch
+    row together (same absolute instant) changes nothing."""
+    t = np.linspace(0.0, 1440.0, 5)
+    el = elem(26560.0, 0.01, 0.96, 0.7, 1.3, 0.2, epoch=100.0)
+    leo = elem(6900.0, 0.001, 0.9, 0.7, 1.3, 0.2, epoch=100.0)
+    r0, _, _ = oracle.propagate(el, t)
+    rl0, _, _ = oracle.propagate(leo, t)
+    with oracle.reference_jd(2451545.0, 3650.0):
+        r1, _, _ = oracle.propagate(el, t)
+        rl1, _, _ = oracle.propagate(leo, t)
+        el2 = el.copy()
+        el2[7] -= 3650.0
+        r2, _, _ = oracle.propagate(el2, t + 1440.0 * -3650.0)
+    assert np.array_equal(rl0, rl1)
+    assert np.max(np.abs(r1 - r0)) > 0.1
+    assert np.max(np.abs(r2 - r0)) < 1e-6
+
+
+def test_code_3_when_lunar_solar_terms_push_e_out_of_range():
+    """The lunar-solar eccentricity change is proportional to the epoch
+    eccentricity: a near-parabolic deep-space set can be pushed past e = 1
+    (code 3, NaN state), checked after code 1 and before codes 4 and 6."""
+    rng = np.random.default_rng(3)
+    n = 400
+    el = np.empty((8, n))
+    el[0] = rng.uniform(0.003, 0.02, n)
+    el[1] = rng.uniform(0.998, 0.99999, n)
+    el[2] = rng.uniform(0.3, 2.8, n)
+    el[3:6] = rng.uniform(0, 2 * math.pi, (3, n))
+    el[6] = 0.0
+    el[7] = 0.0
+    t = np.linspace(0.0, 20 * 1440.0, 21)
+    r, v, err = oracle.propagate(el, t)
+    sat = np.repeat(np.arange(n), t.size)
+    _, _, e2, d = oracle.propagate_points(el, sat, np.tile(t, n), detail=True)
+    assert np.array_equal(e2, err.ravel())
+    three = err.ravel() == 3
+    assert three.sum() > 50
+    # the perturbed eccentricity recorded at a code-3 point is outside [0, 1]
+    ep = d["e"][three]
+    assert np.all((ep < 0) | (ep > 1))
+    assert np.all(np.isnan(r.reshape(3, -1)[:, three]))
+    assert set(np.unique(err).tolist()) <= {0, 1, 3, 4, 6, 7}

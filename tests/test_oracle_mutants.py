@@ -19,12 +19,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sgp4_oracle.cpp")
 
 MUTANTS = [
-    ("short-period radius coefficient", "0.5 * k1 * c.x1 * cos2u", "0.25 * k1 * c.x1 * cos2u"),
-    ("short-period argument of latitude sign", "u - 0.25 * k2 * c.x7 * sin2u", "u + 0.25 * k2 * c.x7 * sin2u"),
-    ("short-period node sign", "node + 1.5 * k2 * c.cosi * sin2u", "node - 1.5 * k2 * c.cosi * sin2u"),
-    ("short-period inclination dropped", "c.i0 + 1.5 * k2 * c.cosi * c.sini * cos2u", "c.i0 + 0.0 * k2"),
-    ("short-period radial rate dropped", "rdot - n / g.ke * k1 * c.x1 * sin2u", "rdot - 0.0 * k1"),
-    ("short-period transverse rate coefficient", "(c.x1 * cos2u + 1.5 * c.c41)", "(c.x1 * cos2u + 0.5 * c.c41)"),
+    ("short-period radius coefficient", "0.5 * k1 * x1 * cos2u", "0.25 * k1 * x1 * cos2u"),
+    ("short-period argument of latitude sign", "u - 0.25 * k2 * x7 * sin2u", "u + 0.25 * k2 * x7 * sin2u"),
+    ("short-period node sign", "node + 1.5 * k2 * cosip * sin2u", "node - 1.5 * k2 * cosip * sin2u"),
+    ("short-period inclination dropped", "incp + 1.5 * k2 * cosip * sinip * cos2u", "incp + 0.0 * k2"),
+    ("short-period radial rate dropped", "rdot - n / g.ke * k1 * x1 * sin2u", "rdot - 0.0 * k1"),
+    ("short-period transverse rate coefficient", "(x1 * cos2u + 1.5 * c41)", "(x1 * cos2u + 0.5 * c41)"),
     ("D3 coefficient", "(17.0 * c.a0pp + c.s)", "(16.0 * c.a0pp + c.s)"),
     ("D4 power of a0", "(2.0 / 3.0) * c.a0pp * c.a0pp * c.xi", "(2.0 / 3.0) * c.a0pp * c.xi"),
     ("t4cof coefficient", "12.0 * c.D2 + 10.0 * C1sq", "12.0 * c.D2 + 8.0 * C1sq"),
@@ -32,7 +32,8 @@ MUTANTS = [
     ("velocity unit", "g->vkms = g->radius * g->ke / 60.0", "g->vkms = g->radius * g->ke / 61.0"),
     ("first-order node rate", "c.nodedot1 = -T1 * c.cosi", "c.nodedot1 = -0.9 * T1 * c.cosi"),
     ("un-Kozai coefficient", "0.75 * J2 * c.c41", "1.5 * J2 * c.c41"),
-    ("J3 long-period eccentricity sign", "ayn = e * sin(argp) + tau * c.aycof", "ayn = e * sin(argp) - tau * c.aycof"),
+    ("J3 long-period eccentricity sign", "ayn = e * sin(argp) + tau * aycof;\n    LT = L +",
+     "ayn = e * sin(argp) - tau * aycof;\n    LT = L +"),
     ("first-order mean-anomaly rate", "0.5 * T1 * c.beta0 * c.c41", "0.6 * T1 * c.beta0 * c.c41"),
     ("C2 eta-squared coefficient", "(1.0 + 1.5 * eta2 + e0eta", "(1.0 + 2.5 * eta2 + e0eta"),
     ("C4 first-order bracket", "e0 * (0.5 + 2.0 * eta2)", "e0 * (0.5 + 1.0 * eta2)"),
@@ -69,6 +70,25 @@ MUTANTS = [
     ("drag periodic epoch offset", "c.dM0 = cube(1.0 + c.eta * cos(c.M0));", "c.dM0 = cube(1.0 + c.eta * sin(c.M0));"),
     ("drag eccentricity epoch offset", "c.sinM0 = sin(c.M0);", "c.sinM0 = cos(c.M0);"),
     ("J3 drag term sign in M", "M = M_df + dargp + dM;", "M = M_df - dargp + dM;"),
+    # deep space: lunar-solar constants, the averaged-quadrupole algebra, the
+    # periodic and body-eccentricity coefficients, the low-inclination form
+    ("lunar node rate sign", "4.5236020 - 9.2422029e-4 * day", "4.5236020 + 9.2422029e-4 * day"),
+    ("lunar perigee epoch value", "5.8351514 + 0.0019443680 * day", "5.8351614 + 0.0019443680 * day"),
+    ("Moon inclination constant", "kMoonCosI0 = 0.91375164", "kMoonCosI0 = 0.91385164"),
+    ("solar strength", "{2.9864797e-6, 4.7968065e-7}", "{2.9964797e-6, 4.7968065e-7}"),
+    ("quadrupole direction cosine sign", "const S a7 = -cg * sh + sg * ci * ch;", "const S a7 = cg * sh + sg * ci * ch;"),
+    ("z31 coefficient", "b.z31 = 12.0 * x1 * x1 - 3.0 * x3 * x3;", "b.z31 = 11.0 * x1 * x1 - 3.0 * x3 * x3;"),
+    ("z1 eccentricity-free term", "b.z1 = 2.0 * z1 + beta2 * b.z31;", "b.z1 = 2.0 * z1 + b.z31;"),
+    ("s1 coefficient", "b.s1 = -15.0 * e * b.s4;", "b.s1 = -14.0 * e * b.s4;"),
+    ("secular M constant", "(q.z1 + q.z3 - 14.0 - 6.0 * e2)", "(q.z1 + q.z3 - 13.0 - 6.0 * e2)"),
+    ("secular node-in-perigee term", "c.dargpdt = dgh - cim * dh;", "c.dargpdt = dgh + cim * dh;"),
+    ("periodic inclination coefficient", "c.pi3[k] = 2.0 * q.s2 * (q.z13 - q.z11);", "c.pi3[k] = 2.0 * q.s2 * (q.z13 + q.z11);"),
+    ("body-eccentricity M term", "(-21.0 - 9.0 * e2) * kEBody[k]", "(-20.0 - 9.0 * e2) * kEBody[k]"),
+    ("body-eccentricity perigee term", "c.pgh4[k] = -18.0 * q.s4 * kEBody[k];", "c.pgh4[k] = -16.0 * q.s4 * kEBody[k];"),
+    ("low-inclination node component sign", "S alf = sinip * sno + (ph * cno + pinc * cosip * sno);",
+     "S alf = sinip * sno + (ph * cno - pinc * cosip * sno);"),
+    ("low-inclination longitude term", "(pl + pgh - pinc * node * sinip)", "(pl + pgh + pinc * node * sinip)"),
+    ("24 h resonance band", "nv < 0.0052359877 && nv > 0.0034906585", "nv < 0.0052359877 && nv > 0.0044906585"),
 ]
 
 
@@ -83,6 +103,7 @@ def _run(mutant, workdir):
                    check=True)
     env = dict(os.environ, SGP4_ORACLE_LIB=lib)
     p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_deep.py"),
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, p.returncode
