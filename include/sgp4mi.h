@@ -6,8 +6,10 @@
  * Roehrich 1980 as revised by Hoots et al. 2004 and Vallado et al. 2006, with
  * WGS72 constants) gives the TEME position in km and velocity in km/s.
  * Validity problems do not abort the batch: each point carries an error code
- * (section 2.2, "Control Flow").  Only near-Earth element sets (period under
- * 225 minutes, section 6) are propagated; deep-space sets are flagged.
+ * (section 2.2, "Control Flow").  Element sets with periods of 225 minutes or
+ * more take the deep-space model's lunar and solar terms (section 6 names deep
+ * space as the variant the paper leaves out); its 12 h and 24 h resonant
+ * classes are flagged, not propagated.
  *
  * Conventions for every call
  *   - Pointers are DEVICE pointers owned by the caller unless marked "host".
@@ -30,12 +32,14 @@
  *     err[p], with P points; p = i*T + j on a dense grid, the CSR position on a
  *     ragged one.  r and v are double for SGP4_FP64 and float otherwise.
  *   - Point codes: 0 ok; 1 mean eccentricity outside [-0.001, 1) (or outside
- *     [0, 1) at epoch); 2 recovered mean motion not positive; 4 semi-latus
- *     rectum negative; 6 decayed (radius below one earth radius; the state is
- *     still written); 7 deep-space element set, not propagated; 8 ragged
- *     point that the offsets place in no satellite's list (malformed offsets
- *     given to sgp4_propagate_ragged without a plan).  Codes 1, 2, 4, 7 and 8
- *     write NaN to r and v.
+ *     [0, 1) at epoch); 2 recovered mean motion not positive; 3 deep space:
+ *     the lunar-solar terms move the eccentricity outside [0, 1]; 4
+ *     semi-latus rectum negative; 6 decayed (radius below one earth radius;
+ *     the state is still written); 7 resonant deep-space element set (24 h,
+ *     or 12 h with e >= 0.5), not propagated; 8 ragged point that the
+ *     offsets place in no satellite's list (malformed offsets given to
+ *     sgp4_propagate_ragged without a plan).  Codes 1, 2, 3, 4, 7 and 8 write
+ *     NaN to r and v.
  */
 #ifndef SGP4MI_H
 #define SGP4MI_H
@@ -80,10 +84,19 @@ size_t sgp4_consts_bytes(int64_t n);
  * propagation).  grav (host, nullable) is {mu km^3/s^2, R km, J2, J3, J4};
  * NULL selects WGS72 (section 2.1).  J3 != 0 with J2 == 0 is rejected.
  * elem: device float64 [8][n].  consts: device, sgp4_consts_bytes(n) bytes,
- * written.  sat_flags: device uint8 [n] or NULL; written with bit0 deep-space,
- * bit1 simplified drag (perigee below 220 km), bit2 invalid elements.
- * 0 <= n < 2^31. */
+ * written.  sat_flags: device uint8 [n] or NULL; written with bit0 deep space
+ * (period of 225 min or more), bit1 simplified drag (perigee below 220 km,
+ * and every deep-space set), bit2 invalid elements, bit3 resonant deep space
+ * (not propagated, code 7).  0 <= n < 2^31.  The deep-space terms need the
+ * absolute epoch: sgp4_init takes the epoch row as days after J2000.0
+ * (JD 2451545.0, the default reference of sgp4_text_parse). */
 int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, uint8_t* sat_flags, void* stream);
+/* As sgp4_init with the reference instant of the epoch row and of the times
+ * given: ref_jd (host) {whole, frac} Julian date, NULL = J2000.0 (not finite:
+ * SGP4_E_ARG).  Only the deep-space terms (their lunar and solar arguments)
+ * depend on it. */
+int sgp4_init_ex(const double* grav, const double* ref_jd, int64_t n, const double* elem, void* consts,
+                 uint8_t* sat_flags, void* stream);
 
 /* Dense N x T propagation (section 2.2: f applied over satellites x times).
  * t: device float64 [T].  r, v: device [3][n*T] of double (FP64) or float;
@@ -140,6 +153,11 @@ int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T,
 int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
                             int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
                             size_t ws_bytes, void* stream);
+/* As sgp4_propagate_elements with the reference instant ref_jd of
+ * sgp4_init_ex. */
+int sgp4_propagate_elements_ex(const double* grav, const double* ref_jd, int64_t n, const double* elem,
+                               const double* t, int64_t T, int precision, void* r, void* v, uint8_t* err,
+                               uint8_t* sat_flags, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- screening --
  * Conjunction screening of a dense propagation output (the catalogue-wide use
@@ -284,7 +302,8 @@ void sgp4_plan_destroy(sgp4_plan* plan);
  * [8][n] elements consts was initialised from (the gravity model is read from
  * consts); gr and gv device [3][n*T] of double
  * (FP64) or float (FP32_MIXED), gv nullable (zero).  Points with codes 1, 2,
- * 4, 7 contribute nothing.  gelem: device float64 [7][n].  FP32 is rejected
+ * 3, 4, 7 contribute nothing.  Deep-space satellites are not differentiated:
+ * their gelem columns are NaN.  gelem: device float64 [7][n].  FP32 is rejected
  * (SGP4_E_PRECISION).  One 256-lane workgroup per satellite: n < 2^24 (else
  * SGP4_E_SIZE). */
 int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
@@ -295,9 +314,12 @@ int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t,
  * jac[(c * 7 + m) * n*T + i*T + j] = d s_c / d theta_m at satellite i, time j,
  * with s = (r_x, r_y, r_z, v_x, v_y, v_z) (km, km/s) and theta as for sgp4_vjp.
  * jac: device float64 [6][7][n*T], written in full; NaN where the point's
- * code is 1, 2, 4 or 7.  elem, consts, t as for sgp4_vjp.  Computed by one
- * reverse sweep per state component, so it costs about six VJPs.  FP32 is
- * rejected (SGP4_E_PRECISION).  n < 2^24 as for sgp4_vjp. */
+ * code is 1, 2, 3, 4 or 7 and at every point of a deep-space satellite (not
+ * differentiated).  elem, consts, t as for sgp4_vjp.  Computed in forward
+ * mode: the seven element tangents carried through one pass of the
+ * propagation (in two groups of four and three directions), each point's
+ * columns stored as they come.  FP32 is rejected (SGP4_E_PRECISION).
+ * n < 2^24 as for sgp4_vjp. */
 int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
                   double* jac, void* stream);
 

@@ -68,8 +68,18 @@ class Record:
         return self.consts.device
 
 
-def init(elem: torch.Tensor, grav: Optional[Sequence[float]] = None) -> Record:
-    """Initialisation: elements float64 [8, n] (device) -> constant record."""
+def _ref(ref_jd):
+    if ref_jd is None:
+        return None
+    w, f = (ref_jd, 0.0) if isinstance(ref_jd, (int, float)) else ref_jd
+    return (ctypes.c_double * 2)(float(w), float(f))
+
+
+def init(elem: torch.Tensor, grav: Optional[Sequence[float]] = None, ref_jd=None) -> Record:
+    """Initialisation: elements float64 [8, n] (device) -> constant record.
+    ref_jd: the reference instant of the epoch row and the times as a Julian
+    date (a number or (whole, frac)); None = J2000.0.  Only the deep-space
+    terms depend on it (sgp4_init_ex)."""
     _need(elem, torch.float64, "elem")
     if elem.dim() != 2 or elem.shape[0] != 8:
         raise ValueError("elem must have shape [8, n]")
@@ -80,8 +90,8 @@ def init(elem: torch.Tensor, grav: Optional[Sequence[float]] = None) -> Record:
     if grav is not None:
         g = (ctypes.c_double * 5)(*[float(x) for x in grav])
     with torch.cuda.device(elem.device):
-        _native.check(_native.lib().sgp4_init(g, n, _ptr(elem), _ptr(consts), _ptr(flags), _stream(elem.device)),
-                      "sgp4_init")
+        _native.check(_native.lib().sgp4_init_ex(g, _ref(ref_jd), n, _ptr(elem), _ptr(consts), _ptr(flags),
+                                                 _stream(elem.device)), "sgp4_init_ex")
     return Record(consts, n, flags[:n], elem)
 
 
@@ -168,12 +178,14 @@ class RaggedPlan:
 
 
 def propagate_elements(elem: torch.Tensor, t: torch.Tensor, precision="fp64", grav: Optional[Sequence[float]] = None,
-                       out=None, workspace: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None):
+                       out=None, workspace: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None,
+                       ref_jd=None):
     """Elements float64 [8, n] straight to r [3, n, T], v [3, n, T], err [n, T] in one
     call (sgp4_propagate_elements): a fused initialise-and-propagate launch for
     short time lists, initialisation into `workspace` (uint8, at least
     consts_bytes(n) bytes) and the dense launch for longer ones when given.
-    flags: optional uint8 [n] tensor that receives the satellite flags."""
+    flags: optional uint8 [n] tensor that receives the satellite flags.  ref_jd as
+    for init."""
     p = _prec(precision)
     _need(elem, torch.float64, "elem")
     if elem.dim() != 2 or elem.shape[0] != 8:
@@ -199,9 +211,9 @@ def propagate_elements(elem: torch.Tensor, t: torch.Tensor, precision="fp64", gr
         if flags.numel() < n:
             raise ValueError("flags must hold n entries")
     with torch.cuda.device(elem.device):
-        _native.check(_native.lib().sgp4_propagate_elements(
-            g, n, _ptr(elem), _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err), _ptr(flags), _ptr(workspace), ws_bytes,
-            _stream(elem.device)), "sgp4_propagate_elements")
+        _native.check(_native.lib().sgp4_propagate_elements_ex(
+            g, _ref(ref_jd), n, _ptr(elem), _ptr(t), T, p, _ptr(r), _ptr(v), _ptr(err), _ptr(flags), _ptr(workspace),
+            ws_bytes, _stream(elem.device)), "sgp4_propagate_elements_ex")
     return r, v, err
 
 

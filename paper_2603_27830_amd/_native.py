@@ -26,10 +26,13 @@ SIGNATURES = [
     ("sgp4_strerror", ctypes.c_char_p, [_int]),
     ("sgp4_consts_bytes", ctypes.c_size_t, [_i64]),
     ("sgp4_init", _int, [_dp, _i64, _vp, _vp, _vp, _vp]),
+    ("sgp4_init_ex", _int, [_dp, _dp, _i64, _vp, _vp, _vp, _vp]),
     ("sgp4_propagate", _int, [_vp, _i64, _vp, _i64, _int, _vp, _vp, _vp, _vp]),
     ("sgp4_propagate_ex", _int, [_vp, _i64, _vp, _i64, _int, _vp, _vp, _vp, _int, _vp]),
     ("sgp4_propagate_elements", _int, [_dp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                        _vp]),
+    ("sgp4_propagate_elements_ex", _int, [_dp, _dp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.c_size_t, _vp]),
     ("sgp4_screen_workspace_bytes", ctypes.c_size_t, [_i64, _i64]),
     ("sgp4_screen", _int, [_vp, _int, _vp, _i64, _i64, ctypes.c_double, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                            _vp]),

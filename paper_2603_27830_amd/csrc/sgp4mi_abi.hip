@@ -17,16 +17,17 @@
 #include "sgp4mi_common.h"
 
 namespace sgp4mi {
-hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
-                       hipStream_t s);
+hipError_t launch_init(const double g[5], double ref_day, int64_t n, const double* elem, void* consts,
+                       uint8_t* user_flags, hipStream_t s);
 hipError_t launch_dense(int precision, const void* consts, int64_t n, const double* t, int64_t T, void* r, void* v,
                         uint8_t* err, int block, bool vec, unsigned grid, bool tiles, bool flat, hipStream_t s);
 bool dense_tiles_fit(int64_t n, int64_t T, int block);
 bool dense_grid_fits(int64_t n, int block);
 bool fused_fits(int64_t n, int64_t T);
 bool dense_flat_fits(int64_t n, int64_t T, int block);
-hipError_t launch_fused(int precision, const double g[5], int64_t n, const double* elem, const double* t, int64_t T,
-                        void* r, void* v, uint8_t* err, uint8_t* user_flags, hipStream_t s);
+hipError_t launch_fused(int precision, const double g[5], double ref_day, int64_t n, const double* elem,
+                        const double* t, int64_t T, void* r, void* v, uint8_t* err, uint8_t* user_flags,
+                        hipStream_t s);
 int64_t fused_max_T();
 hipError_t launch_screen(const void* r, bool fp64, const uint8_t* err, int64_t n, int64_t T, double D, int64_t cap,
                          int32_t* pairs, double* dist, unsigned long long* count, void* ws, int mode, hipStream_t s);
@@ -69,6 +70,15 @@ int default_dense(int precision, int64_t n, int64_t T) {
   const int block = precision == SGP4_FP64 ? 256 : 512;
   if (!dense_tiles_fit(n, T, block)) return 512 | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_PERSISTENT | SGP4_CFG_PER_CU(4);
   return block | SGP4_CFG_SCALAR_CONSTS | SGP4_CFG_TILES;
+}
+
+// Reference instant of the epoch row (host {whole, frac} Julian date, NULL =
+// J2000.0) as days after JD 2415020.0, the origin of the lunar and solar
+// arguments of the deep-space terms; false when not finite.
+bool ref_day_of(const double* ref_jd, double* day) {
+  const double w = ref_jd ? ref_jd[0] : 2451545.0, f = ref_jd ? ref_jd[1] : 0.0;
+  *day = (w - 2415020.0) + f;
+  return std::isfinite(*day);
 }
 
 int check_gravity(const double* g) {
@@ -195,7 +205,7 @@ void cache_store(const std::string& key, int mode, int block, unsigned grid, dou
 // ================================================================== C ABI ==
 extern "C" {
 
-int sgp4_version(void) { return 1; }
+int sgp4_version(void) { return 2; }
 
 const char* sgp4_strerror(int code) {
   switch (code) {
@@ -215,12 +225,19 @@ const char* sgp4_strerror(int code) {
 
 size_t sgp4_consts_bytes(int64_t n) { return n < 0 ? 0 : record_bytes(n); }
 
-int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, uint8_t* sat_flags, void* stream) {
+int sgp4_init_ex(const double* grav, const double* ref_jd, int64_t n, const double* elem, void* consts,
+                 uint8_t* sat_flags, void* stream) {
   if (n < 0 || n > kMaxSats) return SGP4_E_SIZE;
   if (!consts || (n > 0 && !elem)) return SGP4_E_ARG;
   const double* g = grav ? grav : kWgs72;
   if (int rc = check_gravity(g)) return rc;
-  return hip_status(launch_init(g, n, elem, consts, sat_flags, static_cast<hipStream_t>(stream)));
+  double day;
+  if (!ref_day_of(ref_jd, &day)) return SGP4_E_ARG;
+  return hip_status(launch_init(g, day, n, elem, consts, sat_flags, static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, uint8_t* sat_flags, void* stream) {
+  return sgp4_init_ex(grav, nullptr, n, elem, consts, sat_flags, stream);
 }
 
 int sgp4_propagate_ex(const void* consts, int64_t n, const double* t, int64_t T, int precision, void* r, void* v,
@@ -260,13 +277,15 @@ int sgp4_propagate(const void* consts, int64_t n, const double* t, int64_t T, in
   return sgp4_propagate_ex(consts, n, t, T, precision, r, v, err, default_dense(precision, n, T), stream);
 }
 
-int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
-                            int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
-                            size_t ws_bytes, void* stream) {
+int sgp4_propagate_elements_ex(const double* grav, const double* ref_jd, int64_t n, const double* elem,
+                               const double* t, int64_t T, int precision, void* r, void* v, uint8_t* err,
+                               uint8_t* sat_flags, void* ws, size_t ws_bytes, void* stream) {
   if (n < 0 || T < 0 || n > kMaxSats || mul_overflows(n, T) || mul_overflows(n * T, 3)) return SGP4_E_SIZE;
   if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
   const double* g = grav ? grav : kWgs72;
   if (int rc = check_gravity(g)) return rc;
+  double day;
+  if (!ref_day_of(ref_jd, &day)) return SGP4_E_ARG;
   if (ws && ws_bytes < sgp4_consts_bytes(n)) return SGP4_E_WORKSPACE;
   if (n == 0 || T == 0) return SGP4_OK;
   if (!elem || !t || !r || !v || !err) return SGP4_E_ARG;
@@ -274,10 +293,17 @@ int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, c
   if (T <= kFusedMaxT || !ws) {
     if (T > fused_max_T()) return SGP4_E_WORKSPACE;
     if (!fused_fits(n, T)) return ws ? SGP4_E_WORKSPACE : SGP4_E_SIZE;
-    return hip_status(launch_fused(precision, g, n, elem, t, T, r, v, err, sat_flags, s));
+    return hip_status(launch_fused(precision, g, day, n, elem, t, T, r, v, err, sat_flags, s));
   }
-  if (int rc = hip_status(launch_init(g, n, elem, ws, sat_flags, s))) return rc;
+  if (int rc = hip_status(launch_init(g, day, n, elem, ws, sat_flags, s))) return rc;
   return sgp4_propagate(ws, n, t, T, precision, r, v, err, stream);
+}
+
+int sgp4_propagate_elements(const double* grav, int64_t n, const double* elem, const double* t, int64_t T,
+                            int precision, void* r, void* v, uint8_t* err, uint8_t* sat_flags, void* ws,
+                            size_t ws_bytes, void* stream) {
+  return sgp4_propagate_elements_ex(grav, nullptr, n, elem, t, T, precision, r, v, err, sat_flags, ws, ws_bytes,
+                                    stream);
 }
 
 size_t sgp4_screen_workspace_bytes(int64_t n, int64_t T) {

@@ -16,7 +16,12 @@ namespace sgp4mi {
 //   [n slots of kSlotBytes = 512 bytes, one per satellite]:
 //       bytes   0..271  kNRec doubles (full-precision constants)
 //       bytes 272..407  kNRec floats  (the same constants rounded to float)
-//       bytes 408..411  uint32 info: bits 0-7 satellite code, bit 8 isimp
+//       bytes 408..411  uint32 info: bits 0-7 satellite code, bit 8 isimp,
+//                       bit 9 deep space
+//   [n deep-space slots of kDeepBytes = 256 bytes, one per satellite]: the
+//       lunar-solar secular rates, the long-period coefficients of the Sun and
+//       the Moon and their mean anomalies at epoch (written and read only for
+//       satellites with the deep-space bit)
 // One contiguous slot per satellite: a wavefront working on one satellite
 // fetches its constants with a few wide loads from one base address.
 enum Rec : int {
@@ -30,11 +35,34 @@ enum Rec : int {
 // kHF32: float copies of radius, velocity unit and k2 (three floats in the
 // eight bytes of slots kHF32 and kHF32 + 1), so the float paths read them
 // without a conversion per point.
-enum Hdr : int { kHMagic, kHN, kHNpad, kHKe, kHRadius, kHVkms, kHK2, kHJ2, kHJ3oJ2, kHJ4, kHMu, kHF32, kHCount = 64 };
+// kHRefDay: the reference instant of the epoch row, in days after JD 2415020.0
+// (1900 January 0.5, the origin of the lunar and solar arguments).
+enum Hdr : int {
+  kHMagic, kHN, kHNpad, kHKe, kHRadius, kHVkms, kHK2, kHJ2, kHJ3oJ2, kHJ4, kHMu, kHF32, kHRefDay = kHF32 + 2,
+  kHCount = 64
+};
 constexpr double kMagic = 20260331.0;
 
 constexpr uint32_t kInfoCodeMask = 0xffu;
 constexpr uint32_t kInfoIsimp = 0x100u;
+constexpr uint32_t kInfoDeep = 0x200u;
+
+// Deep-space slot: lunar-solar secular rates (rad/min), the Sun's and the
+// Moon's mean anomalies at epoch, and per body (Sun, then Moon) the
+// coefficients of the long-period terms of e, i, M, argp + cos i node and
+// sin i node: the twice-anomaly pairs (x2, x3) and the body-eccentricity
+// terms (l4, gh4).
+enum DeepRec : int {
+  kDeDt, kDiDt, kDMDt, kDNodeDt, kDArgpDt, kDMb0, kDMb1,
+  kDPer0 = 7,  // per body k: kDPer0 + 12 k + one of the offsets below
+  kNDeep = kDPer0 + 24
+};
+enum DeepPer : int { kPe2, kPe3, kPi2, kPi3, kPl2, kPl3, kPl4, kPgh2, kPgh3, kPgh4, kPh2, kPh3, kNPer };
+constexpr int kDeepBytes = 256;
+struct alignas(16) DeepSlot {
+  double d[kDeepBytes / 8];
+};
+static_assert(kNDeep * 8 <= kDeepBytes, "deep-space slot overflow");
 
 // Point code of a ragged point that the offsets place in no satellite's list
 // (malformed offsets given to the plan-less ragged call); r and v are NaN.
@@ -58,25 +86,28 @@ static_assert(sizeof(Slot) == kSlotBytes, "slot size");
 inline bool grid_fits(uint64_t groups, uint64_t block) { return groups * block <= 0xffffffffull; }
 
 inline int64_t npad_of(int64_t n) { return (n + 63) / 64 * 64; }
-inline size_t record_bytes(int64_t n) { return size_t(kHCount) * 8 + size_t(kSlotBytes) * size_t(n > 0 ? n : 0); }
+inline size_t record_bytes(int64_t n) {
+  return size_t(kHCount) * 8 + size_t(kSlotBytes + kDeepBytes) * size_t(n > 0 ? n : 0);
+}
 
 struct RecordView {
   const double* hdr;
   const Slot* slots;
+  const DeepSlot* deep;
 };
 
 inline RecordView view_of(const void* base, int64_t n) {
-  (void)n;
   RecordView v;
   const char* b = static_cast<const char*>(base);
   v.hdr = reinterpret_cast<const double*>(b);
   v.slots = reinterpret_cast<const Slot*>(b + kHCount * 8);
+  v.deep = reinterpret_cast<const DeepSlot*>(b + kHCount * 8 + size_t(kSlotBytes) * size_t(n > 0 ? n : 0));
   return v;
 }
 
 // Gravity-derived scalars read by the kernels (from the record header).
 struct Grav {
-  double ke, radius, vkms, k2;
+  double ke, radius, vkms, k2, j3oj2;
   float radius_f, vkms_f, k2_f;
 };
 template <class T> __device__ __forceinline__ T grav_radius(const Grav& g);

@@ -28,13 +28,14 @@ struct FusedArgs {
   const double* t;      // [T]
   uint8_t* user_flags;  // nullable
   double mu, radius, j2, j3, j4;
+  double ref_day;       // reference instant of the epoch row, days after JD 2415020.0
   uint32_t tt;
 };
 
 // The satellite's constants as the two-stage path reads them from its slot:
 // the double values, and their float roundings for the float types.
 template <class TS, class TP>
-__device__ __forceinline__ SatC<TS, TP> sat_of(const double* x, uint32_t info) {
+__device__ __forceinline__ SatC<TS, TP> sat_of(const double* x, uint32_t info, const double* deep) {
   SatC<TS, TP> c;
   c.M0 = TS(x[kM0]); c.Mdot = TS(x[kMdot]); c.argp0 = TS(x[kArgp0]); c.argpdot = TS(x[kArgpdot]);
   c.node0 = TS(x[kNode0]); c.nodedot = TS(x[kNodedot]); c.nodecf = TS(x[kNodecf]); c.C1 = TS(x[kC1]);
@@ -47,6 +48,7 @@ __device__ __forceinline__ SatC<TS, TP> sat_of(const double* x, uint32_t info) {
   c.Lcof = TP(x[kLcof]); c.c41 = TP(x[kC41]); c.x1 = TP(x[kX1]); c.x7 = TP(x[kX7]); c.cosi = TP(x[kCosi]);
   c.sini = TP(x[kSini]); c.i0 = TP(x[kI0]);
   c.info = info;
+  c.deep = deep;
   return c;
 }
 
@@ -58,14 +60,16 @@ __device__ __forceinline__ Grav grav_of(const FusedArgs& a) {
   g.radius = a.radius;
   g.vkms = a.radius * g.ke / 60.0;
   g.k2 = 0.5 * a.j2;
+  g.j3oj2 = (a.j3 == 0.0) ? 0.0 : a.j3 / a.j2;
   g.radius_f = float(a.radius);
   g.vkms_f = float(a.radius * g.ke / 60.0);
   g.k2_f = float(0.5 * a.j2);
   return g;
 }
 
-// Initialisation of satellite i into rec (kNRec doubles); returns the info word.
-__device__ __forceinline__ uint32_t init_sat(const FusedArgs& a, const Grav& g, int64_t i, double* rec,
+// Initialisation of satellite i into rec (kNRec doubles) and, for a
+// propagated deep-space satellite, deep (kNDeep doubles); returns the info word.
+__device__ __forceinline__ uint32_t init_sat(const FusedArgs& a, const Grav& g, int64_t i, double* rec, double* deep,
                                              bool write_flags) {
   double el[7];
 #pragma unroll
@@ -74,17 +78,19 @@ __device__ __forceinline__ uint32_t init_sat(const FusedArgs& a, const Grav& g, 
   const double j3oj2 = (a.j3 == 0.0) ? 0.0 : a.j3 / a.j2;
   GravIn gi{a.radius, a.j2, a.j4, g.ke, j3oj2};
   uint32_t code;
-  bool isimp;
-  init_record<double>(gi, el, rec, &code, &isimp);
+  bool isimp, dsp;
+  init_record<double>(gi, el, rec, &code, &isimp, &dsp);
   rec[kEpochMin] = 1440.0 * epoch;
+  if (dsp && code == 0) init_deep(el, rec[kN0pp], a.ref_day + epoch, deep);
   if (write_flags && a.user_flags) {
     uint8_t f = 0;
-    if (code == 7) f |= 1;
+    if (dsp) f |= 1;
     if (isimp) f |= 2;
     if (code == 1 || code == 2) f |= 4;
+    if (code == 7) f |= 8;
     a.user_flags[i] = f;
   }
-  return code | (isimp ? kInfoIsimp : 0u);
+  return code | (isimp ? kInfoIsimp : 0u) | (dsp ? kInfoDeep : 0u);
 }
 
 // tt = 1: one wavefront per 64 satellites, each lane initialises and
@@ -94,17 +100,18 @@ __global__ void __launch_bounds__(64) fused_one_kernel(FusedArgs a, Out<TP, kOff
   const int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
   if (i >= a.n) return;
   const Grav g = grav_of(a);
-  double rec[kNRec];
-  const uint32_t info = init_sat(a, g, i, rec, true);
-  const SatC<TS, TP> c = sat_of<TS, TP>(rec, info);
+  double rec[kNRec], deep[kNDeep];
+  const uint32_t info = init_sat(a, g, i, rec, deep, true);
+  const SatC<TS, TP> c = sat_of<TS, TP>(rec, info, deep);
   PointState<TP> s;
-  const uint32_t code = sgp4_point<TS, TP>(c, g, a.t[0], s);
+  const uint32_t code = (c.info & kInfoDeep) ? deep_point<TS, TP>(c, g, a.t[0], s) : sgp4_point<TS, TP>(c, g, a.t[0], s);
   out.put(i, code, s);
 }
 
 template <class TS, class TP, bool kOff32>
 __global__ void __launch_bounds__(64 * kFusedTT) fused_kernel(FusedArgs a, Out<TP, kOff32> out) {
   __shared__ double lrec[kNRec][64];
+  __shared__ double ldeep[64][kNDeep];
   __shared__ uint32_t linfo[64];
   const int64_t i0 = int64_t(blockIdx.x) * 64;
   const Grav g = grav_of(a);
@@ -112,7 +119,7 @@ __global__ void __launch_bounds__(64 * kFusedTT) fused_kernel(FusedArgs a, Out<T
     const int64_t i = i0 + threadIdx.x;
     if (i < a.n) {
       double rec[kNRec];
-      const uint32_t info = init_sat(a, g, i, rec, blockIdx.y == 0);
+      const uint32_t info = init_sat(a, g, i, rec, ldeep[threadIdx.x], blockIdx.y == 0);
 #pragma unroll
       for (int k = 0; k < kNRec; ++k) lrec[k][threadIdx.x] = rec[k];
       linfo[threadIdx.x] = info;
@@ -127,9 +134,9 @@ __global__ void __launch_bounds__(64 * kFusedTT) fused_kernel(FusedArgs a, Out<T
   double x[kNRec];
 #pragma unroll
   for (int k = 0; k < kNRec; ++k) x[k] = lrec[k][sl];
-  const SatC<TS, TP> c = sat_of<TS, TP>(x, linfo[sl]);
+  const SatC<TS, TP> c = sat_of<TS, TP>(x, linfo[sl], ldeep[sl]);
   PointState<TP> s;
-  const uint32_t code = sgp4_point<TS, TP>(c, g, a.t[j], s);
+  const uint32_t code = (c.info & kInfoDeep) ? deep_point<TS, TP>(c, g, a.t[j], s) : sgp4_point<TS, TP>(c, g, a.t[j], s);
   // kOff32: every point index is below 2^30 and fits 32-bit arithmetic
   out.put(kOff32 ? int64_t(uint32_t(i) * uint32_t(a.T) + uint32_t(j)) : i * a.T + j, code, s);
 }
@@ -168,8 +175,9 @@ bool fused_fits(int64_t n, int64_t T) {
   return grid_fits(uint64_t((n + 63) / 64), 64 * (tt > 0 ? tt : 1));
 }
 
-hipError_t launch_fused(int precision, const double g[5], int64_t n, const double* elem, const double* t, int64_t T,
-                        void* r, void* v, uint8_t* err, uint8_t* user_flags, hipStream_t s) {
+hipError_t launch_fused(int precision, const double g[5], double ref_day, int64_t n, const double* elem,
+                        const double* t, int64_t T, void* r, void* v, uint8_t* err, uint8_t* user_flags,
+                        hipStream_t s) {
   FusedArgs a;
   a.n = n;
   a.T = T;
@@ -177,6 +185,7 @@ hipError_t launch_fused(int precision, const double g[5], int64_t n, const doubl
   a.t = t;
   a.user_flags = user_flags;
   a.mu = g[0]; a.radius = g[1]; a.j2 = g[2]; a.j3 = g[3]; a.j4 = g[4];
+  a.ref_day = ref_day;
   a.tt = uint32_t(T < kFusedTT ? T : kFusedTT);
   switch (precision) {
     case 0: fused_t<double, double>(a, r, v, err, s); break;

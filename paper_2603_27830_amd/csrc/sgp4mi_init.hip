@@ -11,8 +11,10 @@ struct InitArgs {
   const double* elem;   // [8][n]
   double* hdr;
   Slot* slots;
+  DeepSlot* deep;
   uint8_t* user_flags;  // nullable
   double mu, radius, j2, j3, j4;
+  double ref_day;       // reference instant of the epoch row, days after JD 2415020.0
 };
 
 // kStaged: the 64 records of the workgroup are assembled in LDS and copied
@@ -38,6 +40,7 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     h[kHJ3oJ2] = j3oj2;
     h[kHJ4] = a.j4;
     h[kHMu] = a.mu;
+    h[kHRefDay] = a.ref_day;
     float* hf = reinterpret_cast<float*>(h + kHF32);
     hf[0] = float(a.radius);
     hf[1] = float(a.radius * ke / 60.0);
@@ -55,8 +58,14 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     GravIn gi{a.radius, a.j2, a.j4, ke, j3oj2};
     double rec[kNRec];
     uint32_t code;
-    bool isimp;
-    init_record<double>(gi, el, rec, &code, &isimp);
+    bool isimp, deep;
+    init_record<double>(gi, el, rec, &code, &isimp, &deep);
+    if (deep && code == 0) {
+      double d[kNDeep];
+      init_deep(el, rec[kN0pp], a.ref_day + epoch, d);
+#pragma unroll
+      for (int k = 0; k < kNDeep; ++k) a.deep[i].d[k] = d[k];
+    }
     rec[kEpochMin] = 1440.0 * epoch;
     Slot* slot = kStaged ? &stage[threadIdx.x] : a.slots + i;
 #pragma unroll
@@ -64,10 +73,11 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
       slot->d[k] = rec[k];
       slot->f[k] = float(rec[k]);
     }
-    slot->info = code | (isimp ? kInfoIsimp : 0u);
+    slot->info = code | (isimp ? kInfoIsimp : 0u) | (deep ? kInfoDeep : 0u);
     if (a.user_flags) {
       uint8_t f = 0;
-      if (code == 7) f |= 1;
+      if (deep) f |= 1;
+      if (code == 7) f |= 8;
       if (isimp) f |= 2;
       if (code == 1 || code == 2) f |= 4;
       a.user_flags[i] = f;
@@ -88,8 +98,8 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
 // latency that a few hundred workgroups do not hide).
 constexpr int64_t kInitStagedFrom = 65536;
 
-hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* consts, uint8_t* user_flags,
-                       hipStream_t s) {
+hipError_t launch_init(const double g[5], double ref_day, int64_t n, const double* elem, void* consts,
+                       uint8_t* user_flags, hipStream_t s) {
   InitArgs a;
   a.n = n;
   a.npad = npad_of(n);
@@ -97,6 +107,8 @@ hipError_t launch_init(const double g[5], int64_t n, const double* elem, void* c
   char* b = static_cast<char*>(consts);
   a.hdr = reinterpret_cast<double*>(b);
   a.slots = reinterpret_cast<Slot*>(b + kHCount * 8);
+  a.deep = reinterpret_cast<DeepSlot*>(b + kHCount * 8 + size_t(kSlotBytes) * size_t(n));
+  a.ref_day = ref_day;
   a.user_flags = user_flags;
   a.mu = g[0]; a.radius = g[1]; a.j2 = g[2]; a.j3 = g[3]; a.j4 = g[4];
   const int64_t blocks = (n + 63) / 64;  // 64-wide: a short kernel spread over more compute units

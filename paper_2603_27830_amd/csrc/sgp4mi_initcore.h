@@ -83,11 +83,19 @@ struct GravIn {
   double radius, j2, j4, ke, j3oj2;
 };
 
+// Whether a deep-space orbit lies in a resonant class (24 h, or 12 h with
+// e >= 0.5), which the library flags instead of propagating.
+__device__ inline bool deep_resonant(double n, double e) {
+  return (n < 0.0052359877 && n > 0.0034906585) || (n >= 8.26e-3 && n <= 9.24e-3 && e >= 0.5);
+}
+
 // el: n0 (Kozai, rad/min), e0, i0, node0, argp0, M0, bstar.  Writes the
-// record entries (all but kEpochMin), the satellite code and the flag.
+// record entries (all but kEpochMin), the satellite code and the flags
+// (simplified drag; deep space: period of 225 min or more, which also takes
+// the simplified drag terms; resonant deep-space orbits get code 7).
 template <class S>
 __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S rec[kNRec], uint32_t* code_out,
-                                            bool* isimp_out) {
+                                            bool* isimp_out, bool* deep_out) {
   using ::cbrt;
   using ::fabs;
   using ::sqrt;
@@ -134,11 +142,15 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   const S qoms2 = qoms * qoms;
   const S qoms24 = qoms2 * qoms2;
 
-  const bool isimp = value(perigee_er) < 1.0 + 220.0 / R;
   uint32_t code = 0;
+  bool deep = false;
   if (!(value(ecco) >= 0.0 && value(ecco) < 1.0)) code = 1;
   else if (!(value(nbar) > 0.0)) code = 2;
-  else if (kTwoPi / value(nbar) >= 225.0) code = 7;
+  else if (kTwoPi / value(nbar) >= 225.0) {
+    deep = true;
+    if (deep_resonant(value(nbar), value(ecco))) code = 7;
+  }
+  const bool isimp = deep || value(perigee_er) < 1.0 + 220.0 / R;
 
   // Power-law drag coefficients.
   const S tsi = quot(1.0, abar - sfour);
@@ -220,6 +232,126 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   rec[kEpochMin] = S(0.0);
   *code_out = code;
   *isimp_out = isimp;
+  *deep_out = deep;
+}
+
+// ---------------------------------------------------------- deep space --
+// Lunar-solar part of the deep-space initialisation (Hujsak's terms in the
+// published model): from the satellite's epoch elements and the absolute
+// epoch, the secular rates and the long-period coefficients of the Sun's and
+// the Moon's quadrupole tidal potential, each averaged over the satellite's
+// orbit, and the two bodies' mean anomalies at epoch.  Double precision, one
+// lane per satellite.  day: epoch in days after JD 2415020.0.
+struct DeepBody {
+  double n, e, c1;  // mean motion (rad/min), orbit eccentricity, tidal strength / (4 n)
+};
+constexpr DeepBody kSun{1.19459e-5, 0.01675, 2.9864797e-6};
+constexpr DeepBody kMoon{1.5835218e-4, 0.05490, 4.7968065e-7};
+
+// Coefficients of one body whose orbit has perigee argument g (from its node
+// on the equator), inclination ib to the equator, and whose node lies h
+// before the satellite's node (cos/sin of each), for a satellite of
+// inclination i, perigee argument w, eccentricity e, mean motion n.  out: the
+// kNPer long-period coefficients; sec: the body's contributions to the rates
+// of e, i, M, argp + cos i node and sin i node (before the division by sin i).
+__device__ inline void deep_body(double cg, double sg, double cib, double sib, double ch, double sh, double cw,
+                                 double sw, double ci, double si, double e, double n, const DeepBody& b,
+                                 double* out, double sec[5]) {
+  const double e2 = e * e, beta2 = 1.0 - e2, beta = sqrt(beta2);
+  // body perigee (p) and its normal-plane axis (q) projected on the
+  // satellite's node line, its in-plane normal and its orbit pole
+  const double p1 = cg * ch + sg * cib * sh;
+  const double q1 = -sg * ch + cg * cib * sh;
+  const double pn = -cg * sh + sg * cib * ch;
+  const double qn = sg * sh + cg * cib * ch;
+  const double p2 = ci * pn + si * sg * sib;
+  const double q2 = ci * qn + si * cg * sib;
+  const double p3 = -si * pn + ci * sg * sib;
+  const double q3 = -si * qn + ci * cg * sib;
+  // ... then on the satellite's perigee direction (x*) and the direction a
+  // quarter turn ahead (y*); the pole components take sin w and cos w
+  const double xp = p1 * cw + p2 * sw, xq = q1 * cw + q2 * sw;
+  const double yp = -p1 * sw + p2 * cw, yq = -q1 * sw + q2 * cw;
+  const double zps = p3 * sw, zqs = q3 * sw, zpc = p3 * cw, zqc = q3 * cw;
+  const double zz1 = 12.0 * xp * xp - 3.0 * yp * yp;
+  const double zz2 = 24.0 * xp * xq - 6.0 * yp * yq;
+  const double zz3 = 12.0 * xq * xq - 3.0 * yq * yq;
+  const double z1 = 2.0 * (3.0 * (p1 * p1 + p2 * p2) + zz1 * e2) + beta2 * zz1;
+  const double z2 = 2.0 * (6.0 * (p1 * q1 + p2 * q2) + zz2 * e2) + beta2 * zz2;
+  const double z3 = 2.0 * (3.0 * (q1 * q1 + q2 * q2) + zz3 * e2) + beta2 * zz3;
+  const double z11 = -6.0 * p1 * p3 + e2 * (-24.0 * xp * zpc - 6.0 * yp * zps);
+  const double z12 = -6.0 * (p1 * q3 + q1 * p3) + e2 * (-24.0 * (xq * zpc + xp * zqc) - 6.0 * (yp * zqs + yq * zps));
+  const double z13 = -6.0 * q1 * q3 + e2 * (-24.0 * xq * zqc - 6.0 * yq * zqs);
+  const double z21 = 6.0 * p2 * p3 + e2 * (24.0 * xp * zps - 6.0 * yp * zpc);
+  const double z22 = 6.0 * (q2 * p3 + p2 * q3) + e2 * (24.0 * (xq * zps + xp * zqs) - 6.0 * (yq * zpc + yp * zqc));
+  const double z23 = 6.0 * q2 * q3 + e2 * (24.0 * xq * zqs - 6.0 * yq * zqc);
+  const double s3 = b.c1 / n;
+  const double s2 = -0.5 * s3 / beta;
+  const double s4 = s3 * beta;
+  const double s1 = -15.0 * e * s4;
+  const double s5 = xp * yp + xq * yq;
+  const double s6 = xq * yp + xp * yq;
+  const double s7 = xq * yq - xp * yp;
+  out[kPe2] = 2.0 * s1 * s6;
+  out[kPe3] = 2.0 * s1 * s7;
+  out[kPi2] = 2.0 * s2 * z12;
+  out[kPi3] = 2.0 * s2 * (z13 - z11);
+  out[kPl2] = -2.0 * s3 * z2;
+  out[kPl3] = -2.0 * s3 * (z3 - z1);
+  out[kPl4] = -2.0 * s3 * (-21.0 - 9.0 * e2) * b.e;
+  out[kPgh2] = 2.0 * s4 * zz2;
+  out[kPgh3] = 2.0 * s4 * (zz3 - zz1);
+  out[kPgh4] = -18.0 * s4 * b.e;
+  out[kPh2] = -2.0 * s2 * z22;
+  out[kPh3] = -2.0 * s2 * (z23 - z21);
+  sec[0] = s1 * b.n * s5;
+  sec[1] = s2 * b.n * (z11 + z13);
+  sec[2] = -b.n * s3 * (z1 + z3 - 14.0 - 6.0 * e2);
+  sec[3] = s4 * b.n * (zz1 + zz3 - 6.0);
+  sec[4] = -b.n * s2 * (z21 + z23);
+}
+
+// el: epoch elements as for init_record; n: recovered mean motion; day: days
+// after JD 2415020.0.  Writes the kNDeep entries of a deep-space slot.
+__device__ inline void init_deep(const double el[7], double n, double day, double* d) {
+  const double e = el[1], inc = el[2];
+  double si, ci, sw, cw, snd, cnd;
+  sincos_rr(inc, &si, &ci);
+  sincos_rr(el[4], &sw, &cw);
+  sincos_rr(el[3], &snd, &cnd);
+  // The Moon's orbit at epoch: node on the ecliptic, its inclination and node
+  // on the equator (spherical triangle with the obliquity), its perigee
+  // argument measured from that equatorial node.
+  const double sin_eps = 0.39785416, cos_eps = 0.91744867, sin_il = 0.089683511;
+  const double node_l = 4.5236020 - 9.2422029e-4 * day;
+  double sl, cl;
+  sincos_rr(node_l, &sl, &cl);
+  const double cib_m = 0.91375164 - 0.03568096 * cl;
+  const double sib_m = sqrt(1.0 - cib_m * cib_m);
+  const double sh_l = sin_il * sl / sib_m;
+  const double ch_l = sqrt(1.0 - sh_l * sh_l);
+  const double perigee_l = 5.8351514 + 0.0019443680 * day;
+  const double g_m = perigee_l + atan2(sin_eps * sl / sib_m, ch_l * cl + cos_eps * sh_l * sl) - node_l;
+  double sg_m, cg_m;
+  sincos_rr(g_m, &sg_m, &cg_m);
+  double sec_s[5], sec_m[5];
+  // Sun: node at the equinox, inclination the obliquity, perigee at 281.22 deg
+  deep_body(0.1945905, -0.98088458, cos_eps, sin_eps, cnd, snd, cw, sw, ci, si, e, n, kSun, d + kDPer0, sec_s);
+  deep_body(cg_m, sg_m, cib_m, sib_m, ch_l * cnd + sh_l * snd, snd * ch_l - cnd * sh_l, cw, sw, ci, si, e, n, kMoon,
+            d + kDPer0 + kNPer, sec_m);
+  // Satellite within 3 degrees of the equator: no lunar-solar node rate.
+  const bool flat = inc < 5.2359877e-2 || inc > kPi - 5.2359877e-2;
+  const double h = flat ? 0.0 : sec_s[4] + sec_m[4];
+  const double dnode = si != 0.0 ? h / si : h;
+  d[kDeDt] = sec_s[0] + sec_m[0];
+  d[kDiDt] = sec_s[1] + sec_m[1];
+  d[kDMDt] = sec_s[2] + sec_m[2];
+  d[kDNodeDt] = dnode;
+  d[kDArgpDt] = sec_s[3] + sec_m[3] - ci * dnode;
+  const double ms = 6.2565837 + 0.017201977 * day;
+  const double mm = 4.7199672 + 0.22997150 * day - perigee_l;
+  d[kDMb0] = ms - kTwoPi * floor(ms * kInvTwoPi);
+  d[kDMb1] = mm - kTwoPi * floor(mm * kInvTwoPi);
 }
 
 }  // namespace sgp4mi

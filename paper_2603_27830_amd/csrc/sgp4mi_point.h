@@ -30,6 +30,7 @@ struct SatC {
   // periodic (TP)
   TP eta, dM0, sinM0, aycof, Lcof, c41, x1, x7, cosi, sini, i0;
   uint32_t info;
+  const double* deep;  // the deep-space slot's entries (read only when info has kInfoDeep)
 };
 
 // Global-address-space view of a slot, for loads the compiler keeps as
@@ -87,12 +88,16 @@ __device__ __forceinline__ SatC<TS, TP> load_from(P sp, PP pp) {
 
 template <class TS, class TP, bool kVec>
 __device__ __forceinline__ SatC<TS, TP> load_sat(const RecordView& rv, int64_t i) {
+  SatC<TS, TP> c;
   if (kVec) {
     const GSlot v = lane_slot(rv.slots + i);
-    return load_from<TS, TP, GSlot, GSlot>(v, v);
+    c = load_from<TS, TP, GSlot, GSlot>(v, v);
+  } else {
+    const CSlot cp = (CSlot)(rv.slots + i);
+    c = load_from<TS, TP, CSlot, CSlot>(cp, cp);
   }
-  const CSlot cp = (CSlot)(rv.slots + i);
-  return load_from<TS, TP, CSlot, CSlot>(cp, cp);
+  c.deep = rv.deep[i].d;
+  return c;
 }
 
 __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
@@ -103,6 +108,7 @@ __device__ __forceinline__ Grav load_grav(const RecordView& rv) {
   g.radius = h[kHRadius];
   g.vkms = h[kHVkms];
   g.k2 = h[kHK2];
+  g.j3oj2 = h[kHJ3oJ2];
   const __attribute__((address_space(4))) float* f = (const __attribute__((address_space(4))) float*)(h + kHF32);
   g.radius_f = f[0];
   g.vkms_f = f[1];
@@ -220,70 +226,34 @@ struct PointState {
   bool ok;
 };
 
-// Returns the point's code (0, 1, 2, 4, 6 or 7).  r and v are written, and ok
-// set, for codes 0 and 6 only.
+// Inclination functions and J3 coefficients the periodic terms use: the
+// epoch's (per-satellite constants) in near-Earth propagation, the
+// lunar-solar perturbed ones (per point) in deep space.
+template <class TS, class TP>
+struct Incl {
+  TP c41, x1, x7, cosi, sini, i0, aycof, Lcof;
+};
+
+// Long-period (J3) and short-period (J2) periodics, Kepler's equation,
+// orientation and the TEME state, from the mean elements a, e (already
+// floored) and the angles M, argp, node (unreduced).  Returns 0, 4 or 6.
 //
 // Reformulations relative to the textbook order, each an identity up to
-// rounding: sin M from sin/cos of the drag-free M by a small rotation (FP64;
-// the float paths take the hardware sine of M); the
-// Kepler iteration carries psi - U and rotates (sin psi, cos psi) by each
-// Newton step; the argument of latitude u never leaves its (sin, cos) pair
-// (no atan2: the short-period correction is a rotation of the normalised
-// pair); sin/cos of the corrected inclination rotate those of i0.  Rotations
-// fall back to a full evaluation when the angle exceeds kRotMax.
+// rounding: the Kepler iteration carries psi - U and rotates (sin psi,
+// cos psi) by each Newton step; the argument of latitude u never leaves its
+// (sin, cos) pair (no atan2: the short-period correction is a rotation of the
+// normalised pair); sin/cos of the corrected inclination rotate those of i0.
+// Rotations fall back to a full evaluation when the angle exceeds kRotMax.
 template <class TS, class TP>
-__device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav& g, double t_abs, PointState<TP>& out) {
+__device__ __forceinline__ uint32_t sgp4_tail(const Grav& g, TP a, TP e, TS M, TS argp, TS node,
+                                              const Incl<TS, TP>& q, PointState<TP>& out) {
   using TR = Trig<TS, TP>;
-  out.ok = false;
-  const uint32_t scode = c.info & kInfoCodeMask;
-  if (scode) return scode;
-
-  // Secular gravity.
-  const TS t = TS(t_abs - c.epoch_min);
-  const TS t2 = t * t;
-  const TS Mdf = lin(c.M0, c.Mdot, t);
-  const TS argpdf = lin(c.argp0, c.argpdot, t);
-  TS node = lin(c.node0, c.nodedot, t) + c.nodecf * t2;
-  // Secular drag.
-  TS A = TS(1) - c.C1 * t;
-  TS Ed = c.bC4 * t;
-  TS Ld = c.t2cof * t2;
-  TS M = Mdf, argp = argpdf;
-  if (!(c.info & kInfoIsimp)) {
-    TP sM, cM;
-    TR::sc_damped(Mdf, &sM, &cM);
-    const TP x = TP(1) + c.eta * cM;
-    const TS dM = c.Mcof * TS(x * x * x - c.dM0);
-    const TS dargp = c.argpcof * t;
-    const TS dMa = dargp + dM;
-    M = Mdf + dMa;
-    argp = argpdf - dMa;
-    const TS t3 = t2 * t, t4 = t3 * t;
-    A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
-    // Float paths: one hardware sine of M costs less than the rotation.
-    if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
-    else rotate_small(&sM, &cM, TP(dMa));
-    Ed = Ed + c.bC5 * TS(sM - c.sinM0);
-    Ld = Ld + c.t3cof * t3 + t4 * lin(c.t4cof, c.t5cof, t);
-  }
-  const TS a_s = c.a0pp * A * A;
-  const TS e_s = c.e0 - Ed;
-  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
-  // Angles stay unreduced: every one of them only enters through sin/cos,
-  // whose own reduction handles any size met here.
-  M = M + c.n0pp * Ld;
-
   // Long-period periodics (J3).
-  // Eccentricity floor 1e-6, taken after the rounding to TP (rounding is
-  // monotonic, so this equals rounding the floored value).  e_s is not NaN
-  // here, so the maximum is the floor: one instruction in float instead of a
-  // compare and two selects.
-  const TP a = TP(a_s), e = vmax(TP(e_s), TP(1.0e-6));
   TP sw, cw;
   TR::sc_damped(argp, &sw, &cw);
   const TP axn = e * cw;
   const TP tau = rcp(a * (TP(1) - e * e));
-  const TP ayn = e * sw + tau * c.aycof;
+  const TP ayn = e * sw + tau * q.aycof;
 
   // Kepler: psi - axn sin psi + ayn cos psi = U, Newton from psi = U with the
   // step clamped to +-0.95; dpsi = psi - U.  A lane is done once its step is
@@ -294,7 +264,7 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   // wavefront is done (at most 10 steps).
   // U = L_T - node, with the mean longitude L = M + argp + node and its J3
   // long-period correction L_T = L + tau L_cof a_xN: node cancels.
-  const TS U = M + argp + TS(tau * c.Lcof * axn);
+  const TS U = M + argp + TS(tau * q.Lcof * axn);
   TP sp, cp;
   TR::sc(U, &sp, &cp);
   TP dpsi = TP(0);
@@ -337,13 +307,13 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const TP nk = ra * ra * ra;  // n / ke = a^-3/2
   // 1.5 c41 as c41 + c41 / 2 (one instruction reading one scalar register
   // twice; 1.5 is no inline constant); the same single rounding of 1.5 c41
-  const TP c41h = vfma(c.c41, TP(0.5), c.c41);
-  const TP mrt = rl * (TP(1) - k2 * betal * c41h) + TP(0.5) * k1 * c.x1 * cos2u;
-  const TP du = TP(-0.25) * k2 * c.x7 * sin2u;
-  const TP dnode = TP(1.5) * k2 * c.cosi * sin2u;
-  const TP dinc = TP(1.5) * k2 * c.cosi * c.sini * cos2u;
-  const TP mvt = rdotl - nk * k1 * c.x1 * sin2u;
-  const TP rvdot = rvdotl + nk * k1 * vfma(c.x1, cos2u, c41h);
+  const TP c41h = vfma(q.c41, TP(0.5), q.c41);
+  const TP mrt = rl * (TP(1) - k2 * betal * c41h) + TP(0.5) * k1 * q.x1 * cos2u;
+  const TP du = TP(-0.25) * k2 * q.x7 * sin2u;
+  const TP dnode = TP(1.5) * k2 * q.cosi * sin2u;
+  const TP dinc = TP(1.5) * k2 * q.cosi * q.sini * cos2u;
+  const TP mvt = rdotl - nk * k1 * q.x1 * sin2u;
+  const TP rvdot = rvdotl + nk * k1 * vfma(q.x1, cos2u, c41h);
 
   // Orientation: sin/cos of u_k = u + du, i_k = i0 + dinc, node_k = node + dnode.
   TP ssu, csu;
@@ -360,9 +330,9 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   } else {
     TR::sc(TS(arctan2(sinu, cosu) + du), &ssu, &csu);
   }
-  TP sinc = c.sini, cinc = c.cosi;
+  TP sinc = q.sini, cinc = q.cosi;
   if (vabs(dinc) <= TP(kRotMax)) rotate_small(&sinc, &cinc, dinc);
-  else TR::sc(TS(c.i0 + dinc), &sinc, &cinc);
+  else TR::sc(TS(q.i0 + dinc), &sinc, &cinc);
   TP snod, cnod;
   TR::sc(node + TS(dnode), &snod, &cnod);
 
@@ -377,6 +347,179 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   out.v[2] = vk * (mvt * uz + rvdot * vz);
   out.ok = true;
   return (mrt < TP(1)) ? 6u : 0u;
+}
+
+
+// Deep space (period of 225 min or more, non-resonant): the near-Earth
+// secular terms with the simplified drag, the lunar-solar secular rates, then
+// the Sun's and the Moon's long-period terms on the mean elements (each body's
+// mean anomaly advanced by its mean motion, its true anomaly to first order in
+// its eccentricity); below 0.2 rad of perturbed inclination the node and
+// inclination changes are applied to (sin i sin node, sin i cos node) and the
+// longitude argp + cos i node is carried instead, so nothing divides by
+// sin i.  The inclination functions of the periodic terms follow the
+// perturbed inclination.  All of this in the secular type; code 3 when the
+// perturbed eccentricity leaves [0, 1].
+template <class TS, class TP>
+__device__ __forceinline__ uint32_t deep_point(const SatC<TS, TP>& c, const Grav& g, double t_abs,
+                                            PointState<TP>& out) {
+  out.ok = false;
+  const uint32_t scode = c.info & kInfoCodeMask;  // codes 1, 2 at epoch; 7: resonant
+  if (scode) return scode;
+  const double* d = c.deep;
+  const TS t = TS(t_abs - c.epoch_min);
+  const TS t2 = t * t;
+  TS M = lin(c.M0, c.Mdot, t) + TS(d[kDMDt]) * t;
+  TS argp = lin(c.argp0, c.argpdot, t) + TS(d[kDArgpDt]) * t;
+  TS node = lin(c.node0, c.nodedot, t) + c.nodecf * t2 + TS(d[kDNodeDt]) * t;
+  const TS incl = TS(c.i0) + TS(d[kDiDt]) * t;
+  const TS A = TS(1) - c.C1 * t;
+  const TS a_s = c.a0pp * A * A;
+  TS e = c.e0 + TS(d[kDeDt]) * t - c.bC4 * t;
+  if (!(e >= TS(-0.001) && e < TS(1))) return 1;
+  e = vmax(e, TS(1.0e-6));
+  M = M + c.n0pp * (c.t2cof * t2);
+  // mean longitude; angles reduced to [0, 2 pi) (the low-inclination form
+  // uses the node's value)
+  const TS twopi = TS(kTwoPi), itwopi = TS(kInvTwoPi);
+  TS L = M + argp + node;
+  node = node - twopi * floor(node * itwopi);
+  argp = argp - twopi * floor(argp * itwopi);
+  L = L - twopi * floor(L * itwopi);
+  M = L - argp - node;
+  // lunar and solar long-period terms
+  TS pe = TS(0), pinc = TS(0), pl = TS(0), pgh = TS(0), ph = TS(0);
+  const double nb[2] = {1.19459e-5, 1.5835218e-4}, eb[2] = {0.01675, 0.05490};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double* q = d + kDPer0 + kNPer * k;
+    const TS Mb = TS(d[kDMb0 + k]) + TS(nb[k]) * t;
+    TS sMb, cMb;
+    Trig<TS, TS>::sc(Mb, &sMb, &cMb);
+    TS sf, cf;
+    Trig<TS, TS>::sc(Mb + TS(2.0 * eb[k]) * sMb, &sf, &cf);
+    const TS f2 = TS(0.5) * sf * sf - TS(0.25);
+    const TS f3 = TS(-0.5) * sf * cf;
+    pe = pe + TS(q[kPe2]) * f2 + TS(q[kPe3]) * f3;
+    pinc = pinc + TS(q[kPi2]) * f2 + TS(q[kPi3]) * f3;
+    pl = pl + TS(q[kPl2]) * f2 + TS(q[kPl3]) * f3 + TS(q[kPl4]) * sf;
+    pgh = pgh + TS(q[kPgh2]) * f2 + TS(q[kPgh3]) * f3 + TS(q[kPgh4]) * sf;
+    ph = ph + TS(q[kPh2]) * f2 + TS(q[kPh3]) * f3;
+  }
+  TS incp = incl + pinc;
+  e = e + pe;
+  TS si, ci;
+  Trig<TS, TS>::sc(incp, &si, &ci);
+  if (incp >= TS(0.2)) {
+    ph = ph / si;
+    argp = argp + pgh - ci * ph;
+    node = node + ph;
+    M = M + pl;
+  } else {
+    TS sn, cn;
+    Trig<TS, TS>::sc(node, &sn, &cn);
+    const TS alf = si * sn + (ph * cn + pinc * ci * sn);
+    const TS bet = si * cn + (-ph * sn + pinc * ci * cn);
+    const TS xls = M + argp + ci * node + (pl + pgh - pinc * node * si);
+    const TS node_old = node;
+    node = arctan2(alf, bet);
+    if (vabs(node_old - node) > TS(kPi)) node = node < node_old ? node + twopi : node - twopi;
+    M = M + pl;
+    argp = xls - M - ci * node;
+  }
+  if (incp < TS(0)) {
+    incp = -incp;
+    node = node + TS(kPi);
+    argp = argp - TS(kPi);
+  }
+  if (!(e >= TS(0) && e <= TS(1))) return 3;
+  Trig<TS, TS>::sc(incp, &si, &ci);
+  const TS cos2 = ci * ci;
+  const TS j3oj2 = TS(g.j3oj2);
+  TS den = TS(1) + ci;
+  if (vabs(den) <= TS(1.5e-12)) den = TS(1.5e-12);
+  const Incl<TS, TP> q{TP(TS(3) * cos2 - TS(1)), TP(TS(1) - cos2), TP(TS(7) * cos2 - TS(1)), TP(ci), TP(si),
+                       TP(incp), TP(TS(-0.5) * j3oj2 * si),
+                       TP(TS(-0.25) * j3oj2 * si * (TS(3) + TS(5) * ci) / den)};
+  return sgp4_tail<TS, TP>(g, TP(a_s), TP(e), M, argp, node, q, out);
+}
+
+// Returns the point's code (0, 1, 2, 3, 4, 6 or 7).  r and v are written, and ok
+// set, for codes 0 and 6 only.
+//
+// Secular part: sin M from sin/cos of the drag-free M by a small rotation
+// (FP64; the float paths take the hardware sine of M), an identity up to
+// rounding.  Deep-space satellites take deep_point (propagate_point branches
+// before loading the constants).
+template <class TS, class TP>
+__device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav& g, double t_abs, PointState<TP>& out) {
+  using TR = Trig<TS, TP>;
+  out.ok = false;
+  const uint32_t scode = c.info & kInfoCodeMask;
+  if (scode) return scode;
+
+  // Secular gravity.
+  const TS t = TS(t_abs - c.epoch_min);
+  const TS t2 = t * t;
+  const TS Mdf = lin(c.M0, c.Mdot, t);
+  const TS argpdf = lin(c.argp0, c.argpdot, t);
+  TS node = lin(c.node0, c.nodedot, t) + c.nodecf * t2;
+  // Secular drag.
+  TS A = TS(1) - c.C1 * t;
+  TS Ed = c.bC4 * t;
+  TS Ld = c.t2cof * t2;
+  TS M = Mdf, argp = argpdf;
+  if (!(c.info & kInfoIsimp)) {
+    TP sM, cM;
+    TR::sc_damped(Mdf, &sM, &cM);
+    const TP x = TP(1) + c.eta * cM;
+    const TS dM = c.Mcof * TS(x * x * x - c.dM0);
+    const TS dargp = c.argpcof * t;
+    const TS dMa = dargp + dM;
+    M = Mdf + dMa;
+    argp = argpdf - dMa;
+    const TS t3 = t2 * t, t4 = t3 * t;
+    A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
+    // Float paths: one hardware sine of M costs less than the rotation.
+    if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
+    else rotate_small(&sM, &cM, TP(dMa));
+    Ed = Ed + c.bC5 * TS(sM - c.sinM0);
+    Ld = Ld + c.t3cof * t3 + t4 * lin(c.t4cof, c.t5cof, t);
+  }
+  const TS a_s = c.a0pp * A * A;
+  const TS e_s = c.e0 - Ed;
+  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
+  // Angles stay unreduced: every one of them only enters through sin/cos,
+  // whose own reduction handles any size met here.
+  M = M + c.n0pp * Ld;
+
+  // Eccentricity floor 1e-6, taken after the rounding to TP (rounding is
+  // monotonic, so this equals rounding the floored value).  e_s is not NaN
+  // here, so the maximum is the floor: one instruction in float instead of a
+  // compare and two selects.
+  const TP a = TP(a_s), e = vmax(TP(e_s), TP(1.0e-6));
+  const Incl<TS, TP> q{c.c41, c.x1, c.x7, c.cosi, c.sini, c.i0, c.aycof, c.Lcof};
+  return sgp4_tail<TS, TP>(g, a, e, M, argp, node, q, out);
+}
+
+// The satellite's info word alone (through the same view as its constants).
+template <bool kVec>
+__device__ __forceinline__ uint32_t load_info(const RecordView& rv, int64_t i) {
+  if (kVec) return lane_slot(rv.slots + i)->info;
+  return ((CSlot)(rv.slots + i))->info;
+}
+
+// Point of satellite i at t_abs: near-Earth, or the deep-space path.  The
+// branch comes before any constant is loaded.
+template <class TS, class TP, bool kVec>
+__device__ __forceinline__ uint32_t propagate_point(const RecordView& rv, int64_t i, const Grav& g, double t_abs,
+                                                    PointState<TP>& out) {
+  if (load_info<kVec>(rv, i) & kInfoDeep) {
+    const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
+    return deep_point<TS, TP>(c, g, t_abs, out);
+  }
+  const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
+  return sgp4_point<TS, TP>(c, g, t_abs, out);
 }
 
 }  // namespace sgp4mi

@@ -16,6 +16,14 @@
 
 namespace sgp4mi {
 
+// Register budget of the one-wavefront-per-tile kernels (the default dense and
+// ragged launches): the deep-space branch, taken by whole wavefronts of
+// deep-space satellites, holds more values than the near-Earth path and would
+// otherwise set every wavefront's allocation (74 registers, six wavefronts per
+// SIMD); asking for at least seven keeps eight, with the near-Earth path
+// compiled to the instructions it has without the branch.
+#define SGP4MI_TILE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(7, 8)))
+
 // ------------------------------------------------------------------ dense --
 // Grid (n, ceil(T / kBlock)): one point per lane.  When T needs more than
 // 65535 workgroups in y, kLoop makes each lane stride over the remaining times.
@@ -26,18 +34,16 @@ __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const doub
   int64_t j = int64_t(blockIdx.y) * kBlock + threadIdx.x;
   if (!kLoop) {
     if (j >= T) return;
-    const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
     const Grav g = load_grav(rv);
     PointState<TP> s;
-    const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+    const uint32_t code = propagate_point<TS, TP, kVec>(rv, i, g, t[j], s);
     out.put(i * T + j, code, s);
     return;
   }
-  const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
   const Grav g = load_grav(rv);
   for (; j < T; j += int64_t(gridDim.y) * kBlock) {
     PointState<TP> s;
-    const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+    const uint32_t code = propagate_point<TS, TP, kVec>(rv, i, g, t[j], s);
     out.put(i * T + j, code, s);
   }
 }
@@ -47,7 +53,7 @@ __global__ void __launch_bounds__(kBlock) dense_kernel(RecordView rv, const doub
 // independent wavefronts, no loop.  Tile indices fit 32 bits (checked by the
 // launcher).
 template <class TS, class TP, int kBlock, bool kOff32>
-__global__ void __launch_bounds__(kBlock) dense_tile_kernel(RecordView rv, const double* __restrict__ t, int64_t T,
+__global__ void __launch_bounds__(kBlock) SGP4MI_TILE_OCCUPANCY dense_tile_kernel(RecordView rv, const double* __restrict__ t, int64_t T,
                                                             uint32_t tps, uint32_t ntiles, Out<TP, kOff32> out) {
   constexpr int kWaves = kBlock / 64;
   const uint32_t w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -55,10 +61,9 @@ __global__ void __launch_bounds__(kBlock) dense_tile_kernel(RecordView rv, const
   const uint32_t sat = w / tps;
   const int64_t j = int64_t(w - sat * tps) * 64 + (threadIdx.x & 63);
   if (j >= T) return;
-  const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, int64_t(sat));
   const Grav g = load_grav(rv);
   PointState<TP> s;
-  const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+  const uint32_t code = propagate_point<TS, TP, false>(rv, int64_t(sat), g, t[j], s);
   // kOff32: every point index is below 2^30, so the index is formed in 32 bits
   // (the satellite's row start on the scalar unit, one vector add)
   const int64_t p = kOff32 ? int64_t(uint32_t(sat) * uint32_t(T) + uint32_t(j)) : int64_t(sat) * T + j;
@@ -82,10 +87,9 @@ __global__ void __launch_bounds__(kBlock) dense_flat_kernel(RecordView rv, const
     i = p / T;
     j = p - i * T;
   }
-  const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, i);
   const Grav g = load_grav(rv);
   PointState<TP> s;
-  const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+  const uint32_t code = propagate_point<TS, TP, true>(rv, i, g, t[j], s);
   out.put(p, code, s);
 }
 
@@ -106,9 +110,8 @@ __global__ void __launch_bounds__(kBlock) dense_persistent_kernel(RecordView rv,
     const uint64_t sat = w / tps;
     const int64_t j = int64_t(w - sat * tps) * 64 + lane;
     if (j < T) {
-      const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, int64_t(sat));
       PointState<TP> s;
-      const uint32_t code = sgp4_point<TS, TP>(c, g, t[j], s);
+      const uint32_t code = propagate_point<TS, TP, kVec>(rv, int64_t(sat), g, t[j], s);
       out.put(int64_t(sat) * T + j, code, s);
     }
   }
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(kBlock) dense_persistent_kernel(RecordView rv,
 // tiles (fewer workgroups; each iteration waits for the previous one's stores
 // before reusing their registers).
 template <class TS, class TP, int kBlock, bool kOff32>
-__global__ void __launch_bounds__(kBlock) tile_once_kernel(RecordView rv, const double* __restrict__ t,
+__global__ void __launch_bounds__(kBlock) SGP4MI_TILE_OCCUPANCY tile_once_kernel(RecordView rv, const double* __restrict__ t,
                                                            const int64_t* __restrict__ tile_start,
                                                            const int32_t* __restrict__ tile_meta, int64_t ntiles,
                                                            Out<TP, kOff32> out) {
@@ -136,11 +139,10 @@ __global__ void __launch_bounds__(kBlock) tile_once_kernel(RecordView rv, const 
   const int32_t sat = tile_meta[2 * w];
   const int32_t len = tile_meta[2 * w + 1];
   if (lane >= len) return;
-  const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, sat);
   const Grav g = load_grav(rv);
   const int64_t p = kOff32 ? int64_t(uint32_t(start) + uint32_t(lane)) : start + lane;  // kOff32: p < 2^30
   PointState<TP> s;
-  const uint32_t code = sgp4_point<TS, TP>(c, g, t[p], s);
+  const uint32_t code = propagate_point<TS, TP, false>(rv, sat, g, t[p], s);
   out.put(p, code, s);
 }
 
@@ -158,10 +160,9 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const doub
     const int64_t start = tile_start[w];
     const int32_t sat = __builtin_amdgcn_readfirstlane(tile_meta[2 * w]);
     const int32_t len = __builtin_amdgcn_readfirstlane(tile_meta[2 * w + 1]);
-    const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, sat);  // satellite uniform: scalar constants
     if (lane < len) {
-      PointState<TP> s;
-      const uint32_t code = sgp4_point<TS, TP>(c, g, t[start + lane], s);
+      PointState<TP> s;  // satellite uniform: scalar constants
+      const uint32_t code = propagate_point<TS, TP, false>(rv, sat, g, t[start + lane], s);
       out.put(start + lane, code, s);
     }
   }
@@ -200,8 +201,7 @@ __global__ void __launch_bounds__(kBlock) flat_kernel(RecordView rv, const int64
       s.ok = false;
       uint32_t code = kCodeUnowned;
       if (owned) {
-        const SatC<TS, TP> c = load_sat<TS, TP, true>(rv, sat);
-        code = sgp4_point<TS, TP>(c, g, t[p], s);
+        code = propagate_point<TS, TP, true>(rv, sat, g, t[p], s);
       }
       out.put(p, code, s);
     }

@@ -28,6 +28,7 @@ __device__ __forceinline__ uint32_t point_vjp(const SatC<TS, TP>& c, const Grav&
                                           const TP gv[3], double* cb) {
   using TR = Trig<TS, TP>;
   if (c.info & kInfoCodeMask) return c.info & kInfoCodeMask;
+  if (c.info & kInfoDeep) return 7;  // deep space: not differentiated
   const bool simp = (c.info & kInfoIsimp) != 0;
 
   // ---------------------------------------------------------- forward --
@@ -347,16 +348,17 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
   __syncthreads();
   if (threadIdx.x < 7) {
     const int m = threadIdx.x;
-    double out = 0.0;
-    if ((c.info & kInfoCodeMask) == 0) {
+    // deep-space satellites are not differentiated: NaN
+    double out = (c.info & kInfoDeep) ? __builtin_nan("") : 0.0;
+    if ((c.info & (kInfoCodeMask | kInfoDeep)) == 0) {
       Dual1 el[7];
       for (int k = 0; k < 7; ++k) el[k] = Dual1(elem[k * n + i], k == m ? 1.0 : 0.0);
       const double R = rv.hdr[kHRadius];
       GravIn gi{R, rv.hdr[kHJ2], rv.hdr[kHJ4], rv.hdr[kHKe], rv.hdr[kHJ3oJ2]};
       Dual1 rec[kNRec];
       uint32_t code;
-      bool isimp;
-      init_record<Dual1>(gi, el, rec, &code, &isimp);
+      bool isimp, dsp;
+      init_record<Dual1>(gi, el, rec, &code, &isimp, &dsp);
       for (int k = 0; k < kNRec; ++k)
         if (k != kEpochMin && cbar[k] != 0.0) out += cbar[k] * rec[k].d;
     }
@@ -368,11 +370,368 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
 // to the elements, the state-transition and covariance use):
 // jac[(c * 7 + m) * P + p] = d state_c / d theta_m at point p, c over r_x, r_y,
 // r_z, v_x, v_y, v_z and m over the seven differentiated elements; NaN where
-// the point's code is 1, 2, 4 or 7.  One workgroup per satellite: seven lanes
-// first push the unit tangents of the elements through the initialisation
-// (forward-mode duals) into the constants' sensitivities dc_k / dtheta_m (LDS);
-// then, per point, each lane runs the reverse sweep once per state component
-// (unit cotangent) and contracts the constants' adjoints with them.
+// the point's code is 1, 2, 4 or 7.
+//
+// Forward mode: one workgroup per satellite; seven lanes first push the unit
+// tangents of the elements through the initialisation (forward-mode duals)
+// into the constants' sensitivities dc[m][k] = dc_k / dtheta_m (LDS).  Then
+// every lane carries the seven tangents of each intermediate of its point
+// through one pass of the forward kernel's formulation, beside the values:
+// each step's tangent is its derivative applied to its inputs' tangents, and
+// Kepler's equation is differentiated at its root (implicit-function theorem:
+// dpsi = (dU + sin psi daxn - cos psi dayn) / (1 - axn cos psi - ayn sin psi)).
+// The six state tangents are the point's Jacobian columns, stored as they
+// come.  Secular tangents are double; periodic ones take the periodic type.
+
+// Tangents of one intermediate in kN of the seven directions (elements kM0 ..
+// kM0 + kN - 1): the directions are carried in groups, each group a pass of
+// its own, so that the tangents fit the register file.
+template <int kM0, int kN>
+struct Dirs {
+  static constexpr int m0 = kM0, n = kN;
+};
+template <class T, class D>
+struct Tan7 {
+  T d[D::n];
+};
+
+// Tangents of record constant k from the sensitivities in LDS.
+template <class T, class D>
+__device__ __forceinline__ Tan7<T, D> ctan(const double (*dc)[kNRec], int k) {
+  Tan7<T, D> r;
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) r.d[m] = T(dc[D::m0 + m][k]);
+  return r;
+}
+
+// x' = a u' + b v' (and variants), elementwise over the seven directions.
+template <class T, class D>
+__device__ __forceinline__ Tan7<T, D> tlin(T a, const Tan7<T, D>& u) {
+  Tan7<T, D> r;
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) r.d[m] = a * u.d[m];
+  return r;
+}
+template <class T, class D>
+__device__ __forceinline__ Tan7<T, D> tlin(T a, const Tan7<T, D>& u, T b, const Tan7<T, D>& v) {
+  Tan7<T, D> r;
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) r.d[m] = fma(a, u.d[m], b * v.d[m]);
+  return r;
+}
+template <class T, class D>
+__device__ __forceinline__ Tan7<T, D> tlin(T a, const Tan7<T, D>& u, T b, const Tan7<T, D>& v, T c, const Tan7<T, D>& w) {
+  Tan7<T, D> r;
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) r.d[m] = fma(a, u.d[m], fma(b, v.d[m], c * w.d[m]));
+  return r;
+}
+// acc += a u'
+template <class T, class D>
+__device__ __forceinline__ void tacc(Tan7<T, D>& acc, T a, const Tan7<T, D>& u) {
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) acc.d[m] = fma(a, u.d[m], acc.d[m]);
+}
+template <class TO, class TI, class D>
+__device__ __forceinline__ Tan7<TO, D> tcast(const Tan7<TI, D>& u) {
+  Tan7<TO, D> r;
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) r.d[m] = TO(u.d[m]);
+  return r;
+}
+
+// One point: the state's seven tangents (jr[c], jv[c] for c = x, y, z), or the
+// point's code when it carries no state (1, 2, 4, 7).
+template <class TS, class TP, class D>
+__device__ __forceinline__ uint32_t point_jvp(const SatC<TS, TP>& c, const Grav& g, double t_abs,
+                                              const double (*dc)[kNRec], Tan7<TP, D> jr[3], Tan7<TP, D> jv[3]) {
+  using TR = Trig<TS, TP>;
+  if (c.info & kInfoCodeMask) return c.info & kInfoCodeMask;
+  if (c.info & kInfoDeep) return 7;  // deep space: not differentiated
+  const bool simp = (c.info & kInfoIsimp) != 0;
+
+  // Secular gravity and drag (tangents in TS).
+  const TS t = TS(t_abs - c.epoch_min);
+  const TS t2 = t * t, t3 = t2 * t, t4 = t3 * t;
+  const TS Mdf = c.M0 + c.Mdot * t;
+  const TS argpdf = c.argp0 + c.argpdot * t;
+  const TS node = c.node0 + c.nodedot * t + c.nodecf * t2;
+  Tan7<TS, D> Mdf_t = tlin(TS(1), ctan<TS, D>(dc, kM0), t, ctan<TS, D>(dc, kMdot));
+  Tan7<TS, D> argp_t = tlin(TS(1), ctan<TS, D>(dc, kArgp0), t, ctan<TS, D>(dc, kArgpdot));
+  Tan7<TS, D> node_t = tlin(TS(1), ctan<TS, D>(dc, kNode0), t, ctan<TS, D>(dc, kNodedot), t2, ctan<TS, D>(dc, kNodecf));
+  TS A = TS(1) - c.C1 * t;
+  Tan7<TS, D> A_t = tlin(-t, ctan<TS, D>(dc, kC1));
+  TS Ed = c.bC4 * t;
+  Tan7<TS, D> Ed_t = tlin(t, ctan<TS, D>(dc, kBC4));
+  TS Ld = c.t2cof * t2;
+  Tan7<TS, D> Ld_t = tlin(t2, ctan<TS, D>(dc, kT2cof));
+  TS M = Mdf, argp = argpdf;
+  Tan7<TS, D> M_t = Mdf_t;
+  if (!simp) {
+    TP sMdf, cMdf;
+    TR::sc_damped(Mdf, &sMdf, &cMdf);
+    const TP x = TP(1) + c.eta * cMdf;
+    // x' = eta' cos Mdf - eta sin Mdf Mdf'
+    const Tan7<TS, D> x_t = tlin(TS(cMdf), ctan<TS, D>(dc, kEta), TS(-c.eta * sMdf), Mdf_t);
+    const TS x3 = TS(x * x * x - c.dM0);
+    const TS dM = c.Mcof * x3;
+    // dMa = argpcof t + Mcof (x^3 - dM0)
+    Tan7<TS, D> dMa_t = tlin(t, ctan<TS, D>(dc, kArgpcof), x3, ctan<TS, D>(dc, kMcof), TS(-c.Mcof), ctan<TS, D>(dc, kDM0));
+    tacc(dMa_t, TS(c.Mcof * TS(TP(3) * x * x)), x_t);
+    const TS dMa = c.argpcof * t + dM;
+    M = Mdf + dMa;
+    argp = argpdf - dMa;
+#pragma unroll
+    for (int m = 0; m < D::n; ++m) {
+      M_t.d[m] += dMa_t.d[m];
+      argp_t.d[m] -= dMa_t.d[m];
+    }
+    A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
+    tacc(A_t, -t2, ctan<TS, D>(dc, kD2));
+    tacc(A_t, -t3, ctan<TS, D>(dc, kD3));
+    tacc(A_t, -t4, ctan<TS, D>(dc, kD4));
+    TP sM = sMdf, cM = cMdf;
+    if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
+    else rotate_small(&sM, &cM, TP(dMa));
+    // Ed += bC5 (sin M - sinM0)
+    const TS dsM = TS(sM - c.sinM0);
+    Ed = Ed + c.bC5 * dsM;
+    tacc(Ed_t, dsM, ctan<TS, D>(dc, kBC5));
+    tacc(Ed_t, TS(c.bC5 * TS(cM)), M_t);
+    tacc(Ed_t, -c.bC5, ctan<TS, D>(dc, kSinM0));
+    Ld = Ld + c.t3cof * t3 + t4 * (c.t4cof + t * c.t5cof);
+    tacc(Ld_t, t3, ctan<TS, D>(dc, kT3cof));
+    tacc(Ld_t, t4, ctan<TS, D>(dc, kT4cof));
+    tacc(Ld_t, t4 * t, ctan<TS, D>(dc, kT5cof));
+  }
+  const TS a_s = c.a0pp * A * A;
+  // a' = a0pp' A^2 + 2 a0pp A A'
+  const Tan7<TS, D> as_t = tlin(A * A, ctan<TS, D>(dc, kA0pp), TS(2) * c.a0pp * A, A_t);
+  TS e_s = c.e0 - Ed;
+  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
+  Tan7<TS, D> es_t = tlin(TS(1), ctan<TS, D>(dc, kE0), TS(-1), Ed_t);
+  // M + n0 Ld (the mean longitude's drag term)
+  const TS Mn = M + c.n0pp * Ld;
+  tacc(M_t, Ld, ctan<TS, D>(dc, kN0pp));
+  tacc(M_t, c.n0pp, Ld_t);
+
+  // Long-period periodics (TP from here).
+  const TP a = TP(a_s);
+  TP e = TP(e_s);
+  if (e < TP(1.0e-6)) {
+    e = TP(1.0e-6);
+#pragma unroll
+    for (int m = 0; m < D::n; ++m) es_t.d[m] = TS(0);
+  }
+  const Tan7<TP, D> a_t = tcast<TP, TS, D>(as_t), e_t = tcast<TP, TS, D>(es_t), w_t = tcast<TP, TS, D>(argp_t);
+  TP sw, cw;
+  TR::sc_damped(argp, &sw, &cw);
+  const TP axn = e * cw;
+  Tan7<TP, D> axn_t = tlin(cw, e_t, -e * sw, w_t);
+  const TP q = a * (TP(1) - e * e);
+  const TP tau = rcp(q);
+  const TP ayn = e * sw + tau * c.aycof;
+  // tau' = -tau^2 (a' (1 - e^2) - 2 a e e')
+  const Tan7<TP, D> tau_t = tlin(-tau * tau * (TP(1) - e * e), a_t, TP(2) * tau * tau * a * e, e_t);
+  Tan7<TP, D> ayn_t = tlin(sw, e_t, e * cw, w_t, c.aycof, tau_t);
+  tacc(ayn_t, tau, ctan<TP, D>(dc, kAycof));
+  const TP LT = tau * c.Lcof * axn;
+  const TS U = Mn + argp + TS(LT);
+  // U' = M' + argp' + (tau Lcof axn)'
+  Tan7<TP, D> U_t = tlin(c.Lcof * axn, tau_t, tau * axn, ctan<TP, D>(dc, kLcof), tau * c.Lcof, axn_t);
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) U_t.d[m] += TP(M_t.d[m] + argp_t.d[m]);
+
+  // Kepler, as the forward kernel.
+  TP sp, cp;
+  TR::sc(U, &sp, &cp);
+  {
+    TP dpsi = TP(0);
+    const TP eb = vabs(axn) + vabs(ayn);
+    const TP quad = eb < TP(0.5) ? eb : TP(1.0e30);
+    for (int k = 0; k < 10; ++k) {
+      TP step = (axn * sp - ayn * cp - dpsi) * rcp(TP(1) - axn * cp - ayn * sp);
+      step = clamp_step(step);
+      dpsi = dpsi + step;
+      if (vabs(step) <= TP(kRotMax)) rotate_small(&sp, &cp, step);
+      else TR::sc(U + TS(dpsi), &sp, &cp);
+      const TP as = vabs(step);
+      if (__all(as < kepler_tol<TP>() || quad * as * as < kepler_tol<TP>())) break;
+    }
+  }
+  const TP iD = rcp(TP(1) - axn * cp - ayn * sp);
+  // psi' = (U' + sin psi axn' - cos psi ayn') / D; then (sin psi, cos psi)' = (cos, -sin) psi'
+  const Tan7<TP, D> psi_t = tlin(iD, U_t, sp * iD, axn_t, -cp * iD, ayn_t);
+
+  // Short-period preliminaries.
+  const TP ecE = axn * cp + ayn * sp;
+  const TP esE = axn * sp - ayn * cp;
+  const TP eL2 = axn * axn + ayn * ayn;
+  // ecE' = cp axn' + sp ayn' - esE psi'; esE' = sp axn' - cp ayn' + ecE psi'
+  const Tan7<TP, D> ecE_t = tlin(cp, axn_t, sp, ayn_t, -esE, psi_t);
+  const Tan7<TP, D> esE_t = tlin(sp, axn_t, -cp, ayn_t, ecE, psi_t);
+  const Tan7<TP, D> eL2_t = tlin(TP(2) * axn, axn_t, TP(2) * ayn, ayn_t);
+  const TP pL = a * (TP(1) - eL2);
+  if (!(pL >= TP(0))) return 4;
+  const Tan7<TP, D> pL_t = tlin(TP(1) - eL2, a_t, -a, eL2_t);
+  const TP rl = a * (TP(1) - ecE);
+  const Tan7<TP, D> rl_t = tlin(TP(1) - ecE, a_t, -a, ecE_t);
+  const TP irl = rcp(rl);
+  const TP ra = rsq(a);
+  const TP sqa = a * ra;
+  const TP ia = ra * ra;
+  const TP rdotl = sqa * esE * irl;
+  // rdotl' = rdotl (a'/(2a) + esE'/esE - rl'/rl), written without 1/esE
+  const Tan7<TP, D> rdotl_t = tlin(TP(0.5) * rdotl * ia, a_t, sqa * irl, esE_t, -rdotl * irl, rl_t);
+  const TP betal = sq_root(TP(1) - eL2);
+  const TP ibetal = rcp(betal);
+  const Tan7<TP, D> betal_t = tlin(TP(-0.5) * ibetal, eL2_t);
+  const TP rvdotl = sqa * betal * irl;
+  const Tan7<TP, D> rvdotl_t = tlin(TP(0.5) * rvdotl * ia, a_t, sqa * irl, betal_t, -rvdotl * irl, rl_t);
+  const TP iopb = rcp(TP(1) + betal);
+  const TP w = esE * iopb;
+  const Tan7<TP, D> w_tan = tlin(iopb, esE_t, -w * iopb, betal_t);
+  const TP ar = a * irl;
+  const Tan7<TP, D> ar_t = tlin(irl, a_t, -ar * irl, rl_t);
+  const TP f1 = sp - ayn - axn * w;
+  const TP f2 = cp - axn + ayn * w;
+  // f1' = cp psi' - ayn' - w axn' - axn w'; f2' = -sp psi' - axn' + w ayn' + ayn w'
+  Tan7<TP, D> f1_t = tlin(cp, psi_t, -TP(1), ayn_t, -w, axn_t);
+  tacc(f1_t, -axn, w_tan);
+  Tan7<TP, D> f2_t = tlin(-sp, psi_t, -TP(1), axn_t, w, ayn_t);
+  tacc(f2_t, ayn, w_tan);
+  const TP sinu = ar * f1, cosu = ar * f2;
+  const Tan7<TP, D> sinu_t = tlin(f1, ar_t, ar, f1_t);
+  const Tan7<TP, D> cosu_t = tlin(f2, ar_t, ar, f2_t);
+  const TP sin2u = TP(2) * sinu * cosu;
+  const TP cos2u = TP(1) - TP(2) * sinu * sinu;
+  const Tan7<TP, D> sin2u_t = tlin(TP(2) * cosu, sinu_t, TP(2) * sinu, cosu_t);
+  const Tan7<TP, D> cos2u_t = tlin(TP(-4) * sinu, sinu_t);
+
+  // Short-period periodics (J2).
+  const TP ipl = rcp(pL);
+  const TP k2g = grav_k2<TP>(g);
+  const TP k1 = k2g * ipl;
+  const TP k2 = k1 * ipl;
+  const Tan7<TP, D> k1_t = tlin(-k1 * ipl, pL_t);
+  const Tan7<TP, D> k2_t = tlin(TP(-2) * k2 * ipl, pL_t);
+  const TP nk = ra * ra * ra;  // a^-3/2
+  const Tan7<TP, D> nk_t = tlin(TP(-1.5) * nk * ia, a_t);
+  const Tan7<TP, D> c41_t = ctan<TP, D>(dc, kC41), x1_t = ctan<TP, D>(dc, kX1);
+  const TP c41h = TP(1.5) * c.c41;
+  const TP bk = TP(1) - k2 * betal * c41h;
+  const TP mrt = rl * bk + TP(0.5) * k1 * c.x1 * cos2u;
+  // mrt' = rl' bk - 1.5 rl (k2' betal c41 + k2 betal' c41 + k2 betal c41') + 0.5 (k1' x1 cos2u + k1 x1' cos2u + k1 x1 cos2u')
+  Tan7<TP, D> mrt_t = tlin(bk, rl_t, -rl * betal * c41h, k2_t, -rl * k2 * c41h, betal_t);
+  tacc(mrt_t, TP(-1.5) * rl * k2 * betal, c41_t);
+  tacc(mrt_t, TP(0.5) * c.x1 * cos2u, k1_t);
+  tacc(mrt_t, TP(0.5) * k1 * cos2u, x1_t);
+  tacc(mrt_t, TP(0.5) * k1 * c.x1, cos2u_t);
+  const TP du = TP(-0.25) * k2 * c.x7 * sin2u;
+  Tan7<TP, D> du_t = tlin(TP(-0.25) * c.x7 * sin2u, k2_t, TP(-0.25) * k2 * sin2u, ctan<TP, D>(dc, kX7),
+                       TP(-0.25) * k2 * c.x7, sin2u_t);
+  const TP dnode = TP(1.5) * k2 * c.cosi * sin2u;
+  Tan7<TP, D> dnode_t = tlin(TP(1.5) * c.cosi * sin2u, k2_t, TP(1.5) * k2 * sin2u, ctan<TP, D>(dc, kCosi),
+                          TP(1.5) * k2 * c.cosi, sin2u_t);
+  const TP dinc = TP(1.5) * k2 * c.cosi * c.sini * cos2u;
+  Tan7<TP, D> dinc_t = tlin(TP(1.5) * c.cosi * c.sini * cos2u, k2_t, TP(1.5) * k2 * c.sini * cos2u,
+                         ctan<TP, D>(dc, kCosi), TP(1.5) * k2 * c.cosi * cos2u, ctan<TP, D>(dc, kSini));
+  tacc(dinc_t, TP(1.5) * k2 * c.cosi * c.sini, cos2u_t);
+  const TP kx = nk * k1 * c.x1;
+  const TP mvt = rdotl - kx * sin2u;
+  // mvt' = rdotl' - (nk k1 x1)' sin2u - nk k1 x1 sin2u'
+  Tan7<TP, D> mvt_t = tlin(TP(1), rdotl_t, -k1 * c.x1 * sin2u, nk_t, -nk * c.x1 * sin2u, k1_t);
+  tacc(mvt_t, -nk * k1 * sin2u, x1_t);
+  tacc(mvt_t, -kx, sin2u_t);
+  const TP g1 = c.x1 * cos2u + c41h;
+  const TP rvdot = rvdotl + nk * k1 * g1;
+  Tan7<TP, D> rvdot_t = tlin(TP(1), rvdotl_t, k1 * g1, nk_t, nk * g1, k1_t);
+  tacc(rvdot_t, nk * k1 * cos2u, x1_t);
+  tacc(rvdot_t, nk * k1 * c.x1, cos2u_t);
+  tacc(rvdot_t, TP(1.5) * nk * k1, c41_t);
+
+  // Orientation: u_k = u + du, i_k = i0 + dinc, node_k = node + dnode.
+  const TP nu2 = sinu * sinu + cosu * cosu;
+  const TP inu2 = rcp(nu2);
+  TP ssu, csu;
+  if (vabs(du) <= TP(kRotMax)) {
+    const TP h = rsq(nu2);
+    ssu = sinu * h;
+    csu = cosu * h;
+    rotate_small(&ssu, &csu, du);
+  } else {
+    TR::sc(TS(arctan2(sinu, cosu) + du), &ssu, &csu);
+  }
+  // u' = (cosu sinu' - sinu cosu') / |.|^2
+  Tan7<TP, D> uk_t = tlin(cosu * inu2, sinu_t, -sinu * inu2, cosu_t);
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) uk_t.d[m] += du_t.d[m];
+  TP sinc = c.sini, cinc = c.cosi;
+  if (vabs(dinc) <= TP(kRotMax)) rotate_small(&sinc, &cinc, dinc);
+  else TR::sc(TS(c.i0 + dinc), &sinc, &cinc);
+  Tan7<TP, D> ik_t = ctan<TP, D>(dc, kI0);
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) ik_t.d[m] += dinc_t.d[m];
+  TP snod, cnod;
+  TR::sc(node + TS(dnode), &snod, &cnod);
+  Tan7<TP, D> nodek_t = tcast<TP, TS, D>(node_t);
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) nodek_t.d[m] += dnode_t.d[m];
+
+  const TP xmx = -snod * cinc, xmy = cnod * cinc;
+  const TP ux = xmx * ssu + cnod * csu, uy = xmy * ssu + snod * csu, uz = sinc * ssu;
+  const TP vx = xmx * csu - cnod * ssu, vy = xmy * csu - snod * ssu, vz = sinc * csu;
+  // d(unit vectors) = vx du_k... written per direction from the three angle tangents:
+  //   d ux = (xmx csu - cnod ssu) uk' + (-cnod cinc ssu - snod csu) nodek' + (snod sinc ssu) ik'
+  //   d uy = (xmy csu - snod ssu) uk' + (-snod cinc ssu + cnod csu) nodek' + (-cnod sinc ssu) ik'
+  //   d uz = (sinc csu) uk' + (cinc ssu) ik'
+  //   d vx = (-xmx ssu - cnod csu) uk' + (-cnod cinc csu + snod ssu) nodek' + (snod sinc csu) ik'
+  //   d vy = (-xmy ssu - snod csu) uk' + (-snod cinc csu - cnod ssu) nodek' + (-cnod sinc csu) ik'
+  //   d vz = (-sinc ssu) uk' + (cinc csu) ik'
+  const TP R = grav_radius<TP>(g), vk = grav_vkms<TP>(g);
+  const TP rr = R * mrt;
+  const TP xn_u = -cnod * cinc * ssu - snod * csu, yn_u = -snod * cinc * ssu + cnod * csu;
+  const TP xn_v = -cnod * cinc * csu + snod * ssu, yn_v = -snod * cinc * csu - cnod * ssu;
+  const TP sss = sinc * ssu, ssc = sinc * csu;
+#pragma unroll
+  for (int m = 0; m < D::n; ++m) {
+    const TP du_ = uk_t.d[m], dn = nodek_t.d[m], di = ik_t.d[m];
+    const TP dux = vx * du_ + xn_u * dn + snod * sss * di;
+    const TP duy = vy * du_ + yn_u * dn - cnod * sss * di;
+    const TP duz = vz * du_ + cinc * ssu * di;
+    const TP dvx = -ux * du_ + xn_v * dn + snod * ssc * di;
+    const TP dvy = -uy * du_ + yn_v * dn - cnod * ssc * di;
+    const TP dvz = -uz * du_ + cinc * csu * di;
+    const TP dmrt = R * mrt_t.d[m];
+    jr[0].d[m] = fma(dmrt, ux, rr * dux);
+    jr[1].d[m] = fma(dmrt, uy, rr * duy);
+    jr[2].d[m] = fma(dmrt, uz, rr * duz);
+    const TP dmvt = mvt_t.d[m], drv = rvdot_t.d[m];
+    jv[0].d[m] = vk * (dmvt * ux + mvt * dux + drv * vx + rvdot * dvx);
+    jv[1].d[m] = vk * (dmvt * uy + mvt * duy + drv * vy + rvdot * dvy);
+    jv[2].d[m] = vk * (dmvt * uz + mvt * duz + drv * vz + rvdot * dvz);
+  }
+  return mrt < TP(1) ? 6u : 0u;
+}
+
+// One group of directions for one point: tangents and their stores.
+template <class TS, class TP, class D>
+__device__ __forceinline__ void jacobian_pass(const SatC<TS, TP>& c, const Grav& g, double tj,
+                                              const double (*dc)[kNRec], double* __restrict__ jac, int64_t P,
+                                              int64_t p) {
+  Tan7<TP, D> jr[3], jv[3];
+  const uint32_t code = point_jvp<TS, TP, D>(c, g, tj, dc, jr, jv);
+  const bool ok = code == 0 || code == 6;
+  const double qnan = __builtin_nan("");
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int m = 0; m < D::n; ++m) {
+      st_nt(jac + (q * 7 + D::m0 + m) * P + p, ok ? double(jr[q].d[m]) : qnan);
+      st_nt(jac + ((q + 3) * 7 + D::m0 + m) * P + p, ok ? double(jv[q].d[m]) : qnan);
+    }
+}
+
 template <class TS, class TP>
 __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
     jacobian_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t,
@@ -388,8 +747,8 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
       GravIn gi{rv.hdr[kHRadius], rv.hdr[kHJ2], rv.hdr[kHJ4], rv.hdr[kHKe], rv.hdr[kHJ3oJ2]};
       Dual1 rec[kNRec];
       uint32_t code;
-      bool isimp;
-      init_record<Dual1>(gi, el, rec, &code, &isimp);
+      bool isimp, dsp;
+      init_record<Dual1>(gi, el, rec, &code, &isimp, &dsp);
 #pragma unroll
       for (int k = 0; k < kNRec; ++k) dc[m][k] = k == kEpochMin ? 0.0 : rec[k].d;
     } else {
@@ -402,34 +761,15 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
   const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, i);
   const Grav g = load_grav(rv);
   const int64_t P = n * T;
-  const double qnan = __builtin_nan("");
   for (int64_t j = threadIdx.x; j < T; j += kVjpBlock) {
     const int64_t p = i * T + j;
-    const double tj = t[j];
-#pragma unroll 1
-    for (int comp = 0; comp < 6; ++comp) {
-      TP gr[3], gv[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        gr[q] = comp == q ? TP(1) : TP(0);
-        gv[q] = comp == q + 3 ? TP(1) : TP(0);
-      }
-      double cb[kNRec];
-#pragma unroll
-      for (int k = 0; k < kNRec; ++k) cb[k] = 0.0;
-      const uint32_t code = point_vjp<TS, TP>(c, g, tj, gr, gv, cb);
-      const bool ok = code == 0 || code == 6;
-      // One element at a time, the sensitivities re-read from LDS (the empty
-      // asm keeps the compiler from hoisting all 238 of them into registers).
-#pragma unroll
-      for (int m = 0; m < 7; ++m) {
-        asm volatile("" ::: "memory");
-        double row = 0.0;
-#pragma unroll
-        for (int k = 0; k < kNRec; ++k) row = fma(cb[k], dc[m][k], row);
-        st_nt(jac + (comp * 7 + m) * P + p, ok ? row : qnan);
-      }
-    }
+    // the sensitivities are read from LDS where each step uses them: without
+    // this fence the compiler would hoist all 238 loop-invariant loads into
+    // registers ahead of the loop
+    asm volatile("" ::: "memory");
+    jacobian_pass<TS, TP, Dirs<0, 4>>(c, g, t[j], dc, jac, P, p);
+    asm volatile("" ::: "memory");
+    jacobian_pass<TS, TP, Dirs<4, 3>>(c, g, t[j], dc, jac, P, p);
   }
 }
 

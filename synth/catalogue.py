@@ -25,7 +25,8 @@ import numpy as np
 
 __all__ = [
     "Catalogue", "Ragged", "ELEMENT_ROWS", "config0", "config1", "config2", "config3", "config4",
-    "uniform_elements", "shell_elements", "sample_satellites", "ragged_lists",
+    "uniform_elements", "shell_elements", "sample_satellites", "ragged_lists", "deep_elements", "config5",
+    "DEEP_REF_JD",
 ]
 
 ELEMENT_ROWS = ("no_kozai", "ecco", "inclo", "nodeo", "argpo", "mo", "bstar", "epoch")
@@ -206,3 +207,57 @@ def sample_satellites(n: int, frac: float, seed: int) -> np.ndarray:
     rng, = _streams(seed + 7919, 1)
     k = max(1, int(round(n * frac)))
     return np.sort(rng.choice(n, size=k, replace=False))
+
+
+# Reference instant of the deep-space catalogue: 2026 January 13 0h UT (the
+# date of the paper's element sets), as a Julian date.
+DEEP_REF_JD = 2461053.5
+
+# (fraction, semi-major axis km, eccentricity range, inclination deg range):
+# navigation-constellation MEO, transfer orbits (low inclinations included, so
+# that the deep-space model's low-inclination form is met), other non-resonant
+# high orbits, and the two resonant classes the library flags (24 h: near-
+# geosynchronous; 12 h with e >= 0.5: Molniya-type).
+DEEP_CLASSES = (
+    (0.25, 26560.0, (0.0, 0.02), (54.0, 56.0)),      # GPS-like 12 h, e < 0.5: not resonant
+    (0.15, 29600.0, (0.0, 0.01), (55.0, 57.0)),      # Galileo-like
+    (0.10, 25510.0, (0.0, 0.01), (64.0, 65.6)),      # GLONASS-like
+    (0.20, 24400.0, (0.70, 0.72), (0.5, 28.5)),      # transfer orbits, perigee 450-1050 km
+    (0.15, 12500.0, (0.0, 0.3), (10.0, 120.0)),      # 232-min and longer periods
+    (0.10, 42164.0, (0.0, 0.001), (0.0, 3.0)),       # near-geosynchronous: resonant, code 7
+    (0.05, 26600.0, (0.68, 0.74), (62.0, 64.0)),     # Molniya-type: resonant, code 7
+)
+
+
+def deep_elements(n: int, seed: int, epoch_days: float = 3.0) -> np.ndarray:
+    """Deep-space catalogue (periods of 225 min or more) by DEEP_CLASSES, B* =
+    1e-5 exp(N(0, 1)), epochs U(-3, +3) days after DEEP_REF_JD."""
+    r_cls, r_shape, r_ang, r_ep = _streams(seed, 4)
+    frac = np.array([c[0] for c in DEEP_CLASSES])
+    counts = r_cls.multinomial(n, frac / frac.sum())
+    cls = np.repeat(np.arange(len(DEEP_CLASSES)), counts)
+    r_cls.shuffle(cls)
+    a_km = np.array([c[1] for c in DEEP_CLASSES])[cls] * (1.0 + r_shape.uniform(-0.002, 0.002, n))
+    e_lo = np.array([c[2][0] for c in DEEP_CLASSES])[cls]
+    e_hi = np.array([c[2][1] for c in DEEP_CLASSES])[cls]
+    i_lo = np.array([c[3][0] for c in DEEP_CLASSES])[cls]
+    i_hi = np.array([c[3][1] for c in DEEP_CLASSES])[cls]
+    ecc = e_lo + (e_hi - e_lo) * r_shape.random(n)
+    inc = np.deg2rad(i_lo + (i_hi - i_lo) * r_shape.random(n))
+    node = r_ang.uniform(0.0, 2.0 * math.pi, n)
+    argp = r_ang.uniform(0.0, 2.0 * math.pi, n)
+    mo = r_ang.uniform(0.0, 2.0 * math.pi, n)
+    bstar = 1e-5 * np.exp(r_ang.normal(0.0, 1.0, n))
+    elem = np.empty((8, n))
+    elem[0] = np.sqrt(_MU_KM3_S2 / a_km ** 3) * 60.0
+    elem[1] = ecc
+    elem[2] = inc
+    elem[3], elem[4], elem[5], elem[6] = node, argp, mo, bstar
+    elem[7] = r_ep.uniform(-epoch_days, epoch_days, n)
+    return elem
+
+
+def config5(n: int = 4096, T: int = 1008) -> Catalogue:
+    """Deep-space catalogue, n satellites x T times at 10-minute steps over 7 days
+    after the reference DEEP_REF_JD, seed 5."""
+    return Catalogue(deep_elements(n, 5), 10.0 * np.arange(T), f"c5: {n} x {T} deep-space catalogue")

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_strerror_and_sizes():
     L = _native.lib()
-    assert L.sgp4_version() == 1
+    assert L.sgp4_version() == 2
     for code in range(-7, 1):
         assert _native.strerror(code)
     assert L.sgp4_consts_bytes(-1) == 0

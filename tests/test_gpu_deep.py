@@ -1,0 +1,203 @@
+"""GPU parity of the deep-space path (periods of 225 min or more: the Sun's
+and the Moon's secular and long-period terms; resonant classes flagged) against
+the CPU oracle, element by element.
+
+Bars: FP64 |dr| <= 1e-6 km and |dv| <= 1e-9 km/s with codes bit-exact (the
+hot path's FP64 bar); FP32-mixed within 10 m and 1e-2 m/s times (|r| / 7,000
+km) / (1 - e0) and codes exact: the float part's rounding grows with the
+radius (one float ulp is 0.5 m at LEO and 3.9 m at 42,000 km) and, near
+perigee, with 1 / (1 - e cos E) <= 1 / (1 - e) through Kepler's equation and
+the short-period terms (measured: 14 m at GPS radius, 23 m and 18 mm/s at the
+7,400 km perigee of e = 0.70 transfer orbits); every dense launch mapping, the ragged
+mappings and the elements-to-states call agree with the two-stage dense path.
+The catalogue is the seeded deep-space stand-in (navigation MEO, transfer
+orbits including inclinations below 0.2 rad, other high orbits, and the two
+resonant classes), epochs within +-3 days of 2026 January 13.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_27830_amd as sg
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+NTHREADS = max(1, min(16, os.cpu_count() or 1))
+REF = synth.DEEP_REF_JD
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(*ts):
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in ts]
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def oracle_dense(elem, t, ref=REF):
+    with oracle.reference_jd(ref):
+        return oracle.propagate(elem, t, nthreads=NTHREADS)
+
+
+def check_fp64(r, v, err, ro, vo, eo):
+    r = r.reshape(3, -1); v = v.reshape(3, -1); err = err.reshape(-1)
+    ro = ro.reshape(3, -1); vo = vo.reshape(3, -1); eo = eo.reshape(-1)
+    assert np.array_equal(err, eo), f"codes differ at {np.flatnonzero(err != eo)[:10]}"
+    ok = (eo == 0) | (eo == 6)
+    assert np.all(np.isnan(r[:, ~ok])) and np.all(np.isnan(v[:, ~ok]))
+    dr = np.max(np.abs(r[:, ok] - ro[:, ok]))
+    dv = np.max(np.abs(v[:, ok] - vo[:, ok]))
+    say(f"  fp64 max |dr| {dr:.2e} km, |dv| {dv:.2e} km/s over {int(ok.sum())} points")
+    assert dr <= 1e-6 and dv <= 1e-9, (dr, dv)
+
+
+def check_mixed(r, v, err, ro, vo, eo, e0, tol_r=0.010, tol_v=1e-5):
+    """e0: the epoch eccentricity of each point's satellite (broadcastable to err)."""
+    e0 = np.broadcast_to(np.asarray(e0, dtype=np.float64), err.shape).reshape(-1)
+    r = r.reshape(3, -1).astype(np.float64); v = v.reshape(3, -1).astype(np.float64); err = err.reshape(-1)
+    ro = ro.reshape(3, -1); vo = vo.reshape(3, -1); eo = eo.reshape(-1)
+    assert np.array_equal(err, eo), f"codes differ at {np.flatnonzero(err != eo)[:10]}"
+    ok = (eo == 0) | (eo == 6)
+    scale = np.maximum(1.0, np.linalg.norm(ro[:, ok], axis=0) / 7000.0) / (1.0 - e0[ok])
+    dr = np.linalg.norm(r[:, ok] - ro[:, ok], axis=0) / scale
+    dv = np.linalg.norm(v[:, ok] - vo[:, ok], axis=0) / scale
+    say(f"  mixed max |dr| {dr.max() * 1e3:.2f} m, |dv| {dv.max() * 1e6:.3f} mm/s per (7,000 km of radius) / (1 - e0)")
+    assert dr.max() <= tol_r and dv.max() <= tol_v, (dr.max(), dv.max())
+
+
+def test_deep_catalogue_dense_fp64_and_mixed():
+    cat = synth.config5()
+    say(f"[gpu] deep-space catalogue {cat.n} x {cat.T} dense")
+    ro, vo, eo = oracle_dense(cat.elem, cat.t)
+    kinds = {int(k): int((eo == k).sum()) for k in np.unique(eo)}
+    say(f"  oracle codes {kinds}")
+    assert 0 in kinds and 7 in kinds
+    rec = sg.init(dev(cat.elem), ref_jd=REF)
+    flags, = host(rec.flags)
+    assert np.all(flags & 1)                        # every set is deep space
+    assert np.array_equal((flags & 8) != 0, np.all(eo == 7, axis=1))
+    dt = dev(cat.t)
+    r, v, err = host(*sg.propagate(rec, dt, "fp64"))
+    check_fp64(r, v, err, ro, vo, eo)
+    r, v, err = host(*sg.propagate(rec, dt, "mixed"))
+    check_mixed(r, v, err, ro, vo, eo, cat.elem[1][:, None])
+    r, v, err = host(*sg.propagate(rec, dt, "fp32"))
+    assert np.array_equal(err, eo)
+
+
+def test_deep_every_dense_launch_mapping_agrees():
+    cat = synth.config5(300, 90)
+    ro, vo, eo = oracle_dense(cat.elem, cat.t)
+    rec = sg.init(dev(cat.elem), ref_jd=REF)
+    dt = dev(cat.t)
+    SCALAR, PERSIST, TILES, FLAT = 0x10000, 0x20000, 0x40000, 0x80000
+    for cfg in (256, 512 | SCALAR, 256 | PERSIST | (4 << 20), 256 | SCALAR | TILES, 512 | SCALAR | TILES, 256 | FLAT):
+        say(f"[gpu] deep launch config {cfg:#x}")
+        r, v, err = host(*sg.propagate(rec, dt, "fp64", block=cfg))
+        check_fp64(r, v, err, ro, vo, eo)
+        r, v, err = host(*sg.propagate(rec, dt, "mixed", block=cfg))
+        check_mixed(r, v, err, ro, vo, eo, cat.elem[1][:, None])
+
+
+def test_deep_ragged_lists_plan_and_no_plan():
+    cat = synth.config5(500, 1)
+    rng = np.random.default_rng(55)
+    lens = rng.integers(0, 300, cat.n)
+    offsets = np.zeros(cat.n + 1, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    t = np.concatenate([np.sort(rng.uniform(-2000.0, 12000.0, L)) for L in lens])
+    with oracle.reference_jd(REF):
+        ro, vo, eo = oracle.propagate_ragged(cat.elem, offsets, t, nthreads=NTHREADS)
+    rec = sg.init(dev(cat.elem), ref_jd=REF)
+    doff, dt = dev(offsets), dev(t)
+    for prec in ("fp64", "mixed"):
+        say(f"[gpu] deep ragged {prec} without a plan, and with plans")
+        outs = [host(*sg.propagate_ragged(rec, doff, dt, prec))]
+        for mode in (0, 1):
+            plan = sg.RaggedPlan(rec, doff, dt, prec, config=(mode, 256, 0))
+            outs.append(host(*plan.launch()))
+            plan.close()
+        e0 = np.repeat(cat.elem[1], lens)
+        for r, v, err in outs:
+            if prec == "fp64":
+                check_fp64(r, v, err, ro, vo, eo)
+            else:
+                check_mixed(r, v, err, ro, vo, eo, e0)
+
+
+@pytest.mark.parametrize("T", [1, 7, 32, 200])
+def test_deep_elements_to_states(T):
+    cat = synth.config5(700, T)
+    ro, vo, eo = oracle_dense(cat.elem, cat.t)
+    e, dt = dev(cat.elem), dev(cat.t)
+    for prec in ("fp64", "mixed"):
+        say(f"[gpu] deep elements to states T={T} {prec}")
+        e0 = cat.elem[1][:, None]
+        r, v, err = host(*sg.propagate_elements(e, dt, prec, ref_jd=REF))
+        if prec == "fp64":
+            check_fp64(r, v, err, ro, vo, eo)
+        else:
+            check_mixed(r, v, err, ro, vo, eo, e0)
+        if T > 32:
+            ws = torch.empty(sg.consts_bytes(cat.n), dtype=torch.uint8, device=DEV)
+            r2, v2, err2 = host(*sg.propagate_elements(e, dt, prec, workspace=ws, ref_jd=REF))
+            if prec == "fp64":
+                check_fp64(r2, v2, err2, ro, vo, eo)
+            else:
+                check_mixed(r2, v2, err2, ro, vo, eo, e0)
+
+
+def test_reference_instant_is_absolute_time():
+    """The same absolute instants from two references: the epoch row and the
+    times shifted together give the same states; the oracle under the second
+    reference agrees."""
+    cat = synth.config5(200, 50)
+    rec1 = sg.init(dev(cat.elem), ref_jd=REF)
+    r1, v1, e1 = host(*sg.propagate(rec1, dev(cat.t), "fp64"))
+    el2 = cat.elem.copy()
+    el2[7] += 400.0
+    rec2 = sg.init(dev(el2), ref_jd=(REF - 400.0, 0.0))
+    r2, v2, e2 = host(*sg.propagate(rec2, dev(cat.t + 400.0 * 1440.0), "fp64"))
+    assert np.array_equal(e1, e2)
+    ok = (e1 == 0) | (e1 == 6)
+    assert np.max(np.abs(r1[:, ok] - r2[:, ok])) <= 1e-6
+    ro, vo, eo = oracle_dense(el2, cat.t + 400.0 * 1440.0, ref=REF - 400.0)
+    check_fp64(r2, v2, e2, ro, vo, eo)
+    # a different absolute epoch moves the lunar-solar terms: states change
+    rec3 = sg.init(dev(cat.elem), ref_jd=REF + 300.0)
+    r3, _, _ = host(*sg.propagate(rec3, dev(cat.t), "fp64"))
+    assert np.nanmax(np.abs(r3 - r1)) > 0.01
+
+
+def test_deep_code_3_near_parabolic():
+    rng = np.random.default_rng(3)
+    n = 400
+    el = np.empty((8, n))
+    el[0] = rng.uniform(0.003, 0.02, n)
+    el[1] = rng.uniform(0.998, 0.99999, n)
+    el[2] = rng.uniform(0.3, 2.8, n)
+    el[3:6] = rng.uniform(0, 2 * math.pi, (3, n))
+    el[6] = 0.0
+    el[7] = 0.0
+    t = np.linspace(0.0, 20 * 1440.0, 21)
+    ro, vo, eo = oracle_dense(el, t)
+    assert (eo == 3).sum() > 50
+    rec = sg.init(dev(el), ref_jd=REF)
+    r, v, err = host(*sg.propagate(rec, dev(t), "fp64"))
+    # codes decided by the lunar-solar eccentricity change (3) and by the
+    # resonance flags (7) are exact; these sets lie outside the model's domain
+    # (near-parabolic), so only codes are compared
+    same = (eo == 3) | (eo == 7)
+    assert np.array_equal(err[same], eo[same])
+    assert np.all(np.isnan(r[:, err == 3]))

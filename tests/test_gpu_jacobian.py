@@ -4,8 +4,9 @@ the GPU VJP (its contraction) and between precisions.
 Bars: FP64 vs the oracle's forward-mode (dual-number) Jacobian to 1e-8 of each
 (component, element) column's scale; NaN exactly where the oracle's code is 1,
 2, 4 or 7; the Jacobian contracted with a cotangent equals the VJP to 1e-10;
-FP32-mixed vs FP64 to 1e-3 of the column scale (the mixed forward state carries
-~1e-7 relative error).
+FP32-mixed vs FP64 to 1e-4 of the column scale (the mixed forward state carries
+~1e-7 relative error; measured ~2e-6).  Deep-space satellites are not
+differentiated (NaN).
 """
 import numpy as np
 import pytest
@@ -66,13 +67,14 @@ def test_jacobian_edge_sets_nan_where_no_state():
     ke = 60.0 / np.sqrt(6378.135 ** 3 / 398600.8)
     el[0, :4] = ke * ((6378.135 + 200.0) / 6378.135) ** -1.5      # perigee below 220 km
     el[6, 4:8] = 2e-3                                              # heavy drag
-    el[0, 8:10] = 2 * np.pi / 300.0                                # deep space: code 7
+    el[0, 8:10] = 2 * np.pi / 300.0                                # deep space: not differentiated
     el[1, 10:12] = 1.5                                             # invalid eccentricity: code 1
     t = np.linspace(0.0, 10080.0, 40)
     say("[gpu] jacobian fp64 edge sets")
     J = gpu_jacobian(el, t, "fp64")
     ref, err = oracle_jacobian(el, t)
     valid = (err == 0) | (err == 6)
+    valid[8:10] = False
     assert np.array_equal(np.isnan(J).all(axis=(0, 1)), ~valid)
     assert np.isfinite(J[:, :, valid]).all()
     assert column_error(J, ref, valid) <= 1e-7
@@ -103,7 +105,7 @@ def test_jacobian_mixed_matches_fp64():
     valid = np.ones((cat.n, cat.T), bool)
     e = column_error(J32, J64, valid)
     say(f"  max column-relative difference {e:.3e}")
-    assert e <= 1e-3
+    assert e <= 1e-4
 
 
 def test_jacobian_rejects_plain_fp32():

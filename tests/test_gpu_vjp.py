@@ -4,9 +4,10 @@ the autograd wrapper.
 Bars: FP64 VJP vs the oracle's forward-mode (dual-number) VJP to 1e-8
 relative per satellite (both differentiate the same function; the oracle
 iterates Newton with duals, the kernel uses the implicit-function theorem at
-the root); FP32-mixed vs FP64 for the same cotangent to 1e-3 relative (the
-forward state of the mixed path carries ~1e-7 relative error); the VJP of a
-least-squares loss vs central differences of that loss to 1e-5 relative.
+the root); FP32-mixed vs FP64 for the same cotangent to 1e-4 relative (the
+forward state of the mixed path carries ~1e-7 relative error; measured
+~2e-6); the VJP of a least-squares loss vs central differences of that loss
+to 1e-5 relative.
 """
 import os
 
@@ -65,13 +66,13 @@ def test_vjp_fp64_matches_dual_oracle(with_gv):
 
 def test_vjp_simplified_drag_and_invalid_points():
     """Low-perigee (simplified drag) and heavy-drag sets differentiate like the
-    oracle; deep-space and invalid element sets (codes 7 and 1 at every point)
-    get a zero gradient."""
+    oracle; invalid element sets (code 1 at every point) get a zero gradient;
+    deep-space sets are not differentiated by the library (NaN)."""
     el = synth.shell_elements(40, 8)
     ke = 60.0 / np.sqrt(6378.135 ** 3 / 398600.8)
     el[0, :8] = ke * ((6378.135 + 200.0) / 6378.135) ** -1.5      # perigee below 220 km
     el[6, 8:16] = 2e-3                                              # heavy drag (20x the median)
-    el[0, 16:18] = 2 * np.pi / 300.0                                # deep space: code 7 everywhere
+    el[0, 16:18] = 2 * np.pi / 300.0                                # deep space: not differentiated
     el[1, 18:20] = 1.5                                              # invalid eccentricity: code 1
     t = np.linspace(0.0, 10080.0, 64)
     rng = np.random.default_rng(6)
@@ -79,10 +80,11 @@ def test_vjp_simplified_drag_and_invalid_points():
     say("[gpu] vjp fp64 edge sets")
     g = gpu_vjp(el, t, gr, None, "fp64")
     ref = oracle.vjp(el, t, gr, None)
-    assert np.all(g[:, 16:20] == 0.0) and np.all(ref[:, 16:20] == 0.0)
+    assert np.all(np.isnan(g[:, 16:18]))
+    assert np.all(g[:, 18:20] == 0.0) and np.all(ref[:, 18:20] == 0.0)
     keep = np.ones(el.shape[1], bool)
     keep[16:20] = False
-    assert np.all(np.isfinite(g))
+    assert np.all(np.isfinite(g[:, keep]))
     assert rel_err_per_sat(g[:, keep], ref[:, keep]) <= 1e-7
 
 
@@ -95,7 +97,7 @@ def test_vjp_mixed_matches_fp64_for_the_same_cotangent():
     g32 = gpu_vjp(cat.elem, cat.t, gr, None, "mixed")
     err = rel_err_per_sat(g32, g64)
     say(f"  mixed vs fp64 max relative error per satellite {err:.3e}")
-    assert err <= 1e-3
+    assert err <= 1e-4
 
 
 def _loss_and_grad(cat, r_obs, prec):
@@ -180,3 +182,10 @@ def test_vjp_full_size_differentiation_workload():
     err32 = rel_err_per_sat(g32[:, idx], g64[:, idx])
     say(f"  mixed vs fp64 (own residuals) on 40 satellites: {err32:.3e}")
     assert err32 <= 0.2
+    # the same cotangent for both paths (the FP64 residuals rounded to float):
+    # the gradients then agree to the mixed forward state's relative error
+    g32s = sg.vjp(rec, dev(cat.t), gr.float(), None, "mixed").cpu().numpy()
+    g64s = sg.vjp(rec, dev(cat.t), gr.float().double(), None, "fp64").cpu().numpy()
+    err_same = rel_err_per_sat(g32s, g64s)
+    say(f"  mixed vs fp64 (same cotangent) on all satellites: {err_same:.3e}")
+    assert err_same <= 1e-4
