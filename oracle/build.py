@@ -1,7 +1,11 @@
 """Build the SGP4 oracle shared library (test infrastructure only).
 
 Plain g++: optimised, but with no fast-math and no fused multiply-add
-contraction, so every operation rounds as written in the source.
+contraction, so every operation rounds as written in the source.  The
+default build is portable (it travels with the repository); native=True adds
+-march=native for timing the oracle on the machine that builds it (the
+rounding is the same: without fast-math the compiler may vectorise but not
+reassociate or contract).
 """
 import os
 import subprocess
@@ -12,14 +16,20 @@ SRC = os.path.join(HERE, "sgp4_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle_sgp4.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-pthread", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC]
+def flags(native: bool = False):
+    f = ["-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread", "-Wall",
+         "-Wextra"]
+    return f + (["-march=native"] if native else [])
+
+
+def build(verbose: bool = False, native: bool = False, out: str = None) -> str:
+    lib = out or LIB
+    cmd = ["g++"] + flags(native) + ["-o", lib + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
