@@ -198,6 +198,23 @@ int sgp4_screen_ex(const void* r, int precision, const uint8_t* err, int64_t n, 
                    int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
                    int mode, void* stream);
 
+/* As sgp4_screen (automatic path), for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): no ws argument, and no device or host allocation in the call.
+ * The workspace is a fixed array of SGP4_SCREEN_NOALLOC_BYTES (64 MiB) in the
+ * library's code object, one per GPU, held from the library's first use on
+ * that GPU until the process ends; its device address is looked up on the
+ * first call on each device.  n and T must satisfy
+ * sgp4_screen_workspace_bytes(n, T) <= SGP4_SCREEN_NOALLOC_BYTES (about
+ * 5.2 million points, e.g. 9,341 satellites x 500 times), else SGP4_E_SIZE.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other host threads) race and give wrong events;
+ * calls ordered on one stream are safe (each initialises what it reads).
+ * Other arguments and the events found are as for sgp4_screen. */
+#define SGP4_SCREEN_NOALLOC_BYTES (64u << 20)
+int sgp4_screen_noalloc(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
+                        int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* stream);
+
 /* ---------------------------------------------------------------- ingestion --
  * Element-set text to the elements sgp4_init takes, on the host.  Formats:
  *   SGP4_TEXT_TLE       two-line element sets, optionally with a name line

@@ -249,6 +249,44 @@ def screen(r: torch.Tensor, dist_km: float, err: Optional[torch.Tensor] = None, 
     return pairs[:m], dist[:m], total
 
 
+def screen_noalloc(r: torch.Tensor, dist_km: float, err: Optional[torch.Tensor] = None, pairs=None, dist=None,
+                   count=None):
+    """As screen (automatic path) through sgp4_screen_noalloc: the workspace is
+    the library's fixed per-GPU array, so the call allocates nothing when the
+    caller passes the outputs pairs (int32 [capacity, 3]), dist (float64
+    [capacity]) and count (int64 [1]); sgp4_screen_workspace_bytes(n, T) must
+    not exceed NOALLOC_SCREEN_BYTES.  Returns (pairs[:m], dist[:m], total)."""
+    if r.dim() != 3 or r.shape[0] != 3:
+        raise ValueError("r must have shape [3, n, T]")
+    if r.dtype not in (torch.float64, torch.float32):
+        raise TypeError("r must be float64 or float32")
+    _need(r, r.dtype, "r")
+    n, T = int(r.shape[1]), int(r.shape[2])
+    if err is not None:
+        _need(err, torch.uint8, "err", r.device)
+    if pairs is None:
+        pairs = torch.empty((1 << 20, 3), dtype=torch.int32, device=r.device)
+    if dist is None:
+        dist = torch.empty(pairs.shape[0], dtype=torch.float64, device=r.device)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=r.device)
+    _need(pairs, torch.int32, "pairs", r.device)
+    _need(dist, torch.float64, "dist", r.device)
+    _need(count, torch.int64, "count", r.device)
+    cap = int(min(pairs.shape[0], dist.shape[0]))
+    prec = _native.SGP4_FP64 if r.dtype == torch.float64 else _native.SGP4_FP32
+    with torch.cuda.device(r.device):
+        _native.check(_native.lib().sgp4_screen_noalloc(_ptr(r), prec, _ptr(err), n, T, float(dist_km), cap,
+                                                        _ptr(pairs), _ptr(dist), _ptr(count), _stream(r.device)),
+                      "sgp4_screen_noalloc")
+    total = int(count.item())
+    m = min(total, cap)
+    return pairs[:m], dist[:m], total
+
+
+NOALLOC_SCREEN_BYTES = 64 << 20
+
+
 def parse_text(text, fmt="tle", ref_jd=None, threads=0):
     """Element-set text (str or bytes; fmt "tle", "omm_kvn", "omm_csv" or
     "omm_json") to host numpy arrays: elem float64 [8, n] (rows as for init,

@@ -38,6 +38,7 @@ SIGNATURES = [
                            _vp]),
     ("sgp4_screen_ex", _int, [_vp, _int, _vp, _i64, _i64, ctypes.c_double, _i64, _vp, _vp, _vp, _vp,
                               ctypes.c_size_t, _int, _vp]),
+    ("sgp4_screen_noalloc", _int, [_vp, _int, _vp, _i64, _i64, ctypes.c_double, _i64, _vp, _vp, _vp, _vp]),
     ("sgp4_text_count", _int, [ctypes.c_char_p, ctypes.c_size_t, _int, ctypes.POINTER(_i64)]),
     ("sgp4_text_parse", _int, [ctypes.c_char_p, ctypes.c_size_t, _int, _i64, _dp, _vp, _vp, _vp, _int]),
     ("sgp4_propagate_ragged", _int, [_vp, _i64, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp, _vp]),

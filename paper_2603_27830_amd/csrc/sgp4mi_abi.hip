@@ -34,6 +34,9 @@ hipError_t launch_screen(const void* r, bool fp64, const uint8_t* err, int64_t n
 int screen_max_n();
 size_t screen_ws_bytes(int64_t n, int64_t T);
 bool screen_global_fits(int64_t n, int64_t T);
+size_t screen_static_bytes();
+hipError_t launch_screen_static(const void* r, bool fp64, const uint8_t* err, int64_t n, int64_t T, double D,
+                                int64_t cap, int32_t* pairs, double* dist, unsigned long long* count, hipStream_t s);
 hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
@@ -331,6 +334,21 @@ int sgp4_screen(const void* r, int precision, const uint8_t* err, int64_t n, int
                 int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* ws, size_t ws_bytes,
                 void* stream) {
   return sgp4_screen_ex(r, precision, err, n, T, dist_km, capacity, pairs, dist, count, ws, ws_bytes, 0, stream);
+}
+
+int sgp4_screen_noalloc(const void* r, int precision, const uint8_t* err, int64_t n, int64_t T, double dist_km,
+                        int64_t capacity, int32_t* pairs, double* dist, int64_t* count, void* stream) {
+  if (n < 0 || T < 0 || T > 0x7ffffff0LL || mul_overflows(n, T) || mul_overflows(n * T, 16) || capacity < 0)
+    return SGP4_E_SIZE;
+  if (!screen_global_fits(n, T)) return SGP4_E_SIZE;
+  if (n >= 2 && T > 0 && screen_ws_bytes(n, T) > screen_static_bytes()) return SGP4_E_SIZE;
+  static_assert(SGP4_SCREEN_NOALLOC_BYTES == 64u << 20, "header limit and scratch size differ");
+  if (precision < 0 || precision > 2) return SGP4_E_PRECISION;
+  if (!(dist_km > 0.0) || !std::isfinite(dist_km)) return SGP4_E_ARG;
+  if (!count || (capacity > 0 && (!pairs || !dist)) || (n > 0 && T > 0 && !r)) return SGP4_E_ARG;
+  return hip_status(launch_screen_static(r, precision == SGP4_FP64, err, n, T, dist_km, capacity, pairs, dist,
+                                         reinterpret_cast<unsigned long long*>(count),
+                                         static_cast<hipStream_t>(stream)));
 }
 
 int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets, const double* t, int64_t nnz,

@@ -31,6 +31,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace sgp4mi {
 
@@ -476,6 +477,54 @@ hipError_t launch_screen(const void* r, bool fp64, const uint8_t* err, int64_t n
     hipLaunchKernelGGL(screen_kernel<float>, dim3(grid), dim3(kScreenBlock), lds, s, static_cast<const float*>(r), w,
                        int32_t(n), T, D, D * D, cap, pairs, dist, count);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------- no-alloc --
+// Workspace for callers that cannot allocate device memory: a fixed array in
+// the code object, one copy per GPU the library runs on, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory); it passes the device address
+// taken with hipGetSymbolAddress once per device, with that device current.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+size_t screen_static_bytes() { return kStaticScratchBytes; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// This GPU's copy of the scratch array (the current device's), looked up on
+// the first call on that device.
+static hipError_t scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// launch_screen (mode 0) with the workspace in this GPU's scratch array; the
+// caller checks that screen_ws_bytes(n, T) fits kStaticScratchBytes.  Both
+// paths initialise every workspace byte they read (the packing pass writes
+// all n T entries; the device-memory path clears its header and counts with a
+// kernel), so nothing of an earlier call's contents is used.
+hipError_t launch_screen_static(const void* r, bool fp64, const uint8_t* err, int64_t n, int64_t T, double D,
+                                int64_t cap, int32_t* pairs, double* dist, unsigned long long* count, hipStream_t s) {
+  void* ws = nullptr;
+  if (hipError_t e = scratch_of_current_device(&ws)) return e;
+  return launch_screen(r, fp64, err, n, T, D, cap, pairs, dist, count, ws, 0, s);
 }
 
 }  // namespace sgp4mi
