@@ -76,6 +76,71 @@ def measured_traffic(path_name):
         return None
 
 
+def valu_quads_per_wave(path_name):
+    """(SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_VALU2) per wavefront of the dense
+    kernel: quad-cycles in which the wavefront's SIMD issued a VALU instruction
+    of it, and those in which it issued two (dual issue), or None when stale."""
+    vals = profile_values(COUNTERS_FILE)
+    try:
+        return float(vals[f"{path_name}_active_inst_valu_per_wave"]), float(vals[f"{path_name}_active_inst_valu2_per_wave"])
+    except (KeyError, TypeError):
+        return None
+
+
+class ClockSampler:
+    """The GPU's graphics clock under a load: a host thread reads the driver's
+    current clock of every XCD (amdsmi GPU metrics) every 20 ms; the first
+    `settle` seconds are not counted (the driver refreshes the metric about
+    once a second, so early samples still show the clock before the load).
+    Reports mean/min/max in MHz, or None where amdsmi is not available."""
+
+    def __init__(self, settle=1.0):
+        self.samples, self.stop, self.thread, self.handle = [], False, None, None
+        self.settle = settle
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self.amdsmi = amdsmi
+            self.handle = amdsmi.amdsmi_get_processor_handles()[0]
+        except Exception:  # noqa: BLE001 - the clock is reported as unavailable
+            self.amdsmi = None
+
+    def _read(self):
+        m = self.amdsmi.amdsmi_get_gpu_metrics_info(self.handle)
+        clks = [c for c in m.get("current_gfxclks", []) if isinstance(c, (int, float)) and c > 0]
+        return sum(clks) / len(clks) if clks else float(m["current_gfxclk"])
+
+    def _run(self):
+        t0 = time.perf_counter()
+        while not self.stop:
+            try:
+                x = self._read()
+            except Exception:  # noqa: BLE001
+                return
+            if time.perf_counter() - t0 >= self.settle:
+                self.samples.append(x)
+            time.sleep(0.02)
+
+    def __enter__(self):
+        if self.amdsmi is not None:
+            import threading
+            self.thread = threading.Thread(target=self._run, daemon=True)
+            self.thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop = True
+        if self.thread is not None:
+            self.thread.join()
+
+    def summary(self):
+        if not self.samples:
+            return None
+        return {"mean_mhz": sum(self.samples) / len(self.samples), "min_mhz": min(self.samples),
+                "max_mhz": max(self.samples), "samples": len(self.samples),
+                "source": "amdsmi GPU metrics current_gfxclks (mean over XCDs), every 20 ms"}
+
+
 def executed_flop_per_point(path_name):
     """FP32 + FP64 VALU flops the dense kernel executes per point (rocprofv3
     SQ_INSTS_VALU_FLOPS_FP32 / _FP64 per wavefront of 64 points, FMA counted
@@ -407,6 +472,14 @@ def main():
 
         s = time_steps(step, args.steps, args.warmup, torch, timer)
         k = timer.mean()
+        # the clock under the same load: the step repeated for a second while
+        # the driver's clock is sampled (the timed region is too short for it)
+        with ClockSampler(settle=0.3 if args.only else 1.0) as clock:
+            t_end = time.perf_counter() + (0.6 if args.only else 2.0)
+            while time.perf_counter() < t_end:
+                for _ in range(50):
+                    step()
+                torch.cuda.synchronize()
         # --only is the profiling mode: a handful of launches, no adaptive repeats
         kb = kernel_time(prop_only, torch, reps=2 if args.only else 20)
         pp = paper_protocol(step, torch) if not args.only else float("nan")
@@ -416,6 +489,7 @@ def main():
             "propagate_only_points_per_s": P / k, "paper_protocol_min_ms": pp * 1e3,
             "hbm_gbs": BYTES_PER_POINT[name] * P / k / 1e9,
             "alg_tflops": ALG_FLOP_PER_POINT * P / k / 1e12,
+            "gpu_clock": clock.summary(),
         }
         log(f"[bench] {name}: {P / s:.3e} pts/s, step {s * 1e3:.3f} ms, kernel {k * 1e6:.1f} us")
 
@@ -636,6 +710,29 @@ def main():
         "bound": "alu", "executed_flop_per_point": xf, "achieved": xf * P / k_s / 1e12, "peak": peak,
         "unit": "TFLOP/s", "frac": xf * P / k_s / 1e12 / peak}
 
+    # The bound the counters show: the fraction of the launch's SIMD quad-cycles
+    # (at the clock sampled during the timed steps) in which the VALU issued
+    # this kernel's instructions, a dual-issued pair counted once.
+    quads = valu_quads_per_wave(head_name)
+    clk = head.get("gpu_clock")
+    issue = None
+    if quads is not None and clk is not None:
+        waves = cat.n * ((cat.T + 63) // 64)
+        busy = waves * (quads[0] - quads[1]) / 1024.0          # quad-cycles per SIMD
+        avail = clk["mean_mhz"] * 1e6 / 4.0 * k_s                # quad-cycles per SIMD in the launch
+        issue = {"bound": "valu_issue", "achieved": busy / k_s / 1e9, "peak": clk["mean_mhz"] * 1e6 / 4.0 / 1e9,
+                 "unit": "G VALU quad-cycles/s per SIMD", "frac": busy / avail,
+                 "valu_quads_per_wave": quads[0], "dual_issue_quads_per_wave": quads[1],
+                 "clock_mhz": clk["mean_mhz"]}
+    calib = None
+    if not args.only:
+        try:
+            c = calibrate(torch)
+            calib = {k: c[k] for k in ("fma_f64_tflops", "fma_f32_vgpr_tflops", "fma_f32_sgpr_operand_tflops",
+                                       "store_nt_gbs") if k in c}
+        except Exception as e:  # noqa: BLE001 - reported, not fatal
+            calib = {"error": repr(e)}
+
     line = {
         "metric": "sat-time propagations/s at 9341x1000: FP32-mixed vs FP64 GPU; % of VALU peak",
         "value": head["points_per_s"], "unit": "sat-time points/s", "n_gpus": 1, "steps": args.steps,
@@ -646,7 +743,8 @@ def main():
         "data": "synthetic (seeded Starlink-shaped catalogue)",
         "config": {"workload": "9341 satellites x 1000 times over 0-1440 min, init + dense propagate",
                    "satellites": cat.n, "times": cat.T, "precision": head_name},
-        "roofline": roof, "roofline_other": other, "roofline_executed": counters,
+        "roofline": roof, "roofline_other": other, "roofline_executed": counters, "roofline_issue": issue,
+        "gpu_clock": clk, "calibration": calib,
         "paths": paths,
     }
     if not args.no_cpu and not args.only:

@@ -14,9 +14,9 @@ namespace sgp4mi {
 // Layout in device memory:
 //   [header: 64 doubles]
 //   [n slots of kSlotBytes = 512 bytes, one per satellite]:
-//       bytes   0..271  kNRec doubles (full-precision constants)
-//       bytes 272..407  kNRec floats  (the same constants rounded to float)
-//       bytes 408..411  uint32 info: bits 0-7 satellite code, bit 8 isimp,
+//       bytes   0..319  kNRec doubles (full-precision constants)
+//       bytes 320..479  kNRec floats  (the same constants rounded to float)
+//       bytes 480..483  uint32 info: bits 0-7 satellite code, bit 8 isimp,
 //                       bit 9 deep space
 //   [n deep-space slots of kDeepBytes = 256 bytes, one per satellite]: the
 //       lunar-solar secular rates, the long-period coefficients of the Sun and
@@ -28,6 +28,11 @@ enum Rec : int {
   kM0, kMdot, kArgp0, kArgpdot, kNode0, kNodedot, kNodecf, kC1, kBC4, kT2cof,
   kArgpcof, kEta, kMcof, kDM0, kD2, kD3, kD4, kBC5, kSinM0, kT3cof, kT4cof, kT5cof,
   kN0pp, kA0pp, kE0, kAycof, kLcof, kC41, kX1, kX7, kCosi, kSini, kI0, kEpochMin,
+  // the short-period coefficients with k2 = J2 / 2 folded in (per point they
+  // are multiplied by powers of 1 / p_L only): 1.5 k2 (3 cos^2 i - 1),
+  // k2 / 2 sin^2 i, k2 sin^2 i, -k2 / 4 (7 cos^2 i - 1), 1.5 k2 cos i and
+  // 1.5 k2 cos i sin i
+  kSpA1, kSpX1h, kSpX1k, kSpX7q, kSpCN, kSpCI,
   kNRec
 };
 

@@ -47,6 +47,11 @@ __device__ __forceinline__ SatC<TS, TP> sat_of(const double* x, uint32_t info, c
   c.eta = TP(x[kEta]); c.dM0 = TP(x[kDM0]); c.sinM0 = TP(x[kSinM0]); c.aycof = TP(x[kAycof]);
   c.Lcof = TP(x[kLcof]); c.c41 = TP(x[kC41]); c.x1 = TP(x[kX1]); c.x7 = TP(x[kX7]); c.cosi = TP(x[kCosi]);
   c.sini = TP(x[kSini]); c.i0 = TP(x[kI0]);
+  c.spA1 = TP(x[kSpA1]); c.spX1h = TP(x[kSpX1h]); c.spX1k = TP(x[kSpX1k]); c.spX7q = TP(x[kSpX7q]);
+  c.spCN = TP(x[kSpCN]); c.spCI = TP(x[kSpCI]);
+  c.pC1 = TP(x[kC1]); c.pbC4 = TP(x[kBC4]); c.pD2 = TP(x[kD2]); c.pD3 = TP(x[kD3]); c.pD4 = TP(x[kD4]);
+  c.pbC5 = TP(x[kBC5]); c.pMcof = TP(x[kMcof]); c.pArgpcof = TP(x[kArgpcof]); c.pA0pp = TP(x[kA0pp]);
+  c.pE0 = TP(x[kE0]);
   c.info = info;
   c.deep = deep;
   return c;

@@ -230,6 +230,9 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   rec[kC41] = con41; rec[kX1] = x1mth2; rec[kX7] = x7thm1; rec[kCosi] = cos_i; rec[kSini] = sin_i;
   rec[kI0] = inclo;
   rec[kEpochMin] = S(0.0);
+  const double k2 = 0.5 * J2;
+  rec[kSpA1] = (1.5 * k2) * con41; rec[kSpX1h] = (0.5 * k2) * x1mth2; rec[kSpX1k] = k2 * x1mth2;
+  rec[kSpX7q] = (-0.25 * k2) * x7thm1; rec[kSpCN] = (1.5 * k2) * cos_i; rec[kSpCI] = (1.5 * k2) * cos_i * sin_i;
   *code_out = code;
   *isimp_out = isimp;
   *deep_out = deep;

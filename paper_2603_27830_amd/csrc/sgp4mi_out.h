@@ -1,6 +1,14 @@
 // Output writer shared by the propagation kernels: component-major SoA
-// arrays r[c * P + p], v[c * P + p] and the code array err[p], written with
-// non-temporal stores; codes 1, 2, 4 and 7 write NaN states.
+// arrays r[c * P + p], v[c * P + p] and the code array err[p]; codes 1, 2, 4
+// and 7 write NaN states.
+//
+// Store policy (measured on MI355X): the state components go out as
+// non-temporal stores (a wavefront writes 256 or 512 contiguous bytes per
+// component); the one-byte codes as ordinary stores, which the L2 merges into
+// whole lines before they reach HBM (a wavefront's 64 code bytes rarely fill
+// an aligned line, and written past the cache each such piece is a partial
+// write): 9,341 x 1,000 mixed 64 -> 60 us, FP32 67 -> 63 us, the 1M ragged
+// catalogue mixed 5.09 -> 4.74 ms, FP64 unchanged.
 #pragma once
 
 #include "sgp4mi_point.h"
@@ -46,7 +54,7 @@ struct Out {
       // the code array seen in the global address space: the store then takes
       // its base from scalar registers and the 32-bit offset as it is
       typedef __attribute__((address_space(1))) uint8_t* GByte;
-      __builtin_nontemporal_store(uint8_t(code), (GByte)err + uint32_t(p));
+      *((GByte)err + uint32_t(p)) = uint8_t(code);
     } else {
       st_nt(r + p, x0);
       st_nt(r + P + p, x1);
@@ -54,7 +62,7 @@ struct Out {
       st_nt(v + p, y0);
       st_nt(v + P + p, y1);
       st_nt(v + 2 * P + p, y2);
-      st_nt(err + p, uint8_t(code));
+      err[p] = uint8_t(code);
     }
   }
 };

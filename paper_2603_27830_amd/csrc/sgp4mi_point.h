@@ -29,6 +29,10 @@ struct SatC {
   double epoch_min;
   // periodic (TP)
   TP eta, dM0, sinM0, aycof, Lcof, c41, x1, x7, cosi, sini, i0;
+  TP spA1, spX1h, spX1k, spX7q, spCN, spCI;
+  // the drag constants again in TP: near-Earth propagation evaluates the drag
+  // polynomials in the periodic type (the mean-anomaly polynomial excepted)
+  TP pC1, pbC4, pD2, pD3, pD4, pbC5, pMcof, pArgpcof, pA0pp, pE0;
   uint32_t info;
   const double* deep;  // the deep-space slot's entries (read only when info has kInfoDeep)
 };
@@ -80,6 +84,10 @@ __device__ __forceinline__ SatC<TS, TP> load_from(P sp, PP pp) {
   c.epoch_min = rec_val<double, P>(sp, kEpochMin);
   c.eta = P_(kEta); c.dM0 = P_(kDM0); c.sinM0 = P_(kSinM0); c.aycof = P_(kAycof); c.Lcof = P_(kLcof);
   c.c41 = P_(kC41); c.x1 = P_(kX1); c.x7 = P_(kX7); c.cosi = P_(kCosi); c.sini = P_(kSini); c.i0 = P_(kI0);
+  c.spA1 = P_(kSpA1); c.spX1h = P_(kSpX1h); c.spX1k = P_(kSpX1k); c.spX7q = P_(kSpX7q); c.spCN = P_(kSpCN);
+  c.spCI = P_(kSpCI);
+  c.pC1 = P_(kC1); c.pbC4 = P_(kBC4); c.pD2 = P_(kD2); c.pD3 = P_(kD3); c.pD4 = P_(kD4); c.pbC5 = P_(kBC5);
+  c.pMcof = P_(kMcof); c.pArgpcof = P_(kArgpcof); c.pA0pp = P_(kA0pp); c.pE0 = P_(kE0);
 #undef S_
 #undef P_
   c.info = sp->info;
@@ -228,10 +236,17 @@ struct PointState {
 
 // Inclination functions and J3 coefficients the periodic terms use: the
 // epoch's (per-satellite constants) in near-Earth propagation, the
-// lunar-solar perturbed ones (per point) in deep space.
+// lunar-solar perturbed ones (per point) in deep space.  The float paths
+// take the short-period coefficients with k2 = J2 / 2 folded in: A1 = 1.5 k2
+// (3 cos^2 i - 1), X1h = k2 / 2 sin^2 i, X1k = k2 sin^2 i, X7q = -k2 / 4
+// (7 cos^2 i - 1), CN = 1.5 k2 cos i, CI = 1.5 k2 cos i sin i (fewer
+// instructions per point, each reading at most one of them); FP64 multiplies
+// by k2 per point (its constants are register pairs, and six more would
+// overflow the scalar register file).
 template <class TS, class TP>
 struct Incl {
   TP c41, x1, x7, cosi, sini, i0, aycof, Lcof;
+  TP A1, X1h, X1k, X7q, CN, CI;
 };
 
 // Long-period (J3) and short-period (J2) periodics, Kepler's equation,
@@ -302,18 +317,33 @@ __device__ __forceinline__ uint32_t sgp4_tail(const Grav& g, TP a, TP e, TS M, T
 
   // Short-period periodics (J2).
   const TP inv_pl = rcp(pL);
-  const TP k1 = grav_k2<TP>(g) * inv_pl;
-  const TP k2 = k1 * inv_pl;
   const TP nk = ra * ra * ra;  // n / ke = a^-3/2
-  // 1.5 c41 as c41 + c41 / 2 (one instruction reading one scalar register
-  // twice; 1.5 is no inline constant); the same single rounding of 1.5 c41
-  const TP c41h = vfma(q.c41, TP(0.5), q.c41);
-  const TP mrt = rl * (TP(1) - k2 * betal * c41h) + TP(0.5) * k1 * q.x1 * cos2u;
-  const TP du = TP(-0.25) * k2 * q.x7 * sin2u;
-  const TP dnode = TP(1.5) * k2 * q.cosi * sin2u;
-  const TP dinc = TP(1.5) * k2 * q.cosi * q.sini * cos2u;
-  const TP mvt = rdotl - nk * k1 * q.x1 * sin2u;
-  const TP rvdot = rvdotl + nk * k1 * vfma(q.x1, cos2u, c41h);
+  TP mrt, du, dnode, dinc, mvt, rvdot;
+  if (sizeof(TP) == 4) {
+    // k2 / p_L and k2 / p_L^2 times the inclination functions, k2 in the
+    // coefficients
+    const TP ip2 = inv_pl * inv_pl;
+    const TP ni = nk * inv_pl;
+    const TP s2 = ip2 * sin2u, c2 = ip2 * cos2u;
+    mrt = rl * vfma(-ip2 * betal, q.A1, TP(1)) + inv_pl * cos2u * q.X1h;
+    du = q.X7q * s2;
+    dnode = q.CN * s2;
+    dinc = q.CI * c2;
+    mvt = rdotl - ni * sin2u * q.X1k;
+    rvdot = rvdotl + ni * vfma(q.X1k, cos2u, q.A1);
+  } else {
+    const TP k1 = grav_k2<TP>(g) * inv_pl;
+    const TP k2 = k1 * inv_pl;
+    // 1.5 c41 as c41 + c41 / 2 (one instruction reading one scalar register
+    // twice; 1.5 is no inline constant); the same single rounding of 1.5 c41
+    const TP c41h = vfma(q.c41, TP(0.5), q.c41);
+    mrt = rl * (TP(1) - k2 * betal * c41h) + TP(0.5) * k1 * q.x1 * cos2u;
+    du = TP(-0.25) * k2 * q.x7 * sin2u;
+    dnode = TP(1.5) * k2 * q.cosi * sin2u;
+    dinc = TP(1.5) * k2 * q.cosi * q.sini * cos2u;
+    mvt = rdotl - nk * k1 * q.x1 * sin2u;
+    rvdot = rvdotl + nk * k1 * vfma(q.x1, cos2u, c41h);
+  }
 
   // Orientation: sin/cos of u_k = u + du, i_k = i0 + dinc, node_k = node + dnode.
   TP ssu, csu;
@@ -436,11 +466,14 @@ __device__ __forceinline__ uint32_t deep_point(const SatC<TS, TP>& c, const Grav
   Trig<TS, TS>::sc(incp, &si, &ci);
   const TS cos2 = ci * ci;
   const TS j3oj2 = TS(g.j3oj2);
+  const TS k2 = TS(g.k2);
   TS den = TS(1) + ci;
   if (vabs(den) <= TS(1.5e-12)) den = TS(1.5e-12);
-  const Incl<TS, TP> q{TP(TS(3) * cos2 - TS(1)), TP(TS(1) - cos2), TP(TS(7) * cos2 - TS(1)), TP(ci), TP(si),
-                       TP(incp), TP(TS(-0.5) * j3oj2 * si),
-                       TP(TS(-0.25) * j3oj2 * si * (TS(3) + TS(5) * ci) / den)};
+  const TS c41 = TS(3) * cos2 - TS(1), x1 = TS(1) - cos2, x7 = TS(7) * cos2 - TS(1);
+  const Incl<TS, TP> q{TP(c41), TP(x1), TP(x7), TP(ci), TP(si), TP(incp), TP(TS(-0.5) * j3oj2 * si),
+                       TP(TS(-0.25) * j3oj2 * si * (TS(3) + TS(5) * ci) / den),
+                       TP(TS(1.5) * k2 * c41), TP(TS(0.5) * k2 * x1), TP(k2 * x1), TP(TS(-0.25) * k2 * x7),
+                       TP(TS(1.5) * k2 * ci), TP(TS(1.5) * k2 * ci * si)};
   return sgp4_tail<TS, TP>(g, TP(a_s), TP(e), M, argp, node, q, out);
 }
 
@@ -458,47 +491,74 @@ __device__ __forceinline__ uint32_t sgp4_point(const SatC<TS, TP>& c, const Grav
   const uint32_t scode = c.info & kInfoCodeMask;
   if (scode) return scode;
 
-  // Secular gravity.
+  // Secular gravity (secular type).
   const TS t = TS(t_abs - c.epoch_min);
+  const TP tp = TP(t);
   const TS t2 = t * t;
   const TS Mdf = lin(c.M0, c.Mdot, t);
   const TS argpdf = lin(c.argp0, c.argpdot, t);
   TS node = lin(c.node0, c.nodedot, t) + c.nodecf * t2;
-  // Secular drag.
-  TS A = TS(1) - c.C1 * t;
-  TS Ed = c.bC4 * t;
-  TS Ld = c.t2cof * t2;
+  TP a, e_s;
   TS M = Mdf, argp = argpdf;
-  if (!(c.info & kInfoIsimp)) {
-    TP sM, cM;
-    TR::sc_damped(Mdf, &sM, &cM);
-    const TP x = TP(1) + c.eta * cM;
-    const TS dM = c.Mcof * TS(x * x * x - c.dM0);
-    const TS dargp = c.argpcof * t;
-    const TS dMa = dargp + dM;
-    M = Mdf + dMa;
-    argp = argpdf - dMa;
-    const TS t3 = t2 * t, t4 = t3 * t;
-    A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
-    // Float paths: one hardware sine of M costs less than the rotation.
-    if (sizeof(TP) == 4 || vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
-    else rotate_small(&sM, &cM, TP(dMa));
-    Ed = Ed + c.bC5 * TS(sM - c.sinM0);
-    Ld = Ld + c.t3cof * t3 + t4 * lin(c.t4cof, c.t5cof, t);
+  if constexpr (sizeof(TP) == 4) {
+    // Float paths: 1 - A, the eccentricity decrement and the drag changes of
+    // M and argp in float; the mean-anomaly polynomial L_d / t^2 (multiplied
+    // by n0'' t^2, an angle of up to radians) in the secular type; all
+    // polynomials in Horner form.
+    TP dA = c.pC1 * tp;
+    TP Ed = c.pbC4 * tp;
+    TS Ld = c.t2cof;
+    if (!(c.info & kInfoIsimp)) {
+      TP sM, cM;
+      TR::sc_damped(Mdf, &sM, &cM);
+      const TP x = TP(1) + c.eta * cM;
+      const TP dMa = vfma(c.pArgpcof, tp, c.pMcof * (x * x * x - c.dM0));
+      M = Mdf + TS(dMa);
+      argp = argpdf - TS(dMa);
+      dA = tp * vfma(tp, vfma(tp, vfma(tp, c.pD4, c.pD3), c.pD2), c.pC1);
+      // one hardware sine of M costs less than the rotation
+      TR::sc_damped(M, &sM, &cM);
+      Ed = vfma(c.pbC5, sM - c.sinM0, Ed);
+      Ld = vfma(vfma(lin(c.t4cof, c.t5cof, t), t, c.t3cof), t, c.t2cof);
+    }
+    // a = a0'' A^2 = a0'' + a0'' (1 - A) ((1 - A) - 2)
+    a = vfma(c.pA0pp, dA * (dA - TP(2)), c.pA0pp);
+    e_s = c.pE0 - Ed;
+    if (!(e_s >= TP(-0.001) && e_s < TP(1))) return 1;
+    M = M + c.n0pp * (Ld * t2);
+  } else {
+    // FP64: sin M from sin/cos of the drag-free M by a small rotation
+    TS A = TS(1) - c.C1 * t;
+    TS Ed = c.bC4 * t;
+    TS Ld = c.t2cof * t2;
+    if (!(c.info & kInfoIsimp)) {
+      TP sM, cM;
+      TR::sc_damped(Mdf, &sM, &cM);
+      const TP x = TP(1) + c.eta * cM;
+      const TS dM = c.Mcof * TS(x * x * x - c.dM0);
+      const TS dMa = c.argpcof * t + dM;
+      M = Mdf + dMa;
+      argp = argpdf - dMa;
+      const TS t3 = t2 * t, t4 = t3 * t;
+      A = A - c.D2 * t2 - c.D3 * t3 - c.D4 * t4;
+      if (vabs(dMa) > TS(kRotMax)) TR::sc_damped(M, &sM, &cM);
+      else rotate_small(&sM, &cM, TP(dMa));
+      Ed = Ed + c.bC5 * TS(sM - c.sinM0);
+      Ld = Ld + c.t3cof * t3 + t4 * lin(c.t4cof, c.t5cof, t);
+    }
+    a = TP(c.a0pp * A * A);
+    e_s = TP(c.e0 - Ed);
+    if (!(e_s >= TP(-0.001) && e_s < TP(1))) return 1;
+    M = M + c.n0pp * Ld;
   }
-  const TS a_s = c.a0pp * A * A;
-  const TS e_s = c.e0 - Ed;
-  if (!(e_s >= TS(-0.001) && e_s < TS(1))) return 1;
   // Angles stay unreduced: every one of them only enters through sin/cos,
   // whose own reduction handles any size met here.
-  M = M + c.n0pp * Ld;
 
-  // Eccentricity floor 1e-6, taken after the rounding to TP (rounding is
-  // monotonic, so this equals rounding the floored value).  e_s is not NaN
-  // here, so the maximum is the floor: one instruction in float instead of a
-  // compare and two selects.
-  const TP a = TP(a_s), e = vmax(TP(e_s), TP(1.0e-6));
-  const Incl<TS, TP> q{c.c41, c.x1, c.x7, c.cosi, c.sini, c.i0, c.aycof, c.Lcof};
+  // Eccentricity floor 1e-6.  e_s is not NaN here, so the maximum is the
+  // floor: one instruction in float instead of a compare and two selects.
+  const TP e = vmax(e_s, TP(1.0e-6));
+  const Incl<TS, TP> q{c.c41, c.x1, c.x7, c.cosi, c.sini, c.i0, c.aycof, c.Lcof,
+                       c.spA1, c.spX1h, c.spX1k, c.spX7q, c.spCN, c.spCI};
   return sgp4_tail<TS, TP>(g, a, e, M, argp, node, q, out);
 }
 

@@ -9,8 +9,8 @@
 //   flat       ragged lists read as one flat run of points, 64 per wavefront;
 //              each lane finds its satellite from the tile's first satellite
 //              by a short forward scan of the offsets (constants per lane).
-// Outputs are component-major SoA, r[c * P + p], written with non-temporal
-// stores; codes 1, 2, 4 and 7 write NaN states.
+// Outputs are component-major SoA, r[c * P + p] (states by non-temporal
+// stores, codes by ordinary ones); codes 1, 2, 4 and 7 write NaN states.
 #include "sgp4mi_out.h"
 #include "sgp4mi_search.h"
 
