@@ -1,0 +1,149 @@
+"""The GPU's per-satellite constant record against the oracle's initialisation
+constants, field by field (the record is otherwise checked only end to end,
+through the propagated states).
+
+The record's layout is internal to the library (a 512-byte header of 64
+doubles, then per satellite a 512-byte slot: 40 doubles, the same 40 rounded
+to float, a uint32 info word; then per satellite a 256-byte deep-space slot);
+this test reads it back to the host and names the entries in the order the
+library writes them.  FP64 entries must equal the oracle's to 1e-12 relative
+(the two evaluate the same definitions in a different order and with their
+own cube roots and sines); the float block must be the rounding of the double
+block; the info word must carry the oracle's epoch code, simplified-drag and
+deep-space flags.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_27830_amd as sg
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+MU, RE, J2, J3, J4 = oracle.WGS72
+
+# The slot's double entries in the library's order.
+SLOT = ["M0", "Mdot", "argp0", "argpdot", "node0", "nodedot", "nodecf", "C1", "bC4", "t2cof", "argpcof", "eta",
+        "Mcof", "dM0", "D2", "D3", "D4", "bC5", "sinM0", "t3cof", "t4cof", "t5cof", "n0pp", "a0pp", "e0", "aycof",
+        "Lcof", "c41", "x1", "x7", "cosi", "sini", "i0", "epoch_min", "spA1", "spX1h", "spX1k", "spX7q", "spCN",
+        "spCI"]
+NREC = len(SLOT)
+DEEP = ["dedt", "didt", "dMdt", "dnodedt", "dargpdt", "Msun0", "Mmoon0"] + [
+    f"{name}_{body}" for body in ("sun", "moon")
+    for name in ("pe2", "pe3", "pi2", "pi3", "pl2", "pl3", "pl4", "pgh2", "pgh3", "pgh4", "ph2", "ph3")]
+# model-defined drag terms that the simplified model (and deep space) leaves out
+SIMP_ZERO = {"argpcof", "Mcof", "bC5", "D2", "D3", "D4", "t3cof", "t4cof", "t5cof"}
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def read_record(rec):
+    raw = rec.consts.cpu().numpy().tobytes()
+    n = rec.n
+    hdr = np.frombuffer(raw, dtype=np.float64, count=64)
+    slots = np.frombuffer(raw, dtype=np.uint8, count=512 * n, offset=512).reshape(n, 512)
+    d = slots[:, :8 * NREC].copy().view(np.float64)
+    f = slots[:, 8 * NREC:12 * NREC].copy().view(np.float32)
+    info = slots[:, 12 * NREC:12 * NREC + 4].copy().view(np.uint32)[:, 0]
+    deep = np.frombuffer(raw, dtype=np.float64, count=32 * n, offset=512 + 512 * n).reshape(n, 32)
+    return hdr, d, f, info, deep
+
+
+def expected_slot(elem, ci):
+    """The oracle's value of each slot entry (elements, oracle constants, and
+    products the library stores pre-multiplied)."""
+    k2 = 0.5 * J2
+    bstar = elem[6]
+    simp = (ci["isimp"] != 0) | (ci["deep"] != 0)
+    x = {
+        "M0": elem[5], "Mdot": ci["Mdot"], "argp0": elem[4], "argpdot": ci["argpdot"], "node0": elem[3],
+        "nodedot": ci["nodedot"], "nodecf": ci["nodecf"], "C1": ci["C1"], "bC4": bstar * ci["C4"],
+        "t2cof": ci["t2cof"], "argpcof": ci["argpcof"], "eta": ci["eta"], "Mcof": ci["Mcof"], "dM0": ci["dM0"],
+        "D2": ci["D2"], "D3": ci["D3"], "D4": ci["D4"], "bC5": bstar * ci["C5"], "sinM0": ci["sinM0"],
+        "t3cof": ci["t3cof"], "t4cof": ci["t4cof"], "t5cof": ci["t5cof"], "n0pp": ci["n0pp"], "a0pp": ci["a0pp"],
+        "e0": elem[1], "aycof": ci["aycof"], "Lcof": ci["Lcof"], "c41": ci["c41"], "x1": ci["x1"], "x7": ci["x7"],
+        "cosi": ci["cosi"], "sini": ci["sini"], "i0": elem[2], "epoch_min": 1440.0 * elem[7],
+        "spA1": 1.5 * k2 * ci["c41"], "spX1h": 0.5 * k2 * ci["x1"], "spX1k": k2 * ci["x1"],
+        "spX7q": -0.25 * k2 * ci["x7"], "spCN": 1.5 * k2 * ci["cosi"], "spCI": 1.5 * k2 * ci["cosi"] * ci["sini"],
+    }
+    for name in SIMP_ZERO:
+        x[name] = np.where(simp, 0.0, x[name])
+    return x, simp
+
+
+def compare(elem, rec, ci, what):
+    hdr, d, f, info, deep = read_record(rec)
+    x, simp = expected_slot(elem, ci)
+    ok = (ci["epoch_code"] == 0)
+    errs = {}
+    for k, name in enumerate(SLOT):
+        gpu, ora = d[ok, k], x[name][ok]
+        # relative error, measured against a floor of 1e-3 of the column's
+        # largest value (sines near zero, drag terms of nearly circular orbits)
+        floor = max(float(np.max(np.abs(ora), initial=0.0)) * 1e-3, 1e-300)
+        rel = np.abs(gpu - ora) / np.maximum(np.abs(ora), floor)
+        errs[name] = float(rel.max()) if rel.size else 0.0
+    worst = max(errs.items(), key=lambda kv: kv[1])
+    bad = {k: v for k, v in errs.items() if not v <= 1e-12}
+    assert not bad, f"{what}: entries beyond 1e-12: {bad}"
+    # the float block is the rounding of the double block
+    fd = d.astype(np.float32)
+    same = (f == fd) | (np.isnan(f) & np.isnan(fd))
+    assert same.all(), (f"{what}: float block is not the rounding of the doubles at "
+                        f"{[(int(i), SLOT[j]) for i, j in np.argwhere(~same)[:8]]}")
+    # info: code, isimp, deep
+    assert np.array_equal(info & 0xFF, np.where(ci["resonant"] != 0, 7, ci["epoch_code"]).astype(np.uint32))
+    assert np.array_equal(((info >> 8) & 1)[ok], simp[ok].astype(np.uint32))
+    assert np.array_equal((info >> 9) & 1, (ci["deep"] != 0).astype(np.uint32))
+    say(f"  {what}: {int(ok.sum())} satellites, worst {worst[0]} {worst[1]:.2e}")
+    return hdr, d, deep, ok
+
+
+def test_record_matches_oracle_init_near_earth():
+    cat = synth.config1()
+    el = cat.elem.copy()
+    # edge sets: simplified drag (perigee below 220 km), e below the 1e-4 cut,
+    # e = 0, equatorial and retrograde orbits, invalid e (epoch code 1)
+    ke = 60.0 / np.sqrt(RE ** 3 / MU)
+    el[0, :6] = ke * ((RE + 190.0) / RE) ** -1.5
+    el[1, 6:9] = [0.0, 5e-5, 1e-4]
+    el[2, 9:12] = [0.0, np.pi, 2.0]
+    el[1, 12] = 1.2
+    say("[gpu] record vs oracle init, 9,341 near-Earth sets + edge sets")
+    rec = sg.init(torch.from_numpy(el).to(DEV))
+    ci = oracle.init_constants(el)
+    hdr, d, deep, ok = compare(el, rec, ci, "near-Earth")
+    assert not ok[12] and ci["epoch_code"][12] == 1
+    # header: gravity-derived scalars
+    assert abs(hdr[3] / ci["ke"][0] - 1) < 1e-14          # ke
+    assert abs(hdr[5] / ci["vkms"][0] - 1) < 1e-14        # velocity unit
+    assert abs(hdr[8] / ci["j3oj2"][0] - 1) < 1e-14       # J3 / J2
+
+
+def test_record_matches_oracle_init_deep_space():
+    cat = synth.config5(n=512, T=1)
+    ref = synth.DEEP_REF_JD
+    say("[gpu] record vs oracle init, 512 deep-space sets")
+    rec = sg.init(torch.from_numpy(cat.elem).to(DEV), ref_jd=ref)
+    with oracle.reference_jd(ref):
+        ci = oracle.init_constants(cat.elem)
+    hdr, d, deep, ok = compare(cat.elem, rec, ci, "deep space")
+    use = ok & (ci["deep"] != 0) & (ci["resonant"] == 0)
+    assert use.sum() > 300
+    for k, name in enumerate(DEEP):
+        gpu, ora = deep[use, k], ci[name][use]
+        # the bodies' anomalies at epoch (rate x days since 1900, ~1e4 rad before
+        # reduction, whose double rounding alone is ~2e-12) to 1e-11 rad; rates
+        # and coefficients to 1e-12 of each column's scale
+        if name in ("Msun0", "Mmoon0"):
+            m = float(np.max(np.abs(np.remainder(gpu - ora + np.pi, 2 * np.pi) - np.pi)))
+            assert m <= 1e-11, f"deep slot {name} differs by {m:.2e} rad"
+        else:
+            m = float(np.max(np.abs(gpu - ora))) / max(float(np.max(np.abs(ora))), 1e-300)
+            assert m <= 1e-12, f"deep slot {name} differs by {m:.2e}"
+    say(f"  deep slot: {int(use.sum())} non-resonant deep-space satellites, all {len(DEEP)} entries within the bars")
