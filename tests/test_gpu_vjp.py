@@ -4,10 +4,11 @@ the autograd wrapper.
 Bars: FP64 VJP vs the oracle's forward-mode (dual-number) VJP to 1e-8
 relative per satellite (both differentiate the same function; the oracle
 iterates Newton with duals, the kernel uses the implicit-function theorem at
-the root); FP32-mixed vs FP64 for the same cotangent to 1e-4 relative (the
-forward state of the mixed path carries ~1e-7 relative error; measured
-~2e-6); the VJP of a least-squares loss vs central differences of that loss
-to 1e-5 relative.
+the root); FP32-mixed vs FP64 and vs the dual oracle for the same cotangent
+to 1e-4 relative (the forward state of the mixed path carries ~1e-7 relative
+error; measured ~2e-6); the VJP of a least-squares loss vs central
+differences of that loss to 1e-5 relative (FP64), and for the mixed path vs
+central differences of the mixed loss to 2% plus its rounding noise.
 """
 import os
 
@@ -100,6 +101,21 @@ def test_vjp_mixed_matches_fp64_for_the_same_cotangent():
     assert err <= 1e-4
 
 
+def test_vjp_mixed_matches_dual_oracle():
+    """The mixed VJP against the FP64 dual-number oracle on the same (float-
+    representable) cotangent: within 1e-4 per satellite, the forward mixed
+    state's relative error carried through the sweep."""
+    cat = synth.config1(40, 50)
+    rng = np.random.default_rng(11)
+    gr = rng.normal(size=(3, cat.n, cat.T)).astype(np.float32).astype(np.float64)
+    say("[gpu] vjp mixed vs dual oracle")
+    g32 = gpu_vjp(cat.elem, cat.t, gr, None, "mixed")
+    ref = oracle.vjp(cat.elem, cat.t, gr, None)
+    err = rel_err_per_sat(g32, ref)
+    say(f"  max relative error per satellite {err:.3e}")
+    assert err <= 1e-4
+
+
 def _loss_and_grad(cat, r_obs, prec):
     elem = dev(cat.elem).requires_grad_(True)
     r, v, err = sg.SGP4Function.apply(elem, dev(cat.t), prec)
@@ -132,6 +148,34 @@ def test_least_squares_gradient_matches_central_differences():
             fd = (L(h) - L(-h)) / (2 * h)
             assert abs(fd - grad[m, i]) <= 1e-5 * abs(grad[m, i]) + 1e-6 * abs(loss) / max(abs(cat.elem[m, i]), 1e-3), \
                 (m, i, fd, grad[m, i])
+
+
+def test_mixed_least_squares_gradient_matches_central_differences():
+    """The same loss evaluated by the mixed forward kernel: its autograd gradient
+    (the mixed VJP) against central differences of the mixed loss, with steps
+    that move the positions by tens of metres so that the float rounding of the
+    states (a few decimetres, ~1e-3 km^2 in the loss) stays below the
+    difference; bar 2% of the gradient plus that noise over the step."""
+    cat, truth, noise = synth.config4(24, 40)
+    ro, _, eo = oracle.propagate(truth, cat.t)
+    r_obs = ro + noise
+    say("[gpu] mixed least-squares gradient vs central differences of the mixed loss")
+    loss, grad = _loss_and_grad(cat, r_obs, "mixed")
+    steps = [1e-8, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5]
+    worst = 0.0
+    for m, h in enumerate(steps):
+        for i in (0, 7, 19):
+            def L(delta):
+                el = cat.elem.copy()
+                el[m, i] += delta
+                rec = sg.init(dev(el))
+                r, _, _ = sg.propagate(rec, dev(cat.t), "mixed")
+                return float(((r.double() - dev(r_obs)) ** 2).sum().item())
+            fd = (L(h) - L(-h)) / (2 * h)
+            bar = 2e-2 * abs(grad[m, i]) + 2e-3 / (2 * h)
+            worst = max(worst, abs(fd - grad[m, i]) / bar)
+            assert abs(fd - grad[m, i]) <= bar, (m, i, fd, grad[m, i])
+    say(f"  worst |fd - grad| / bar = {worst:.3f}")
 
 
 def test_autograd_gradient_equals_direct_vjp_call():
