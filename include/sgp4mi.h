@@ -285,7 +285,12 @@ int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets,
  * of 64 points; workgroup size; one wavefront per tile or a persistent grid
  * of a given size) and keeps the fastest (SGP4_PLAN_AUTOTUNE), and optionally
  * captures the launch in a HIP graph (SGP4_PLAN_GRAPH).  Without autotuning
- * the plan launches one wavefront per tile in 256-wide workgroups.
+ * the plan launches one wavefront per tile in 256-wide workgroups.  The plan
+ * also reads the record's satellite flags once: when no satellite is a
+ * deep-space one, its tile kernels are those compiled without the deep-space
+ * terms (sgp4_plan_describe reports "near_earth": true); should the record
+ * later be re-initialised with deep-space satellites under the same plan,
+ * their points get code 7 and NaN states (make a new plan).
  * Synchronises `stream`.  Autotuning writes r, v, err. */
 int sgp4_plan_create(sgp4_plan** out, const void* consts, int64_t n, const int64_t* offsets, const double* t,
                      int64_t nnz, int precision, void* r, void* v, uint8_t* err, unsigned flags, void* stream);

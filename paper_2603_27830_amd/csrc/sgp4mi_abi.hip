@@ -37,9 +37,10 @@ bool screen_global_fits(int64_t n, int64_t T);
 size_t screen_static_bytes();
 hipError_t launch_screen_static(const void* r, bool fp64, const uint8_t* err, int64_t n, int64_t T, double D,
                                 int64_t cap, int32_t* pairs, double* dist, unsigned long long* count, hipStream_t s);
-hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
+hipError_t launch_ragged(int precision, int mode, bool deep, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s);
+hipError_t launch_any_deep(const void* consts, int64_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* consts, const double* t, int64_t T,
                       const void* gr, const void* gv, double* gelem, hipStream_t s);
 hipError_t launch_jacobian(int precision, int64_t n, const double* elem, const void* consts, const double* t,
@@ -131,6 +132,9 @@ struct sgp4_plan {
   int64_t nchunks = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // whether the record held a deep-space satellite when the plan was made;
+  // without one the tile kernels are the ones compiled without that branch
+  bool deep = true;
   double best_us = -1.0;
   int ncandidates = 0;
   bool from_cache = false;
@@ -140,10 +144,10 @@ namespace {
 
 hipError_t plan_launch_direct(const sgp4_plan* p, hipStream_t s) {
   if (p->mode == 0)
-    return launch_ragged(p->precision, 0, p->consts, p->n, p->offsets, p->t, p->nnz, p->tile_start, p->tile_sat,
-                         p->ntiles, p->r, p->v, p->err, p->block, p->grid, s);
-  return launch_ragged(p->precision, 1, p->consts, p->n, p->offsets, p->t, p->nnz, nullptr, p->chunk_sat, p->nchunks,
-                       p->r, p->v, p->err, p->block, p->grid, s);
+    return launch_ragged(p->precision, 0, p->deep, p->consts, p->n, p->offsets, p->t, p->nnz, p->tile_start,
+                         p->tile_sat, p->ntiles, p->r, p->v, p->err, p->block, p->grid, s);
+  return launch_ragged(p->precision, 1, true, p->consts, p->n, p->offsets, p->t, p->nnz, nullptr, p->chunk_sat,
+                       p->nchunks, p->r, p->v, p->err, p->block, p->grid, s);
 }
 
 void plan_free(sgp4_plan* p) {
@@ -165,16 +169,17 @@ std::string cache_path() {
 }
 
 std::string tune_key(const sgp4_plan* p) {
-  // Keyed by device, precision and the batch's size class (powers of two of n
-  // and nnz): a plan for a similar batch reuses the choice.
+  // Keyed by device, precision, whether the record holds deep-space
+  // satellites and the batch's size class (powers of two of n and nnz): a
+  // plan for a similar batch reuses the choice.
   hipDeviceProp_t prop;
   int dev = 0;
   std::string arch = "unknown";
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
   for (auto& ch : arch) if (ch == ' ' || ch == ':') ch = '_';
   char buf[256];
-  std::snprintf(buf, sizeof buf, "v3/%s/p%d/n%d/z%d", arch.c_str(), p->precision, int(std::log2(double(p->n) + 1)),
-                int(std::log2(double(p->nnz) + 1)));
+  std::snprintf(buf, sizeof buf, "v4/%s/p%d/d%d/n%d/z%d", arch.c_str(), p->precision, p->deep ? 1 : 0,
+                int(std::log2(double(p->n) + 1)), int(std::log2(double(p->nnz) + 1)));
   return buf;
 }
 
@@ -370,7 +375,7 @@ int sgp4_propagate_ragged(const void* consts, int64_t n, const int64_t* offsets,
   // which the wavefronts loop.
   const int64_t nchunks = (nnz + 63) / 64;
   const unsigned grid = unsigned(std::min<int64_t>((nchunks + 3) / 4, int64_t(0xffffffffu / 256)));
-  return hip_status(launch_ragged(precision, 1, consts, n, offsets, t, nnz, nullptr, nullptr, nchunks, r, v, err, 256,
+  return hip_status(launch_ragged(precision, 1, true, consts, n, offsets, t, nnz, nullptr, nullptr, nchunks, r, v, err, 256,
                                   std::max(grid, 1u), s));
 }
 
@@ -426,6 +431,18 @@ static int plan_build(sgp4_plan** out, const void* consts, int64_t n, const int6
       while (off[size_t(i) + 1] <= q) ++i;
       csat[size_t(k)] = int32_t(i);
     }
+  }
+  // Deep-space satellites in the record (one word read back).
+  {
+    uint32_t* flag = nullptr;
+    uint32_t any = 1;
+    const bool fok = hipMalloc(&flag, sizeof(uint32_t)) == hipSuccess &&
+                     launch_any_deep(consts, n, flag, s) == hipSuccess &&
+                     hipMemcpyAsync(&any, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                     hipStreamSynchronize(s) == hipSuccess;
+    if (flag) (void)hipFree(flag);
+    if (!fok) return SGP4_E_HIP;
+    p->deep = any != 0;
   }
   bool ok = hipMalloc(&p->tile_start, ts.size() * sizeof(int64_t)) == hipSuccess &&
             hipMalloc(&p->tile_sat, tsat.size() * sizeof(int32_t)) == hipSuccess &&
@@ -562,10 +579,10 @@ int sgp4_plan_describe(const sgp4_plan* plan, char* buf, size_t len) {
   if (!plan || !buf || len == 0) return SGP4_E_ARG;
   std::snprintf(buf, len,
                 "{\"mode\": \"%s\", \"block\": %d, \"grid\": %u, \"tiles\": %lld, \"chunks\": %lld, "
-                "\"tuned_us\": %.3f, \"candidates\": %d, \"from_cache\": %s, \"graph\": %s}",
+                "\"tuned_us\": %.3f, \"candidates\": %d, \"from_cache\": %s, \"graph\": %s, \"near_earth\": %s}",
                 plan->mode == 0 ? "tiles" : "flat", plan->block, plan->grid, (long long)plan->ntiles,
                 (long long)plan->nchunks, plan->best_us, plan->ncandidates, plan->from_cache ? "true" : "false",
-                plan->exec ? "true" : "false");
+                plan->exec ? "true" : "false", (plan->mode == 0 && !plan->deep) ? "true" : "false");
   return SGP4_OK;
 }
 

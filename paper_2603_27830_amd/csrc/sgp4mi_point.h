@@ -570,10 +570,22 @@ __device__ __forceinline__ uint32_t load_info(const RecordView& rv, int64_t i) {
 }
 
 // Point of satellite i at t_abs: near-Earth, or the deep-space path.  The
-// branch comes before any constant is loaded.
-template <class TS, class TP, bool kVec>
+// branch comes before any constant is loaded.  kDeep = false: a launch for a
+// record known to hold no deep-space satellite (a ragged plan checks its
+// record when it is created): the constants and the info word load together
+// and the deep-space code is not compiled in; a deep-space satellite met
+// anyway (the record re-initialised under the plan) gets code 7 and no state.
+template <class TS, class TP, bool kVec, bool kDeep = true>
 __device__ __forceinline__ uint32_t propagate_point(const RecordView& rv, int64_t i, const Grav& g, double t_abs,
                                                     PointState<TP>& out) {
+  if (!kDeep) {
+    const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
+    if (c.info & kInfoDeep) {
+      out.ok = false;
+      return 7u;
+    }
+    return sgp4_point<TS, TP>(c, g, t_abs, out);
+  }
   if (load_info<kVec>(rv, i) & kInfoDeep) {
     const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
     return deep_point<TS, TP>(c, g, t_abs, out);

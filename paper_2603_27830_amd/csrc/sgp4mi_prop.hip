@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) dense_persistent_kernel(RecordView rv,
 // waits for them.  tiles_kernel: a persistent grid whose wavefronts loop over
 // tiles (fewer workgroups; each iteration waits for the previous one's stores
 // before reusing their registers).
-template <class TS, class TP, int kBlock, bool kOff32>
+template <class TS, class TP, int kBlock, bool kOff32, bool kDeep>
 __global__ void __launch_bounds__(kBlock) SGP4MI_TILE_OCCUPANCY tile_once_kernel(RecordView rv, const double* __restrict__ t,
                                                            const int64_t* __restrict__ tile_start,
                                                            const int32_t* __restrict__ tile_meta, int64_t ntiles,
@@ -142,11 +142,11 @@ __global__ void __launch_bounds__(kBlock) SGP4MI_TILE_OCCUPANCY tile_once_kernel
   const Grav g = load_grav(rv);
   const int64_t p = kOff32 ? int64_t(uint32_t(start) + uint32_t(lane)) : start + lane;  // kOff32: p < 2^30
   PointState<TP> s;
-  const uint32_t code = propagate_point<TS, TP, false>(rv, sat, g, t[p], s);
+  const uint32_t code = propagate_point<TS, TP, false, kDeep>(rv, sat, g, t[p], s);
   out.put(p, code, s);
 }
 
-template <class TS, class TP, int kBlock, bool kOff32>
+template <class TS, class TP, int kBlock, bool kOff32, bool kDeep>
 __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const double* __restrict__ t,
                                                        const int64_t* __restrict__ tile_start,
                                                        const int32_t* __restrict__ tile_meta, int64_t ntiles,
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kBlock) tiles_kernel(RecordView rv, const doub
     const int32_t len = __builtin_amdgcn_readfirstlane(tile_meta[2 * w + 1]);
     if (lane < len) {
       PointState<TP> s;  // satellite uniform: scalar constants
-      const uint32_t code = propagate_point<TS, TP, false>(rv, sat, g, t[start + lane], s);
+      const uint32_t code = propagate_point<TS, TP, false, kDeep>(rv, sat, g, t[start + lane], s);
       out.put(start + lane, code, s);
     }
   }
@@ -408,40 +408,51 @@ hipError_t launch_dense(int precision, const void* consts, int64_t n, const doub
 }
 
 template <class TS, class TP, int kBlock, bool kOff32>
-static void ragged_go(int mode, unsigned grid, hipStream_t s, const RecordView& rv, const int64_t* offsets,
-                      int64_t n, const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
-                      int64_t ntiles, void* r, void* v, uint8_t* err) {
+static void ragged_go(int mode, bool deep, unsigned grid, hipStream_t s, const RecordView& rv,
+                      const int64_t* offsets, int64_t n, const double* t, int64_t nnz, const int64_t* tile_start,
+                      const int32_t* tile_sat, int64_t ntiles, void* r, void* v, uint8_t* err) {
   Out<TP, kOff32> o{static_cast<TP*>(r), static_cast<TP*>(v), err, nnz};
-  if (mode == 0 && int64_t(grid) * (kBlock / 64) >= ntiles)
-    hipLaunchKernelGGL((tile_once_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, t, tile_start,
-                       tile_sat, ntiles, o);
-  else if (mode == 0)
-    hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, t, tile_start,
-                       tile_sat, ntiles, o);
+  if (mode == 0 && int64_t(grid) * (kBlock / 64) >= ntiles) {
+    if (deep)
+      hipLaunchKernelGGL((tile_once_kernel<TS, TP, kBlock, kOff32, true>), dim3(grid), dim3(kBlock), 0, s, rv, t,
+                         tile_start, tile_sat, ntiles, o);
+    else
+      hipLaunchKernelGGL((tile_once_kernel<TS, TP, kBlock, kOff32, false>), dim3(grid), dim3(kBlock), 0, s, rv, t,
+                         tile_start, tile_sat, ntiles, o);
+  } else if (mode == 0) {
+    if (deep)
+      hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock, kOff32, true>), dim3(grid), dim3(kBlock), 0, s, rv, t,
+                         tile_start, tile_sat, ntiles, o);
+    else
+      hipLaunchKernelGGL((tiles_kernel<TS, TP, kBlock, kOff32, false>), dim3(grid), dim3(kBlock), 0, s, rv, t,
+                         tile_start, tile_sat, ntiles, o);
+  }
   else
     hipLaunchKernelGGL((flat_kernel<TS, TP, kBlock, kOff32>), dim3(grid), dim3(kBlock), 0, s, rv, offsets, n, t, nnz,
                        tile_sat, ntiles, o);
 }
 
 template <class TS, class TP, int kBlock>
-static void ragged_b(int mode, unsigned grid, hipStream_t s, const RecordView& rv, const int64_t* offsets, int64_t n,
-                     const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat, int64_t ntiles,
-                     void* r, void* v, uint8_t* err) {
+static void ragged_b(int mode, bool deep, unsigned grid, hipStream_t s, const RecordView& rv, const int64_t* offsets,
+                     int64_t n, const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
+                     int64_t ntiles, void* r, void* v, uint8_t* err) {
   if (fits32<TP>(nnz))
-    ragged_go<TS, TP, kBlock, true>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err);
+    ragged_go<TS, TP, kBlock, true>(mode, deep, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v,
+                                    err);
   else
-    ragged_go<TS, TP, kBlock, false>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err);
+    ragged_go<TS, TP, kBlock, false>(mode, deep, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v,
+                                     err);
 }
 
 template <class TS, class TP>
-static hipError_t ragged_t(int mode, const RecordView& rv, const int64_t* offsets, int64_t n, const double* t,
-                           int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat, int64_t ntiles, void* r,
-                           void* v, uint8_t* err, int block, unsigned grid, hipStream_t s) {
+static hipError_t ragged_t(int mode, bool deep, const RecordView& rv, const int64_t* offsets, int64_t n,
+                           const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
+                           int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s) {
   switch (block) {
-    case 64: ragged_b<TS, TP, 64>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
-    case 128: ragged_b<TS, TP, 128>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
-    case 256: ragged_b<TS, TP, 256>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
-    case 512: ragged_b<TS, TP, 512>(mode, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 64: ragged_b<TS, TP, 64>(mode, deep, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 128: ragged_b<TS, TP, 128>(mode, deep, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 256: ragged_b<TS, TP, 256>(mode, deep, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
+    case 512: ragged_b<TS, TP, 512>(mode, deep, grid, s, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -451,20 +462,38 @@ static hipError_t ragged_t(int mode, const RecordView& rv, const int64_t* offset
 // ntiles tiles; one wavefront per tile when the grid covers them all, else a
 // persistent loop); mode 1: flat (tile_sat holds
 // the chunk satellites of ntiles = ceil(nnz / 64) chunks or is null for the
-// in-kernel search; tile_start unused).
-hipError_t launch_ragged(int precision, int mode, const void* consts, int64_t n, const int64_t* offsets,
+// in-kernel search; tile_start unused).  deep = false (mode 0 only): the
+// record holds no deep-space satellite; kernels without the deep-space branch.
+hipError_t launch_ragged(int precision, int mode, bool deep, const void* consts, int64_t n, const int64_t* offsets,
                          const double* t, int64_t nnz, const int64_t* tile_start, const int32_t* tile_sat,
                          int64_t ntiles, void* r, void* v, uint8_t* err, int block, unsigned grid, hipStream_t s) {
   const RecordView rv = view_of(consts, n);
+  deep = deep || mode != 0;
   switch (precision) {
-    case 0: return ragged_t<double, double>(mode, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err,
-                                            block, grid, s);
-    case 1: return ragged_t<float, float>(mode, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err,
-                                          block, grid, s);
-    case 2: return ragged_t<double, float>(mode, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v, err,
-                                           block, grid, s);
+    case 0: return ragged_t<double, double>(mode, deep, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v,
+                                            err, block, grid, s);
+    case 1: return ragged_t<float, float>(mode, deep, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v,
+                                          err, block, grid, s);
+    case 2: return ragged_t<double, float>(mode, deep, rv, offsets, n, t, nnz, tile_start, tile_sat, ntiles, r, v,
+                                           err, block, grid, s);
   }
   return hipErrorInvalidValue;
+}
+
+// Whether any satellite of the record carries the deep-space bit: *flag (a
+// device word) is cleared, then set by every lane whose satellite has it.
+__global__ void clear_word_kernel(uint32_t* flag) { *flag = 0u; }
+__global__ void __launch_bounds__(256) any_deep_kernel(RecordView rv, int64_t n, uint32_t* flag) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n && (rv.slots[i].info & kInfoDeep)) atomicOr(flag, 1u);
+}
+hipError_t launch_any_deep(const void* consts, int64_t n, uint32_t* flag, hipStream_t s) {
+  const RecordView rv = view_of(consts, n);
+  hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, s, flag);
+  const int64_t blocks = (n + 255) / 256;
+  // the grid in chunks of at most 2^31 - 1 workgroups is never needed: n < 2^31 here
+  hipLaunchKernelGGL(any_deep_kernel, dim3(unsigned(blocks > 0 ? blocks : 1)), dim3(256), 0, s, rv, n, flag);
+  return hipGetLastError();
 }
 
 }  // namespace sgp4mi

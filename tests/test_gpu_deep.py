@@ -14,6 +14,8 @@ The catalogue is the seeded deep-space stand-in (navigation MEO, transfer
 orbits including inclinations below 0.2 rad, other high orbits, and the two
 resonant classes), epochs within +-3 days of 2026 January 13.
 """
+import ctypes
+import json
 import math
 import os
 
@@ -23,6 +25,7 @@ import torch
 
 import oracle
 import paper_2603_27830_amd as sg
+from paper_2603_27830_amd import _native
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -126,6 +129,8 @@ def test_deep_ragged_lists_plan_and_no_plan():
         outs = [host(*sg.propagate_ragged(rec, doff, dt, prec))]
         for mode in (0, 1):
             plan = sg.RaggedPlan(rec, doff, dt, prec, config=(mode, 256, 0))
+            # a record with deep-space satellites keeps the general kernels
+            assert json.loads(plan.describe())["near_earth"] is False
             outs.append(host(*plan.launch()))
             plan.close()
         e0 = np.repeat(cat.elem[1], lens)
@@ -201,3 +206,53 @@ def test_deep_code_3_near_parabolic():
     same = (eo == 3) | (eo == 7)
     assert np.array_equal(err[same], eo[same])
     assert np.all(np.isnan(r[:, err == 3]))
+
+
+def test_near_earth_plan_after_reinitialisation_with_deep_sets():
+    """A plan made for a record without deep-space satellites runs the kernels
+    compiled without the deep-space terms (describe: near_earth).  If the same
+    record buffer is then re-initialised with deep-space sets, the plan gives
+    their points code 7 and NaN, and the near-Earth satellites stay exact."""
+    near = synth.config1(64, 1).elem
+    deep = synth.config5(64, 1).elem
+    mix = near.copy()
+    mix[:, 1::4] = deep[:, 1::4]                   # every fourth satellite deep space
+    rng = np.random.default_rng(21)
+    lens = rng.integers(1, 200, near.shape[1])
+    offsets = np.zeros(near.shape[1] + 1, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    t = np.concatenate([np.sort(rng.uniform(0.0, 4000.0, L)) for L in lens])
+    rec = sg.init(dev(near), ref_jd=REF)
+    doff, dt = dev(offsets), dev(t)
+    for prec in ("fp64", "mixed"):
+        say(f"[gpu] near-Earth plan {prec}: near-Earth record, then the buffer re-initialised with deep sets")
+        rec = sg.init(dev(near), ref_jd=REF)
+        plan = sg.RaggedPlan(rec, doff, dt, prec, autotune=False, graph=True)
+        assert json.loads(plan.describe())["near_earth"] is True
+        with oracle.reference_jd(REF):
+            ro, vo, eo = oracle.propagate_ragged(near, offsets, t, nthreads=NTHREADS)
+        r, v, err = host(*plan.launch())
+        if prec == "fp64":
+            check_fp64(r, v, err, ro, vo, eo)
+        else:
+            check_mixed(r, v, err, ro, vo, eo, np.repeat(near[1], lens))
+        # re-initialise the same record buffer in place with the mixed catalogue
+        el = dev(mix)
+        ref = (ctypes.c_double * 2)(REF, 0.0)
+        _native.check(_native.lib().sgp4_init_ex(None, ref, mix.shape[1], ctypes.c_void_p(el.data_ptr()),
+                                                 ctypes.c_void_p(rec.consts.data_ptr()), None, None), "sgp4_init_ex")
+        torch.cuda.synchronize()
+        r, v, err = host(*plan.launch())
+        sat = np.repeat(np.arange(mix.shape[1]), lens)
+        is_deep = (np.arange(mix.shape[1]) % 4) == 1
+        dp = is_deep[sat]
+        assert np.all(err[dp] == 7) and np.all(np.isnan(r[:, dp])) and np.all(np.isnan(v[:, dp]))
+        with oracle.reference_jd(REF):
+            ro2, vo2, eo2 = oracle.propagate_ragged(mix, offsets, t, nthreads=NTHREADS)
+        keep = ~dp
+        if prec == "fp64":
+            check_fp64(r[:, keep], v[:, keep], err[keep], ro2[:, keep], vo2[:, keep], eo2[keep])
+        else:
+            check_mixed(r[:, keep], v[:, keep], err[keep], ro2[:, keep], vo2[:, keep], eo2[keep],
+                        np.repeat(mix[1], lens)[keep])
+        plan.close()
