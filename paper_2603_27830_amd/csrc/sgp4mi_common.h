@@ -42,8 +42,17 @@ enum Rec : int {
 // without a conversion per point.
 // kHRefDay: the reference instant of the epoch row, in days after JD 2415020.0
 // (1900 January 0.5, the origin of the lunar and solar arguments).
+// kHGen, kHDeepGen: whether the record holds a deep-space satellite, without
+// atomics or a clearing pass: every initialisation takes a fresh generation
+// number g, the thread that writes the header stores g in kHGen and every
+// deep-space satellite's thread stores g in kHDeepGen.  The two are equal if
+// and only if this initialisation met a deep-space satellite (kHDeepGen can
+// hold an older generation, never the current one otherwise; a stale equal
+// value, possible only for a buffer reused across processes, just selects
+// the general code path).
 enum Hdr : int {
   kHMagic, kHN, kHNpad, kHKe, kHRadius, kHVkms, kHK2, kHJ2, kHJ3oJ2, kHJ4, kHMu, kHF32, kHRefDay = kHF32 + 2,
+  kHGen, kHDeepGen,
   kHCount = 64
 };
 constexpr double kMagic = 20260331.0;
@@ -100,6 +109,15 @@ struct RecordView {
   const Slot* slots;
   const DeepSlot* deep;
 };
+
+// Whether the record's initialisation met a deep-space satellite (see
+// kHGen); read through the constant address space (scalar loads of two
+// header words every wavefront shares).
+__device__ __forceinline__ bool record_has_deep(const RecordView& rv) {
+  typedef const __attribute__((address_space(4))) double* CHdrD;
+  const CHdrD h = (CHdrD)rv.hdr;
+  return h[kHGen] == h[kHDeepGen];
+}
 
 inline RecordView view_of(const void* base, int64_t n) {
   RecordView v;

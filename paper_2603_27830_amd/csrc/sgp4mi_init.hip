@@ -2,6 +2,9 @@
 //
 // One lane per satellite, double precision; the model's steps are in
 // sgp4mi_initcore.h (shared with the derivative kernel of the VJP).
+#include <atomic>
+#include <chrono>
+
 #include "sgp4mi_initcore.h"
 
 namespace sgp4mi {
@@ -15,6 +18,7 @@ struct InitArgs {
   uint8_t* user_flags;  // nullable
   double mu, radius, j2, j3, j4;
   double ref_day;       // reference instant of the epoch row, days after JD 2415020.0
+  double gen;           // this initialisation's generation number (kHGen)
 };
 
 // kStaged: the 64 records of the workgroup are assembled in LDS and copied
@@ -41,6 +45,7 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     h[kHJ4] = a.j4;
     h[kHMu] = a.mu;
     h[kHRefDay] = a.ref_day;
+    h[kHGen] = a.gen;
     float* hf = reinterpret_cast<float*>(h + kHF32);
     hf[0] = float(a.radius);
     hf[1] = float(a.radius * ke / 60.0);
@@ -74,6 +79,7 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
       slot->f[k] = float(rec[k]);
     }
     slot->info = code | (isimp ? kInfoIsimp : 0u) | (deep ? kInfoDeep : 0u);
+    if (deep) a.hdr[kHDeepGen] = a.gen;  // every such thread stores the same value
     if (a.user_flags) {
       uint8_t f = 0;
       if (deep) f |= 1;
@@ -98,6 +104,15 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
 // latency that a few hundred workgroups do not hide).
 constexpr int64_t kInitStagedFrom = 65536;
 
+// Generation numbers of initialisations: process-wide and increasing, seeded
+// from the clock so that a record buffer reused by another process rarely
+// meets its old value (which would only select the general code path).
+static double next_generation() {
+  static std::atomic<uint64_t> counter{uint64_t(std::chrono::steady_clock::now().time_since_epoch().count()) &
+                                       ((uint64_t(1) << 40) - 1)};
+  return double(++counter);  // below 2^41: exact in a double
+}
+
 hipError_t launch_init(const double g[5], double ref_day, int64_t n, const double* elem, void* consts,
                        uint8_t* user_flags, hipStream_t s) {
   InitArgs a;
@@ -109,6 +124,7 @@ hipError_t launch_init(const double g[5], double ref_day, int64_t n, const doubl
   a.slots = reinterpret_cast<Slot*>(b + kHCount * 8);
   a.deep = reinterpret_cast<DeepSlot*>(b + kHCount * 8 + size_t(kSlotBytes) * size_t(n));
   a.ref_day = ref_day;
+  a.gen = next_generation();
   a.user_flags = user_flags;
   a.mu = g[0]; a.radius = g[1]; a.j2 = g[2]; a.j3 = g[3]; a.j4 = g[4];
   const int64_t blocks = (n + 63) / 64;  // 64-wide: a short kernel spread over more compute units

@@ -569,16 +569,20 @@ __device__ __forceinline__ uint32_t load_info(const RecordView& rv, int64_t i) {
   return ((CSlot)(rv.slots + i))->info;
 }
 
-// Point of satellite i at t_abs: near-Earth, or the deep-space path.  The
-// branch comes before any constant is loaded.  kDeep = false: a launch for a
-// record known to hold no deep-space satellite (a ragged plan checks its
-// record when it is created): the constants and the info word load together
-// and the deep-space code is not compiled in; a deep-space satellite met
-// anyway (the record re-initialised under the plan) gets code 7 and no state.
+// Point of satellite i at t_abs: near-Earth, or the deep-space path.
+//
+// When the record holds no deep-space satellite (record_has_deep: two header
+// words every wavefront shares) the constants and the info word load together
+// and go to the near-Earth terms; otherwise the info word comes first and the
+// branch precedes any other load (so the deep-space terms do not hold the
+// near-Earth constants).  kDeep = false: an instantiation without the
+// deep-space terms at all, for a ragged plan whose record held none when the
+// plan was made; a deep-space satellite met anyway (the record re-initialised
+// under the plan) gets code 7 and no state.
 template <class TS, class TP, bool kVec, bool kDeep = true>
 __device__ __forceinline__ uint32_t propagate_point(const RecordView& rv, int64_t i, const Grav& g, double t_abs,
                                                     PointState<TP>& out) {
-  if (!kDeep) {
+  if (!kDeep || !record_has_deep(rv)) {
     const SatC<TS, TP> c = load_sat<TS, TP, kVec>(rv, i);
     if (c.info & kInfoDeep) {
       out.ok = false;
