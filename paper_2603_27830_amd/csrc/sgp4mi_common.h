@@ -18,23 +18,34 @@ namespace sgp4mi {
 //       bytes 320..479  kNRec floats  (the same constants rounded to float)
 //       bytes 480..483  uint32 info: bits 0-7 satellite code, bit 8 isimp,
 //                       bit 9 deep space
+//       (entries ordered so that the FP32-mixed path touches two lines)
 //   [n deep-space slots of kDeepBytes = 256 bytes, one per satellite]: the
 //       lunar-solar secular rates, the long-period coefficients of the Sun and
 //       the Moon and their mean anomalies at epoch (written and read only for
 //       satellites with the deep-space bit)
 // One contiguous slot per satellite: a wavefront working on one satellite
 // fetches its constants with a few wide loads from one base address.
+// Order: the FP32-mixed near-Earth path reads the double copies of the first
+// 13 entries (bytes 0-103 of the slot: one 128-byte line) and the float copies
+// of entries 16-39 with the info word (bytes 384-483: another line), so a
+// wavefront of that path fetches two of the slot's four lines.
 enum Rec : int {
-  kM0, kMdot, kArgp0, kArgpdot, kNode0, kNodedot, kNodecf, kC1, kBC4, kT2cof,
-  kArgpcof, kEta, kMcof, kDM0, kD2, kD3, kD4, kBC5, kSinM0, kT3cof, kT4cof, kT5cof,
-  kN0pp, kA0pp, kE0, kAycof, kLcof, kC41, kX1, kX7, kCosi, kSini, kI0, kEpochMin,
+  // secular terms the mixed path keeps in double
+  kM0, kMdot, kArgp0, kArgpdot, kNode0, kNodedot, kNodecf, kT2cof, kT3cof, kT4cof, kT5cof, kN0pp, kEpochMin,
+  // read by FP64 only
+  kC41, kX1, kX7,
+  // taken in float by the mixed path
+  kEta, kDM0, kSinM0, kAycof, kLcof, kCosi, kSini, kI0,
   // the short-period coefficients with k2 = J2 / 2 folded in (per point they
   // are multiplied by powers of 1 / p_L only): 1.5 k2 (3 cos^2 i - 1),
   // k2 / 2 sin^2 i, k2 sin^2 i, -k2 / 4 (7 cos^2 i - 1), 1.5 k2 cos i and
   // 1.5 k2 cos i sin i
   kSpA1, kSpX1h, kSpX1k, kSpX7q, kSpCN, kSpCI,
+  // drag coefficients (the float paths' polynomials), mean a and e at epoch
+  kC1, kBC4, kD2, kD3, kD4, kBC5, kMcof, kArgpcof, kA0pp, kE0,
   kNRec
 };
+static_assert(kEpochMin == 12 && kEta == 16 && kNRec == 40, "slot line layout");
 
 // Header slots (doubles).
 // kHF32: float copies of radius, velocity unit and k2 (three floats in the

@@ -26,10 +26,9 @@ DEV = torch.device("cuda:0")
 MU, RE, J2, J3, J4 = oracle.WGS72
 
 # The slot's double entries in the library's order.
-SLOT = ["M0", "Mdot", "argp0", "argpdot", "node0", "nodedot", "nodecf", "C1", "bC4", "t2cof", "argpcof", "eta",
-        "Mcof", "dM0", "D2", "D3", "D4", "bC5", "sinM0", "t3cof", "t4cof", "t5cof", "n0pp", "a0pp", "e0", "aycof",
-        "Lcof", "c41", "x1", "x7", "cosi", "sini", "i0", "epoch_min", "spA1", "spX1h", "spX1k", "spX7q", "spCN",
-        "spCI"]
+SLOT = ["M0", "Mdot", "argp0", "argpdot", "node0", "nodedot", "nodecf", "t2cof", "t3cof", "t4cof", "t5cof", "n0pp",
+        "epoch_min", "c41", "x1", "x7", "eta", "dM0", "sinM0", "aycof", "Lcof", "cosi", "sini", "i0", "spA1", "spX1h",
+        "spX1k", "spX7q", "spCN", "spCI", "C1", "bC4", "D2", "D3", "D4", "bC5", "Mcof", "argpcof", "a0pp", "e0"]
 NREC = len(SLOT)
 DEEP = ["dedt", "didt", "dMdt", "dnodedt", "dargpdt", "Msun0", "Mmoon0"] + [
     f"{name}_{body}" for body in ("sun", "moon")
