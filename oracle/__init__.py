@@ -36,7 +36,10 @@ INIT_NAMES = [
     "D2", "D3", "D4", "t3cof", "t4cof", "t5cof", "isimp", "deep", "epoch_code", "ke", "j3oj2", "vkms",
     "resonant", "dedt", "didt", "dMdt", "dnodedt", "dargpdt", "Msun0", "Mmoon0",
 ] + [f"{name}_{body}" for body in ("sun", "moon")
-     for name in ("pe2", "pe3", "pi2", "pi3", "pl2", "pl3", "pl4", "pgh2", "pgh3", "pgh4", "ph2", "ph3")]
+     for name in ("pe2", "pe3", "pi2", "pi3", "pl2", "pl3", "pl4", "pgh2", "pgh3", "pgh4", "ph2", "ph3")] + [
+    "irez", "xlamo", "xfact", "gsto"] + [f"res{k}" for k in range(10)]
+RES_F = ["F311", "F220", "F330", "F221", "F321", "F322", "F441", "F442", "F522", "F523", "F542", "F543"]
+RES_G = ["G310s", "G200", "G300", "G201", "G211", "G310", "G322", "G410", "G422", "G520", "G532", "G521", "G533"]
 WGS72 = (398600.8, 6378.135, 0.001082616, -0.00000253881, -0.00000165597)
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -64,6 +67,12 @@ def lib():
         L.oracle_count_ops.argtypes = [_dp, _dp, ctypes.c_double, _u64p]
         L.oracle_set_reference_jd.argtypes = [ctypes.c_double, ctypes.c_double]
         L.oracle_reference_jd.restype = ctypes.c_double
+        L.oracle_resonance_functions.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
+        L.oracle_resonance_constants.argtypes = [_dp]
+        L.oracle_gmst.argtypes = [ctypes.c_double]
+        L.oracle_gmst.restype = ctypes.c_double
+        L.oracle_resonance_rates.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.oracle_resonance_integrate.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.oracle_ke.argtypes = [_dp]
         L.oracle_ke.restype = ctypes.c_double
         assert L.oracle_detail_count() == ND
@@ -196,3 +205,42 @@ class reference_jd:
 def ke(grav=None):
     g = _grav(grav)
     return lib().oracle_ke(_p(g))
+
+
+def resonance_functions(e, inc):
+    """The model's inclination and eccentricity functions of the resonant
+    terms at (e, i): two dicts keyed by RES_F and RES_G names."""
+    out = np.empty(len(RES_F) + len(RES_G))
+    lib().oracle_resonance_functions(float(e), float(inc), _p(out))
+    return dict(zip(RES_F, out[:len(RES_F)])), dict(zip(RES_G, out[len(RES_F):]))
+
+
+def resonance_constants():
+    """Earth rotation rate (rad/min), step (min), and the 24 h / 12 h term
+    tables as lists of dicts (j, k, l, phase, J)."""
+    out = np.empty(2 + 5 * 13)
+    m = lib().oracle_resonance_constants(_p(out))
+    assert m == out.size
+    terms = [dict(zip(("j", "k", "l", "phase", "J"), out[2 + 5 * i:7 + 5 * i])) for i in range(13)]
+    return float(out[0]), float(out[1]), terms[:3], terms[3:]
+
+
+def gmst(jd):
+    """Greenwich mean sidereal angle (rad) at Julian date jd (UT1)."""
+    return lib().oracle_gmst(float(jd))
+
+
+def resonance_rates(elem1, xli, xni, atime, grav=None):
+    """(dn/dt, d2n/dt2, dlambda/dt) of one element set's resonance, and its class."""
+    e = _f64(elem1).reshape(-1); g = _grav(grav)
+    out = np.empty(3)
+    cls = lib().oracle_resonance_rates(_p(g), _p(e), float(xli), float(xni), float(atime), _p(out))
+    return out, cls
+
+
+def resonance_integrate(elem1, t, grav=None):
+    """(lambda, n, time of the last step) integrated to t minutes after epoch, and the class."""
+    e = _f64(elem1).reshape(-1); g = _grav(grav)
+    out = np.empty(3)
+    cls = lib().oracle_resonance_integrate(_p(g), _p(e), float(t), _p(out))
+    return out, cls

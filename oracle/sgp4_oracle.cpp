@@ -17,9 +17,9 @@
 // Orbits with periods of 225 min or more take the deep-space model's lunar and
 // solar terms (Hujsak 1979 in the same reports; section 6 of the paper names
 // deep space as the variant it leaves out): secular rates and long-period terms
-// of the quadrupole tidal potential of the Sun and the Moon (I9, P2d, P4d).  The
-// 12 h and 24 h resonant classes, whose resonance integrator this oracle does
-// not implement, are flagged and not propagated.
+// of the quadrupole tidal potential of the Sun and the Moon (I9, P2d, P4d), and,
+// for the 12 h and 24 h resonant classes, the tesseral resonance of the
+// geopotential, integrated in mean motion and mean longitude (I10, P3r).
 //
 // Readings where the paper is silent (each is listed in the design notes):
 //  * WGS72: mu = 398600.8 km^3/s^2, R = 6378.135 km, J2 = 0.001082616,
@@ -32,14 +32,16 @@
 //    flagged, not exited): 1 mean eccentricity outside [-0.001, 1) (or e0
 //    outside [0, 1) at epoch), 2 mean motion n0'' not > 0, 3 deep space: the
 //    lunar-solar terms move e outside [0, 1], 4 semi-latus rectum p_L < 0, 6
-//    decayed (r_k < 1 earth radius; state still written), 7 resonant deep-space
-//    element set (not propagated).  Checks run in the order 1(epoch) -> 2 -> 7
-//    -> 1 -> 3 -> 4 -> 6; the first failing one wins.  Codes 1, 2, 3, 4, 7
-//    write NaN to r and v.
+//    decayed (r_k < 1 earth radius; state still written).  Checks run in the
+//    order 1(epoch) -> 2 -> 2 (resonance-integrated mean motion) -> 1 -> 3 ->
+//    4 -> 6; the first failing one wins.  Codes 1, 2, 3, 4 write NaN to r and v.
+//    (Code 7, "not propagated", is the library's, for paths that leave deep
+//    space out; this oracle never returns it.)
 //  * Deep space: the lunar and solar arguments use absolute time, the epoch
 //    row taken as days after a reference Julian date (J2000.0 unless set); the
 //    node is reduced with floor to [0, 2*pi) before the low-inclination form
-//    uses its value.
+//    uses its value.  The Greenwich sidereal angle of the resonance is the
+//    IAU 1982 mean sidereal time of that instant, taken as UT1.
 //  * Checks are written so that NaN fails them (NaN never passes as valid).
 //  * Angles are reduced with floor to [0, 2*pi).
 //  * pow(x, 2/3) is cbrt(x)^2 and x^1.5 is x*sqrt(x).
@@ -59,14 +61,24 @@
 // against textbook astronomy, the five secular rates and the ten twice-anomaly
 // periodic coefficients per body against Lagrange's equations on the
 // numerically averaged quadrupole, the body-eccentricity terms, the
-// low-inclination form at its switch, the resonance flags and code 3.
+// low-inclination form at its switch, the resonance flags and code 3;
+// resonance: the inclination functions against Kaula's closed form, the
+// eccentricity functions against Hansen coefficients by quadrature, the 24 h
+// rates against the tesseral field's along-track force on a geostationary
+// orbit (stable longitudes, drift acceleration), the 12 h rates against the
+// resonant arguments the tesseral terms select, the integrator against a
+// fine numerical solution of its own equations, the sidereal time against
+// its epoch value and rate, and a geostationary satellite's Earth-fixed
+// longitude drift end to end.
 //
 // Parity unpinned (model definitions no available pin reaches): the J2 bracket
 // of C4, the eccentricity factor (beta0^2) of the drag node term, the
 // low-perigee density parameter (156 km / 98 km branch), the 220 km
 // simplified-drag switch, the e0 > 1e-4 gate and the 1.5e-12 guard; in deep
 // space the 0.2 rad switch value, the 3-degree cut of the node rate, the
-// resonance bands and the first-order true anomaly of the bodies; and, as a
+// resonance bands, the first-order true anomaly of the bodies, the tesseral
+// magnitudes and phases of degrees 3 to 5 of the 12 h class, the 720-minute
+// step and the eccentricity ranges of the 12 h fits; and, as a
 // whole, numeric agreement with the published model's own verification
 // vectors, which are not available here.
 //
@@ -217,6 +229,14 @@ struct Sat {
   // flagged and not propagated.
   bool resonant = false;
   S dedt, didt, dMdt, dnodedt, dargpdt;
+  // Resonance (I10): class (1: 24 h, 2: 12 h), the coefficients of its terms
+  // (24 h: three; 12 h: ten), the mean longitude of the resonant argument at
+  // epoch, its rate apart from the integrated mean motion, and the Greenwich
+  // sidereal angle at epoch.
+  int irez = 0;
+  S res[10];
+  S xlamo, xfact;
+  double gsto = 0.0;
   S pe2[2], pe3[2], pi2[2], pi3[2], pl2[2], pl3[2], pl4[2], pgh2[2], pgh3[2], pgh4[2], ph2[2], ph3[2];
   double Mbody0[2];
 };
@@ -361,7 +381,8 @@ void deep_init(Sat<S>& c, double day) {
 
   // Resonance classes: 24 h (synchronous) and 12 h with e >= 0.5.
   const double nv = val(c.n0pp), ev = val(c.e0);
-  c.resonant = (nv < 0.0052359877 && nv > 0.0034906585) || (nv >= 8.26e-3 && nv <= 9.24e-3 && ev >= 0.5);
+  c.irez = (nv < 0.0052359877 && nv > 0.0034906585) ? 1 : (nv >= 8.26e-3 && nv <= 9.24e-3 && ev >= 0.5) ? 2 : 0;
+  c.resonant = c.irez != 0;
 
   // Secular rates: the doubly averaged quadrupole in Lagrange's equations.
   // Near-equatorial orbits (inclination within 3 degrees of 0 or 180) take no
@@ -385,6 +406,197 @@ void deep_init(Sat<S>& c, double day) {
   c.dMdt = dM;
   c.dnodedt = dh;
   c.dargpdt = dgh - cim * dh;
+}
+
+// ------------------------------------------------------------- resonance --
+// Tesseral resonance of the deep-space model (Hoots & Roehrich 1980 as revised
+// by Vallado et al. 2006).  An orbit whose mean motion is commensurate with the
+// Earth's rotation (24 h: once per sidereal day; 12 h: twice, for e >= 0.5)
+// feels tesseral harmonics J_lm of the geopotential secularly, through the
+// arguments psi = (l-2p) w + k M + m (node - theta) - m lambda_lm with
+// k = l-2p+q.  Lagrange's equation dn/dt = -(3/a^2) dR/dM gives, per term,
+// dn/dt = 3 n^2 (R/a)^l k F_lmp(i) G_lpq(e) J_lm sin psi (F: Kaula's
+// inclination function, G: the eccentricity function).  Mean motion and the
+// mean longitude of the resonant argument (24 h: M + node + w - theta; 12 h:
+// M + 2 node - 2 theta) are integrated from epoch with fixed 720-minute
+// second-order Taylor steps.
+
+// Earth's rotation rate (rad/min), the integrator's step (min) and its reach
+// from epoch (10 Julian years, min): beyond it, or for a time that is not
+// finite, the integrated mean motion is NaN (code 2).
+constexpr double kEarthRate = 4.37526908801129966e-3;
+constexpr double kResStep = 720.0;
+constexpr double kResReach = 5259600.0;
+
+// One resonant term: sin(j w + k lambda - phase), with degree l and the
+// tesseral magnitude J_lm of the model's geopotential.
+struct ResTerm { int j, k, l; double phase, J; };
+// 24 h: (l, m) = (3, 1), (2, 2), (3, 3); phases m lambda_lm.
+constexpr ResTerm kRes24[3] = {
+    {0, 1, 3, 0.13130908, 2.1460748e-6},
+    {0, 2, 2, 2.0 * 2.8843198, 1.7891679e-6},
+    {0, 3, 3, 3.0 * 0.37448087, 2.2123015e-7}};
+// 12 h, in the order (l m p q) = 2201 2211 3210 3222 4410 4422 5220 5232 5421
+// 5433 (q signed as k - (l - 2p)).
+constexpr ResTerm kRes12[10] = {
+    {2, 1, 2, 5.7686396, 1.7891679e-6}, {0, 1, 2, 5.7686396, 1.7891679e-6},
+    {1, 1, 3, 0.95240898, 3.7393792e-7}, {-1, 1, 3, 0.95240898, 3.7393792e-7},
+    {2, 2, 4, 1.8014998, 7.3636953e-9}, {0, 2, 4, 1.8014998, 7.3636953e-9},
+    {1, 1, 5, 1.0508330, 1.1428639e-7}, {-1, 1, 5, 1.0508330, 1.1428639e-7},
+    {1, 2, 5, 4.4108898, 2.1765803e-9}, {-1, 2, 5, 4.4108898, 2.1765803e-9}};
+
+// Inclination functions F_lmp(i) of the resonant terms: 24 h (3,1,1),
+// (2,2,0), (3,3,0); 12 h (2,2,0), (2,2,1), (3,2,1), (3,2,2), (4,4,1),
+// (4,4,2), (5,2,2), (5,2,3), (5,4,2), (5,4,3).
+enum { kF311, kF220, kF330, kF221, kF321, kF322, kF441, kF442, kF522, kF523, kF542, kF543, kNF };
+template <class S>
+void res_inclination(const S& ci, const S& si, S F[kNF]) {
+  const S c2 = ci * ci, s2 = si * si;
+  F[kF220] = 0.75 * (1.0 + ci) * (1.0 + ci);
+  F[kF311] = 0.9375 * s2 * (1.0 + 3.0 * ci) - 0.75 * (1.0 + ci);
+  F[kF330] = 1.875 * cube(1.0 + ci);
+  F[kF221] = 1.5 * s2;
+  F[kF321] = 1.875 * si * (1.0 - 2.0 * ci - 3.0 * c2);
+  F[kF322] = -1.875 * si * (1.0 + 2.0 * ci - 3.0 * c2);
+  F[kF441] = 35.0 * s2 * F[kF220];
+  F[kF442] = 39.375 * s2 * s2;
+  F[kF522] = 9.84375 * si * (s2 * (1.0 - 2.0 * ci - 5.0 * c2) + 0.33333333 * (-2.0 + 4.0 * ci + 6.0 * c2));
+  F[kF523] = si * (4.92187512 * s2 * (-2.0 - 4.0 * ci + 10.0 * c2) + 6.56250012 * (1.0 + 2.0 * ci - 3.0 * c2));
+  F[kF542] = 29.53125 * si * (2.0 - 8.0 * ci + c2 * (-12.0 + 8.0 * ci + 10.0 * c2));
+  F[kF543] = 29.53125 * si * (-2.0 - 8.0 * ci + c2 * (12.0 + 8.0 * ci - 10.0 * c2));
+}
+
+// Eccentricity functions G_lpq(e): 24 h as series in e (G310, G200, G300);
+// 12 h as the model's polynomial fits over e >= 0.5 (G201, G211, G310, G322,
+// G410, G422, G520, G532, G521, G533; q = -1 for G201).
+enum { kG310s, kG200, kG300, kG201, kG211, kG310, kG322, kG410, kG422, kG520, kG532, kG521, kG533, kNG };
+template <class S>
+void res_eccentricity(const S& e, S G[kNG]) {
+  const S e2 = e * e, e3 = e2 * e;
+  G[kG310s] = 1.0 + 2.0 * e2;
+  G[kG200] = 1.0 + e2 * (-2.5 + 0.8125 * e2);
+  G[kG300] = 1.0 + e2 * (-6.0 + 6.60937 * e2);
+  G[kG201] = -0.306 - (e - 0.64) * 0.440;
+  if (val(e) <= 0.65) {
+    G[kG211] = 3.616 - 13.2470 * e + 16.2900 * e2;
+    G[kG310] = -19.302 + 117.3900 * e - 228.4190 * e2 + 156.5910 * e3;
+    G[kG322] = -18.9068 + 109.7927 * e - 214.6334 * e2 + 146.5816 * e3;
+    G[kG410] = -41.122 + 242.6940 * e - 471.0940 * e2 + 313.9530 * e3;
+    G[kG422] = -146.407 + 841.8800 * e - 1629.014 * e2 + 1083.4350 * e3;
+    G[kG520] = -532.114 + 3017.977 * e - 5740.032 * e2 + 3708.2760 * e3;
+  } else {
+    G[kG211] = -72.099 + 331.819 * e - 508.738 * e2 + 266.724 * e3;
+    G[kG310] = -346.844 + 1582.851 * e - 2415.925 * e2 + 1246.113 * e3;
+    G[kG322] = -342.585 + 1554.908 * e - 2366.899 * e2 + 1215.972 * e3;
+    G[kG410] = -1052.797 + 4758.686 * e - 7193.992 * e2 + 3651.957 * e3;
+    G[kG422] = -3581.690 + 16178.110 * e - 24462.770 * e2 + 12422.520 * e3;
+    if (val(e) > 0.715)
+      G[kG520] = -5149.66 + 29936.92 * e - 54087.36 * e2 + 31324.56 * e3;
+    else
+      G[kG520] = 1464.74 - 4664.75 * e + 3763.64 * e2;
+  }
+  if (val(e) < 0.7) {
+    G[kG533] = -919.22770 + 4988.6100 * e - 9064.7700 * e2 + 5542.21 * e3;
+    G[kG521] = -822.71072 + 4568.6173 * e - 8491.4146 * e2 + 5337.524 * e3;
+    G[kG532] = -853.66600 + 4690.2500 * e - 8624.7700 * e2 + 5341.4 * e3;
+  } else {
+    G[kG533] = -37995.780 + 161616.52 * e - 229838.20 * e2 + 109377.94 * e3;
+    G[kG521] = -51752.104 + 218913.95 * e - 309468.16 * e2 + 146349.42 * e3;
+    G[kG532] = -40023.880 + 170470.89 * e - 242699.48 * e2 + 115605.82 * e3;
+  }
+}
+
+// IAU 1982 Greenwich mean sidereal time (Aoki et al. 1982) at a Julian date
+// taken as UT1, radians in [0, 2 pi): seconds of sidereal time as a cubic in
+// Julian centuries from J2000.0, the 12 h offset of that epoch included.
+double gmst_iau82(double day1900) {
+  const double T = (day1900 - 36525.0) / 36525.0;  // J2000.0 is day 36525 after JD 2415020.0
+  const double sec = 67310.54841 + (876600.0 * 3600.0 + 8640184.812866) * T + 0.093104 * T * T - 6.2e-6 * T * T * T;
+  double x = std::fmod(sec, 86400.0) * (kTwoPi / 86400.0);
+  if (x < 0.0) x += kTwoPi;
+  return x;
+}
+
+// One term's coefficient 3 n^2 (R/a)^l k J F G, from base = 3 n^2 (R/a)^2.
+template <class S>
+S res_coef(const S& base, const S& ra, const ResTerm& q, const S& FG) {
+  S coef = base * double(q.k) * q.J * FG;
+  for (int l = 2; l < q.l; ++l) coef = coef * ra;
+  return coef;
+}
+
+// I10 (resonant deep space): term coefficients 3 n^2 (R/a)^l k J F G, the
+// resonant mean longitude at epoch and its rate apart from the mean motion:
+// the secular rates of M, w and node (gravity and the bodies) minus the
+// Earth's rotation, taken m times.
+template <class S>
+void resonance_init(const Gravity& g, Sat<S>& c, double day) {
+  c.gsto = gmst_iau82(day);
+  if (!c.irez) return;
+  const S ra = sq(cbrt(c.n0pp / g.ke));  // R/a
+  const S base = 3.0 * c.n0pp * c.n0pp * ra * ra;
+  S F[kNF], G[kNG];
+  res_inclination(c.cosi, c.sini, F);
+  res_eccentricity(c.e0, G);
+  if (c.irez == 1) {
+    const S FG[3] = {F[kF311] * G[kG310s], F[kF220] * G[kG200], F[kF330] * G[kG300]};
+    for (int k = 0; k < 3; ++k) c.res[k] = res_coef(base, ra, kRes24[k], FG[k]);
+    c.xlamo = mod2pi(c.M0 + c.node0 + c.argp0 - c.gsto);
+    c.xfact = c.Mdot + (c.argpdot + c.nodedot) - kEarthRate + c.dMdt + c.dargpdt + c.dnodedt - c.n0pp;
+  } else {
+    const S FG[10] = {F[kF220] * G[kG201], F[kF221] * G[kG211], F[kF321] * G[kG310], F[kF322] * G[kG322],
+                      F[kF441] * G[kG410], F[kF442] * G[kG422], F[kF522] * G[kG520], F[kF523] * G[kG532],
+                      F[kF542] * G[kG521], F[kF543] * G[kG533]};
+    for (int k = 0; k < 10; ++k) c.res[k] = res_coef(base, ra, kRes12[k], FG[k]);
+    c.xlamo = mod2pi(c.M0 + 2.0 * c.node0 - 2.0 * c.gsto);
+    c.xfact = c.Mdot + c.dMdt + 2.0 * (c.nodedot + c.dnodedt - kEarthRate) - c.n0pp;
+  }
+}
+
+// Resonance rates at mean longitude xli and mean motion xni, atime minutes
+// after epoch (the perigee argument of the 12 h terms advanced by its
+// gravity rate): dn/dt, its time derivative along the resonant argument, and
+// d(lambda)/dt.
+template <class S>
+void res_rates(const Sat<S>& c, const S& xli, const S& xni, double atime, S* ndot, S* nddot, S* ldot) {
+  const int nt = c.irez == 1 ? 3 : 10;
+  const ResTerm* terms = c.irez == 1 ? kRes24 : kRes12;
+  const S w = c.argp0 + c.argpdot * atime;
+  S sn = S(0.0), cs = S(0.0);
+  for (int k = 0; k < nt; ++k) {
+    const ResTerm& q = terms[k];
+    const S arg = double(q.j) * w + double(q.k) * xli - q.phase;
+    sn = sn + c.res[k] * sin(arg);
+    cs = cs + double(q.k) * c.res[k] * cos(arg);
+  }
+  *ldot = xni + c.xfact;
+  *ndot = sn;
+  *nddot = cs * *ldot;
+}
+
+// P3r: integrate (lambda, n) from epoch to t in steps of 720 minutes toward t
+// while at least a whole step remains, then the Taylor polynomial over the
+// remainder.  Returns the time of the last step.
+template <class S>
+double res_integrate(const Sat<S>& c, double t, S* xl, S* nm) {
+  S xli = c.xlamo, xni = c.n0pp, ndot, nddot, ldot;
+  double atime = 0.0;
+  const double h = t > 0.0 ? kResStep : -kResStep;
+  if (!(std::fabs(t) <= kResReach)) {
+    *xl = *nm = S(std::numeric_limits<double>::quiet_NaN());
+    return 0.0;
+  }
+  for (;;) {
+    res_rates(c, xli, xni, atime, &ndot, &nddot, &ldot);
+    if (!(std::fabs(t - atime) >= kResStep)) break;
+    xli = xli + ldot * h + ndot * (0.5 * h * h);
+    xni = xni + ndot * h + nddot * (0.5 * h * h);
+    atime += h;
+  }
+  const double ft = t - atime;
+  *nm = xni + ndot * ft + nddot * (0.5 * ft * ft);
+  *xl = xli + ldot * ft + ndot * (0.5 * ft * ft);
+  return atime;
 }
 
 template <class S>
@@ -497,7 +709,15 @@ Sat<S> sgp4_init(const Gravity& g, const S el[kNElem], double epoch) {
     c.pe2[k] = c.pe3[k] = c.pi2[k] = c.pi3[k] = c.pl2[k] = c.pl3[k] = c.pl4[k] = c.pgh2[k] = c.pgh3[k] =
         c.pgh4[k] = c.ph2[k] = c.ph3[k] = S(0.0);
   // I9: deep space.  The epoch in days after 1900 January 0.5.
-  if (c.deep && !c.epoch_code) deep_init(c, (g_ref_jd - 2415020.0) + epoch);
+  // I10: resonance (after the secular rates it adds to).
+  c.irez = 0;
+  c.xlamo = c.xfact = S(0.0);
+  for (int k = 0; k < 10; ++k) c.res[k] = S(0.0);
+  if (c.deep && !c.epoch_code) {
+    const double day = (g_ref_jd - 2415020.0) + epoch;
+    deep_init(c, day);
+    resonance_init(g, c, day);
+  }
   return c;
 }
 
@@ -542,7 +762,6 @@ int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3],
   if (det) for (int k = 0; k < kD_COUNT; ++k) det[k] = nan;
   if (c.epoch_code) return fail(1);
   if (!(val(c.n0pp) > 0.0)) return fail(2);
-  if (c.deep && c.resonant) return fail(7);
 
   const double t = tsince;
   const double t2 = t * t;
@@ -578,8 +797,23 @@ int sgp4_point(const Gravity& g, const Sat<S>& c, double tsince, S r[3], S v[3],
     node = node + c.dnodedt * t;
     M = M + c.dMdt * t;
   }
+  // P3r (resonant deep space): the mean anomaly from the integrated resonant
+  // longitude and the Greenwich sidereal angle at t; the semi-major axis from
+  // the integrated mean motion.
+  S a0 = c.a0pp;
+  if (c.irez) {
+    S xl, nm;
+    res_integrate(c, t, &xl, &nm);
+    const double theta = mod2pi(c.gsto + t * kEarthRate);
+    if (c.irez == 1)
+      M = xl - node - argp + theta;
+    else
+      M = xl - 2.0 * node + 2.0 * theta;
+    if (!(val(nm) > 0.0)) return fail(2);
+    a0 = sq(cbrt(g.ke / nm));
+  }
   // P3: drag-decayed semi-major axis, mean motion and eccentricity.
-  S a = c.a0pp * A * A;
+  S a = a0 * A * A;
   S n = g.ke / (a * sqrt(a));
   S e = e_sec - Ed;
   if (det) det[kD_emargin] = std::min(val(e) + 0.001, 1.0 - val(e));
@@ -852,8 +1086,8 @@ int oracle_propagate_points(const double* grav, int64_t n, const double* elem, i
 
 int oracle_detail_count(void) { return kD_COUNT; }
 
-// Initialisation constants per satellite, [n][44] in this order.
-enum { kI_COUNT = 76 };
+// Initialisation constants per satellite, [n][kI_COUNT] in this order.
+enum { kI_COUNT = 90 };
 int oracle_init_count(void) { return kI_COUNT; }
 int oracle_init(const double* grav, int64_t n, const double* elem, double* rec) {
   Gravity g;
@@ -872,10 +1106,65 @@ int oracle_init(const double* grav, int64_t n, const double* elem, double* rec) 
         c.pe2[0], c.pe3[0], c.pi2[0], c.pi3[0], c.pl2[0], c.pl3[0], c.pl4[0], c.pgh2[0], c.pgh3[0], c.pgh4[0],
         c.ph2[0], c.ph3[0],
         c.pe2[1], c.pe3[1], c.pi2[1], c.pi3[1], c.pl2[1], c.pl3[1], c.pl4[1], c.pgh2[1], c.pgh3[1], c.pgh4[1],
-        c.ph2[1], c.ph3[1]};
+        c.ph2[1], c.ph3[1],
+        double(c.irez), c.xlamo, c.xfact, c.gsto,
+        c.res[0], c.res[1], c.res[2], c.res[3], c.res[4], c.res[5], c.res[6], c.res[7], c.res[8], c.res[9]};
+    static_assert(sizeof out == kI_COUNT * sizeof(double), "init export");
     std::memcpy(rec + i * kI_COUNT, out, sizeof out);
   }
   return 0;
+}
+
+// Resonance internals, for the pins.  Inclination and eccentricity functions
+// at (e, i): out[0..11] F in the order F311 F220 F330 F221 F321 F322 F441 F442
+// F522 F523 F542 F543, out[12..24] G in the order G310 (24 h series) G200 G300
+// G201 G211 G310 G322 G410 G422 G520 G532 G521 G533.
+void oracle_resonance_functions(double e, double inc, double* out) {
+  double F[kNF], G[kNG];
+  res_inclination(std::cos(inc), std::sin(inc), F);
+  res_eccentricity(e, G);
+  for (int k = 0; k < kNF; ++k) out[k] = F[k];
+  for (int k = 0; k < kNG; ++k) out[kNF + k] = G[k];
+}
+
+// Model constants: out[0] the Earth's rotation rate (rad/min), out[1] the
+// step (min), then per term (24 h: 3, then 12 h: 10) j, k, l, phase, J.
+int oracle_resonance_constants(double* out) {
+  out[0] = kEarthRate;
+  out[1] = kResStep;
+  int m = 2;
+  for (const ResTerm& q : kRes24) { out[m++] = q.j; out[m++] = q.k; out[m++] = q.l; out[m++] = q.phase; out[m++] = q.J; }
+  for (const ResTerm& q : kRes12) { out[m++] = q.j; out[m++] = q.k; out[m++] = q.l; out[m++] = q.phase; out[m++] = q.J; }
+  return m;
+}
+
+// Sidereal angle (rad) at a Julian date taken as UT1.
+double oracle_gmst(double jd) { return gmst_iau82(jd - 2415020.0); }
+
+// For one element set elem1[8] (the current reference date applies): the
+// rates (dn/dt, d2n/dt2, dlambda/dt) at (xli, xni, atime), and the integrated
+// (lambda, n, time of the last step) at t minutes after epoch.  Return the
+// resonance class (0 when the set is not resonant; nothing written).
+int oracle_resonance_rates(const double* grav, const double* elem1, double xli, double xni, double atime,
+                           double* out3) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  double el[kNElem];
+  for (int k = 0; k < kNElem; ++k) el[k] = elem1[k];
+  Sat<double> c = sgp4_init<double>(g, el, elem1[7]);
+  if (!c.irez) return 0;
+  res_rates(c, xli, xni, atime, &out3[0], &out3[1], &out3[2]);
+  return c.irez;
+}
+int oracle_resonance_integrate(const double* grav, const double* elem1, double t, double* out3) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  double el[kNElem];
+  for (int k = 0; k < kNElem; ++k) el[k] = elem1[k];
+  Sat<double> c = sgp4_init<double>(g, el, elem1[7]);
+  if (!c.irez) return 0;
+  out3[2] = res_integrate(c, t, &out3[0], &out3[1]);
+  return c.irez;
 }
 
 // Forward-mode Jacobian d(r, v)/d(n0, e0, i0, node0, argp0, M0, bstar) at

@@ -89,6 +89,35 @@ MUTANTS = [
      "S alf = sinip * sno + (ph * cno - pinc * cosip * sno);"),
     ("low-inclination longitude term", "(pl + pgh - pinc * node * sinip)", "(pl + pgh + pinc * node * sinip)"),
     ("24 h resonance band", "nv < 0.0052359877 && nv > 0.0034906585", "nv < 0.0052359877 && nv > 0.0044906585"),
+    # resonance: inclination and eccentricity functions, the 24 h harmonics,
+    # the 12 h arguments, the coefficients' k factor, epoch longitude and
+    # rate, the integrator and the sidereal time
+    ("F311 second term", "- 0.75 * (1.0 + ci);", "- 0.7 * (1.0 + ci);"),
+    ("F442 coefficient", "F[kF442] = 39.375 * s2 * s2;", "F[kF442] = 38.375 * s2 * s2;"),
+    ("F523 second coefficient", "6.56250012 * (1.0 + 2.0 * ci - 3.0 * c2)", "6.06250012 * (1.0 + 2.0 * ci - 3.0 * c2)"),
+    ("F543 sign", "F[kF543] = 29.53125 * si * (-2.0", "F[kF543] = -29.53125 * si * (-2.0"),
+    ("G300 quartic coefficient", "(-6.0 + 6.60937 * e2)", "(-6.0 + 5.60937 * e2)"),
+    ("G200 quadratic coefficient", "(-2.5 + 0.8125 * e2)", "(-2.0 + 0.8125 * e2)"),
+    ("G201 slope sign", "G[kG201] = -0.306 - (e - 0.64) * 0.440;", "G[kG201] = -0.306 + (e - 0.64) * 0.440;"),
+    ("G422 fit coefficient", "- 1629.014 * e2", "- 1529.014 * e2"),
+    ("G533 fit coefficient (e >= 0.7)", "+ 109377.94 * e3", "+ 109277.94 * e3"),
+    ("24 h (3,1) phase", "{0, 1, 3, 0.13130908, 2.1460748e-6}", "{0, 1, 3, 0.23130908, 2.1460748e-6}"),
+    ("24 h (2,2) magnitude", "{0, 2, 2, 2.0 * 2.8843198, 1.7891679e-6}", "{0, 2, 2, 2.0 * 2.8843198, 1.6891679e-6}"),
+    ("24 h (3,3) phase", "{0, 3, 3, 3.0 * 0.37448087, 2.2123015e-7}", "{0, 3, 3, 3.0 * 0.47448087, 2.2123015e-7}"),
+    ("12 h (3,2,2,2) perigee multiple", "{-1, 1, 3, 0.95240898", "{1, 1, 3, 0.95240898"),
+    ("12 h (4,4,2,2) longitude multiple", "{0, 2, 4, 1.8014998", "{0, 1, 4, 1.8014998"),
+    ("resonant coefficient k factor", "S coef = base * double(q.k) * q.J * FG;", "S coef = base * q.J * FG;"),
+    ("24 h epoch longitude", "c.xlamo = mod2pi(c.M0 + c.node0 + c.argp0 - c.gsto);",
+     "c.xlamo = mod2pi(c.M0 + c.node0 + c.argp0 + c.gsto);"),
+    ("24 h longitude rate drops the bodies' M rate", "- kEarthRate + c.dMdt + c.dargpdt", "- kEarthRate + c.dargpdt"),
+    ("12 h longitude rate", "2.0 * (c.nodedot + c.dnodedt - kEarthRate)", "2.0 * (c.nodedot - kEarthRate)"),
+    ("integrator step's second-order term", "xni = xni + ndot * h + nddot * (0.5 * h * h);",
+     "xni = xni + ndot * h + nddot * (h * h);"),
+    ("integrator remainder's second-order term", "*xl = xli + ldot * ft + ndot * (0.5 * ft * ft);",
+     "*xl = xli + ldot * ft + ndot * (0.4 * ft * ft);"),
+    ("12 h perigee of the rates", "const S w = c.argp0 + c.argpdot * atime;", "const S w = c.argp0;"),
+    ("sidereal time rate", "(876600.0 * 3600.0 + 8640184.812866) * T", "(876600.0 * 3600.0 + 8640194.812866) * T"),
+    ("resonant mean anomaly, 12 h", "M = xl - 2.0 * node + 2.0 * theta;", "M = xl - 2.0 * node + theta;"),
 ]
 
 
@@ -104,6 +133,7 @@ def _run(mutant, workdir):
     env = dict(os.environ, SGP4_ORACLE_LIB=lib)
     p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_deep.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_resonance.py"),
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, p.returncode

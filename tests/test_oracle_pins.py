@@ -818,17 +818,16 @@ def _one(n0=0.065, e0=1e-3, inc=0.9, node=0.1, argp=0.2, mo=0.3, bstar=1e-4, epo
 
 def test_error_codes_crafted():
     t = np.linspace(-1000.0, 5000.0, 13)
-    # the 24 h (synchronous) and 12 h (e >= 0.5) resonant deep-space classes are
-    # flagged, not propagated
-    for el, code in [(_one(e0=1.2), 1), (_one(e0=-0.1), 1), (_one(n0=-0.06), 2), (_one(n0=0.0), 2),
-                     (_one(n0=2 * math.pi / 1436.0, e0=2e-4, bstar=0.0), 7),
-                     (_one(n0=2 * math.pi / 718.0, e0=0.7, bstar=0.0), 7)]:
+    for el, code in [(_one(e0=1.2), 1), (_one(e0=-0.1), 1), (_one(n0=-0.06), 2), (_one(n0=0.0), 2)]:
         r, v, err = oracle.propagate(el, t)
         assert np.all(err == code)
         assert np.all(np.isnan(r)) and np.all(np.isnan(v))
-    # a non-resonant deep-space set (300-minute period) is propagated
-    r, v, err = oracle.propagate(_one(n0=2 * math.pi / 300.0, bstar=0.0), t)
-    assert np.all(err == 0) and np.all(np.isfinite(r))
+    # deep-space sets, the 24 h (synchronous) and 12 h (e >= 0.5) resonant
+    # classes and a non-resonant one (300-minute period), are propagated
+    for el in (_one(n0=2 * math.pi / 1436.0, e0=2e-4, bstar=0.0), _one(n0=2 * math.pi / 718.0, e0=0.7, bstar=0.0),
+               _one(n0=2 * math.pi / 300.0, bstar=0.0)):
+        r, v, err = oracle.propagate(el, t)
+        assert np.all(err == 0) and np.all(np.isfinite(r))
     # just under the 225-minute period threshold (on n0'') stays near-Earth
     ci = oracle.init_constants(_one(n0=2 * math.pi / 224.0))
     assert ci["deep"][0] == 0.0
