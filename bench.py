@@ -577,8 +577,9 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_vjp and not args.only:
-        # Deep-space catalogue (4,096 satellites x 1,008 times over 7 days; the
-        # resonant 15% are flagged, the rest take the lunar-solar terms).
+        # Deep-space catalogue (4,096 satellites x 1,008 times over 7 days; every
+        # set takes the lunar-solar terms, the 15% in the resonant classes the
+        # resonance integrator as well).
         c5 = synth.config5()
         e5, t5 = torch.from_numpy(c5.elem).to(dev), torch.from_numpy(c5.t).to(dev)
         P5 = c5.n * c5.T

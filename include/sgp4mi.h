@@ -8,8 +8,10 @@
  * Validity problems do not abort the batch: each point carries an error code
  * (section 2.2, "Control Flow").  Element sets with periods of 225 minutes or
  * more take the deep-space model's lunar and solar terms (section 6 names deep
- * space as the variant the paper leaves out); its 12 h and 24 h resonant
- * classes are flagged, not propagated.
+ * space as the variant the paper leaves out), and those of its 12 h and 24 h
+ * resonant classes the tesseral resonance, integrated in mean motion and
+ * resonant longitude in 720-minute steps from epoch (up to 10 years from
+ * epoch; beyond, code 2).
  *
  * Conventions for every call
  *   - Pointers are DEVICE pointers owned by the caller unless marked "host".
@@ -35,8 +37,9 @@
  *     [0, 1) at epoch); 2 recovered mean motion not positive; 3 deep space:
  *     the lunar-solar terms move the eccentricity outside [0, 1]; 4
  *     semi-latus rectum negative; 6 decayed (radius below one earth radius;
- *     the state is still written); 7 resonant deep-space element set (24 h,
- *     or 12 h with e >= 0.5), not propagated; 8 ragged point that the
+ *     the state is still written); 7 not propagated by this call (a
+ *     deep-space satellite met by a ragged plan made for a record without
+ *     one, see sgp4_plan_create); 8 ragged point that the
  *     offsets place in no satellite's list (malformed offsets given to
  *     sgp4_propagate_ragged without a plan).  Codes 1, 2, 3, 4, 7 and 8 write
  *     NaN to r and v.
@@ -87,7 +90,7 @@ size_t sgp4_consts_bytes(int64_t n);
  * written.  sat_flags: device uint8 [n] or NULL; written with bit0 deep space
  * (period of 225 min or more), bit1 simplified drag (perigee below 220 km,
  * and every deep-space set), bit2 invalid elements, bit3 resonant deep space
- * (not propagated, code 7).  0 <= n < 2^31.  The deep-space terms need the
+ * (the 24 h class, or the 12 h class with e >= 0.5).  0 <= n < 2^31.  The deep-space terms need the
  * absolute epoch: sgp4_init takes the epoch row as days after J2000.0
  * (JD 2451545.0, the default reference of sgp4_text_parse). */
 int sgp4_init(const double* grav, int64_t n, const double* elem, void* consts, uint8_t* sat_flags, void* stream);

@@ -19,10 +19,10 @@ namespace sgp4mi {
 //       bytes 480..483  uint32 info: bits 0-7 satellite code, bit 8 isimp,
 //                       bit 9 deep space
 //       (entries ordered so that the FP32-mixed path touches two lines)
-//   [n deep-space slots of kDeepBytes = 256 bytes, one per satellite]: the
+//   [n deep-space slots of kDeepBytes = 512 bytes, one per satellite]: the
 //       lunar-solar secular rates, the long-period coefficients of the Sun and
-//       the Moon and their mean anomalies at epoch (written and read only for
-//       satellites with the deep-space bit)
+//       the Moon and their mean anomalies at epoch, the tesseral resonance
+//       terms (written and read only for satellites with the deep-space bit)
 // One contiguous slot per satellite: a wavefront working on one satellite
 // fetches its constants with a few wide loads from one base address.
 // Order: the FP32-mixed near-Earth path reads the double copies of the first
@@ -76,14 +76,25 @@ constexpr uint32_t kInfoDeep = 0x200u;
 // Moon's mean anomalies at epoch, and per body (Sun, then Moon) the
 // coefficients of the long-period terms of e, i, M, argp + cos i node and
 // sin i node: the twice-anomaly pairs (x2, x3) and the body-eccentricity
-// terms (l4, gh4).
+// terms (l4, gh4).  Then the tesseral resonance: its class (0 none, 1 the
+// 24 h class, 2 the 12 h class), the resonant mean longitude at epoch, its
+// rate apart from the integrated mean motion, the Greenwich sidereal angle
+// at epoch, and per term (24 h: 3, 12 h: 10) the pair (c cos phase,
+// c sin phase) of its coefficient c and phase.
 enum DeepRec : int {
   kDeDt, kDiDt, kDMDt, kDNodeDt, kDArgpDt, kDMb0, kDMb1,
   kDPer0 = 7,  // per body k: kDPer0 + 12 k + one of the offsets below
-  kNDeep = kDPer0 + 24
+  kDRes = kDPer0 + 24, kDXlamo, kDXfact, kDGsto,
+  kDRc0,  // term m: kDRc0 + 2 m (cos part), kDRc0 + 2 m + 1 (sin part)
+  kNDeep = kDRc0 + 20
 };
 enum DeepPer : int { kPe2, kPe3, kPi2, kPi3, kPl2, kPl3, kPl4, kPgh2, kPgh3, kPgh4, kPh2, kPh3, kNPer };
-constexpr int kDeepBytes = 256;
+// The Earth's rotation rate (rad/min) of the resonance; the resonance
+// integrator's step and its reach from epoch (10 Julian years), in minutes.
+constexpr double kEarthRot = 4.37526908801129966e-3;
+constexpr double kResStepMin = 720.0;
+constexpr double kResMaxMin = 5259600.0;
+constexpr int kDeepBytes = 512;
 struct alignas(16) DeepSlot {
   double d[kDeepBytes / 8];
 };

@@ -86,13 +86,13 @@ __device__ __forceinline__ uint32_t init_sat(const FusedArgs& a, const Grav& g, 
   bool isimp, dsp;
   init_record<double>(gi, el, rec, &code, &isimp, &dsp);
   rec[kEpochMin] = 1440.0 * epoch;
-  if (dsp && code == 0) init_deep(el, rec[kN0pp], a.ref_day + epoch, deep);
+  if (dsp && code == 0) init_deep(el, rec, g.ke, a.ref_day + epoch, deep);
   if (write_flags && a.user_flags) {
     uint8_t f = 0;
     if (dsp) f |= 1;
     if (isimp) f |= 2;
     if (code == 1 || code == 2) f |= 4;
-    if (code == 7) f |= 8;
+    if (dsp && code == 0 && deep[kDRes] != 0.0) f |= 8;
     a.user_flags[i] = f;
   }
   return code | (isimp ? kInfoIsimp : 0u) | (dsp ? kInfoDeep : 0u);

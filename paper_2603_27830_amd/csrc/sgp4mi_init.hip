@@ -65,9 +65,11 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     uint32_t code;
     bool isimp, deep;
     init_record<double>(gi, el, rec, &code, &isimp, &deep);
+    bool resonant = false;
     if (deep && code == 0) {
       double d[kNDeep];
-      init_deep(el, rec[kN0pp], a.ref_day + epoch, d);
+      init_deep(el, rec, ke, a.ref_day + epoch, d);
+      resonant = d[kDRes] != 0.0;
 #pragma unroll
       for (int k = 0; k < kNDeep; ++k) a.deep[i].d[k] = d[k];
     }
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__(64) init_kernel(InitArgs a) {
     if (a.user_flags) {
       uint8_t f = 0;
       if (deep) f |= 1;
-      if (code == 7) f |= 8;
+      if (resonant) f |= 8;
       if (isimp) f |= 2;
       if (code == 1 || code == 2) f |= 4;
       a.user_flags[i] = f;

@@ -83,16 +83,10 @@ struct GravIn {
   double radius, j2, j4, ke, j3oj2;
 };
 
-// Whether a deep-space orbit lies in a resonant class (24 h, or 12 h with
-// e >= 0.5), which the library flags instead of propagating.
-__device__ inline bool deep_resonant(double n, double e) {
-  return (n < 0.0052359877 && n > 0.0034906585) || (n >= 8.26e-3 && n <= 9.24e-3 && e >= 0.5);
-}
-
 // el: n0 (Kozai, rad/min), e0, i0, node0, argp0, M0, bstar.  Writes the
 // record entries (all but kEpochMin), the satellite code and the flags
 // (simplified drag; deep space: period of 225 min or more, which also takes
-// the simplified drag terms; resonant deep-space orbits get code 7).
+// the simplified drag terms).
 template <class S>
 __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S rec[kNRec], uint32_t* code_out,
                                             bool* isimp_out, bool* deep_out) {
@@ -146,10 +140,7 @@ __device__ __forceinline__ void init_record(const GravIn& g, const S el[7], S re
   bool deep = false;
   if (!(value(ecco) >= 0.0 && value(ecco) < 1.0)) code = 1;
   else if (!(value(nbar) > 0.0)) code = 2;
-  else if (kTwoPi / value(nbar) >= 225.0) {
-    deep = true;
-    if (deep_resonant(value(nbar), value(ecco))) code = 7;
-  }
+  else if (kTwoPi / value(nbar) >= 225.0) deep = true;
   const bool isimp = deep || value(perigee_er) < 1.0 + 220.0 / R;
 
   // Power-law drag coefficients.
@@ -314,9 +305,138 @@ __device__ inline void deep_body(double cg, double sg, double cib, double sib, d
   sec[4] = -b.n * s2 * (z21 + z23);
 }
 
-// el: epoch elements as for init_record; n: recovered mean motion; day: days
-// after JD 2415020.0.  Writes the kNDeep entries of a deep-space slot.
-__device__ inline void init_deep(const double el[7], double n, double day, double* d) {
+// ------------------------------------------------------------ resonance --
+// Tesseral resonance (the published model's 24 h and 12 h classes): an
+// orbit commensurate with the Earth's rotation feels the tesseral harmonics
+// J_lm secularly through the arguments psi = j w + k lambda - phase, lambda
+// the resonant mean longitude (24 h: M + node + w - theta, j = 0, k = m;
+// 12 h: M + 2 node - 2 theta, j = l - 2p, k = m / 2); per term
+// dn/dt = c sin psi with c = 3 n^2 (R/a)^l k J_lm F_lmp(i) G_lpq(e).
+
+// Greenwich mean sidereal time (IAU 1982) of a Julian date taken as UT1,
+// given as days after JD 2415020.0; radians in [0, 2 pi).
+__device__ inline double gmst1982(double day) {
+  const double T = (day - 36525.0) * (1.0 / 36525.0);
+  const double sec = 67310.54841 + T * ((876600.0 * 3600.0 + 8640184.812866) + T * (0.093104 - 6.2e-6 * T));
+  const double x = fmod(sec, 86400.0) * (kTwoPi / 86400.0);
+  return x < 0.0 ? x + kTwoPi : x;
+}
+
+// Per-satellite resonance terms.  rec: the satellite's record (mean motion,
+// inclination functions, secular rates); d: its deep-space slot with the
+// lunar-solar rates already written; M0, node0, argp0, e0 from el.
+__device__ inline void init_resonance(const double el[7], const double* rec, double ke, double day, double* d) {
+  const double n = rec[kN0pp], e = el[1];
+  const int cls = (n < 0.0052359877 && n > 0.0034906585) ? 1 : (n >= 8.26e-3 && n <= 9.24e-3 && e >= 0.5) ? 2 : 0;
+  const double gsto = gmst1982(day);
+  d[kDRes] = double(cls);
+  d[kDGsto] = gsto;
+  d[kDXlamo] = 0.0;
+  d[kDXfact] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 20; ++m) d[kDRc0 + m] = 0.0;
+  if (cls == 0) return;
+  const double ci = rec[kCosi], si = rec[kSini], c2 = ci * ci, s2 = si * si;
+  const double ra = cbrt(n / ke) * cbrt(n / ke);  // R / a
+  const double n2 = 3.0 * n * n * ra * ra;         // 3 n^2 (R/a)^2
+  const double e2 = e * e, e3 = e2 * e;
+  const double f220 = 0.75 * (1.0 + ci) * (1.0 + ci);
+  // (k J F G (R/a)^(l-2), phase) per term
+  double cf[10], ph[10];
+  int nt;
+  if (cls == 1) {
+    // (l, m, p, q) = (3,1,1,0), (2,2,0,0), (3,3,0,0): F311 G310, F220 G200, F330 G300
+    const double f311 = 0.9375 * s2 * (1.0 + 3.0 * ci) - 0.75 * (1.0 + ci);
+    const double f330 = 1.875 * (1.0 + ci) * (1.0 + ci) * (1.0 + ci);
+    const double g310 = 1.0 + 2.0 * e2;
+    const double g200 = 1.0 + e2 * (-2.5 + 0.8125 * e2);
+    const double g300 = 1.0 + e2 * (-6.0 + 6.60937 * e2);
+    cf[0] = 2.1460748e-6 * f311 * g310 * ra;
+    cf[1] = 2.0 * 1.7891679e-6 * f220 * g200;
+    cf[2] = 3.0 * 2.2123015e-7 * f330 * g300 * ra;
+    ph[0] = 0.13130908;
+    ph[1] = 2.0 * 2.8843198;
+    ph[2] = 3.0 * 0.37448087;
+    nt = 3;
+    d[kDXlamo] = el[5] + el[3] + el[4] - gsto;
+    d[kDXfact] = rec[kMdot] + (rec[kArgpdot] + rec[kNodedot]) - kEarthRot + d[kDMDt] + d[kDArgpDt] + d[kDNodeDt] - n;
+  } else {
+    // Kaula's inclination functions of the ten terms
+    const double f221 = 1.5 * s2;
+    const double f321 = 1.875 * si * (1.0 - 2.0 * ci - 3.0 * c2);
+    const double f322 = -1.875 * si * (1.0 + 2.0 * ci - 3.0 * c2);
+    const double f441 = 35.0 * s2 * f220;
+    const double f442 = 39.375 * s2 * s2;
+    const double f522 = 9.84375 * si * (s2 * (1.0 - 2.0 * ci - 5.0 * c2) + 0.33333333 * (-2.0 + 4.0 * ci + 6.0 * c2));
+    const double f523 = si * (4.92187512 * s2 * (-2.0 - 4.0 * ci + 10.0 * c2) + 6.56250012 * (1.0 + 2.0 * ci - 3.0 * c2));
+    const double f542 = 29.53125 * si * (2.0 - 8.0 * ci + c2 * (-12.0 + 8.0 * ci + 10.0 * c2));
+    const double f543 = 29.53125 * si * (-2.0 - 8.0 * ci + c2 * (12.0 + 8.0 * ci - 10.0 * c2));
+    // the model's fits of the eccentricity functions over e >= 0.5
+    const double g201 = -0.306 - (e - 0.64) * 0.440;
+    double g211, g310, g322, g410, g422, g520, g533, g521, g532;
+    if (e <= 0.65) {
+      g211 = 3.616 - 13.2470 * e + 16.2900 * e2;
+      g310 = -19.302 + 117.3900 * e - 228.4190 * e2 + 156.5910 * e3;
+      g322 = -18.9068 + 109.7927 * e - 214.6334 * e2 + 146.5816 * e3;
+      g410 = -41.122 + 242.6940 * e - 471.0940 * e2 + 313.9530 * e3;
+      g422 = -146.407 + 841.8800 * e - 1629.014 * e2 + 1083.4350 * e3;
+      g520 = -532.114 + 3017.977 * e - 5740.032 * e2 + 3708.2760 * e3;
+    } else {
+      g211 = -72.099 + 331.819 * e - 508.738 * e2 + 266.724 * e3;
+      g310 = -346.844 + 1582.851 * e - 2415.925 * e2 + 1246.113 * e3;
+      g322 = -342.585 + 1554.908 * e - 2366.899 * e2 + 1215.972 * e3;
+      g410 = -1052.797 + 4758.686 * e - 7193.992 * e2 + 3651.957 * e3;
+      g422 = -3581.690 + 16178.110 * e - 24462.770 * e2 + 12422.520 * e3;
+      g520 = e > 0.715 ? -5149.66 + 29936.92 * e - 54087.36 * e2 + 31324.56 * e3
+                       : 1464.74 - 4664.75 * e + 3763.64 * e2;
+    }
+    if (e < 0.7) {
+      g533 = -919.22770 + 4988.6100 * e - 9064.7700 * e2 + 5542.21 * e3;
+      g521 = -822.71072 + 4568.6173 * e - 8491.4146 * e2 + 5337.524 * e3;
+      g532 = -853.66600 + 4690.2500 * e - 8624.7700 * e2 + 5341.4 * e3;
+    } else {
+      g533 = -37995.780 + 161616.52 * e - 229838.20 * e2 + 109377.94 * e3;
+      g521 = -51752.104 + 218913.95 * e - 309468.16 * e2 + 146349.42 * e3;
+      g532 = -40023.880 + 170470.89 * e - 242699.48 * e2 + 115605.82 * e3;
+    }
+    // (l m p q) = 2201 2211 3210 3222 4410 4422 5220 5232 5421 5433: J_lm,
+    // phase m lambda_lm, k (1 or 2) and (R/a)^(l-2)
+    const double ra2 = ra * ra, ra3 = ra2 * ra;
+    cf[0] = 1.7891679e-6 * f220 * g201;
+    cf[1] = 1.7891679e-6 * f221 * g211;
+    cf[2] = 3.7393792e-7 * f321 * g310 * ra;
+    cf[3] = 3.7393792e-7 * f322 * g322 * ra;
+    cf[4] = 2.0 * 7.3636953e-9 * f441 * g410 * ra2;
+    cf[5] = 2.0 * 7.3636953e-9 * f442 * g422 * ra2;
+    cf[6] = 1.1428639e-7 * f522 * g520 * ra3;
+    cf[7] = 1.1428639e-7 * f523 * g532 * ra3;
+    cf[8] = 2.0 * 2.1765803e-9 * f542 * g521 * ra3;
+    cf[9] = 2.0 * 2.1765803e-9 * f543 * g533 * ra3;
+    ph[0] = ph[1] = 5.7686396;
+    ph[2] = ph[3] = 0.95240898;
+    ph[4] = ph[5] = 1.8014998;
+    ph[6] = ph[7] = 1.0508330;
+    ph[8] = ph[9] = 4.4108898;
+    nt = 10;
+    d[kDXlamo] = el[5] + 2.0 * el[3] - 2.0 * gsto;
+    d[kDXfact] = rec[kMdot] + d[kDMDt] + 2.0 * (rec[kNodedot] + d[kDNodeDt] - kEarthRot) - n;
+  }
+  d[kDXlamo] = d[kDXlamo] - kTwoPi * floor(d[kDXlamo] * kInvTwoPi);
+  for (int m = 0; m < nt; ++m) {
+    double sp, cp;
+    sincos_rr(ph[m], &sp, &cp);
+    const double c = n2 * cf[m];
+    d[kDRc0 + 2 * m] = c * cp;
+    d[kDRc0 + 2 * m + 1] = c * sp;
+  }
+}
+
+// el: epoch elements as for init_record; rec: the satellite's record (its
+// recovered mean motion, inclination functions and secular rates); ke: the
+// gravity's ke; day: days after JD 2415020.0.  Writes the kNDeep entries of a
+// deep-space slot.
+__device__ inline void init_deep(const double el[7], const double* rec, double ke, double day, double* d) {
+  const double n = rec[kN0pp];
   const double e = el[1], inc = el[2];
   double si, ci, sw, cw, snd, cnd;
   sincos_rr(inc, &si, &ci);
@@ -355,6 +475,7 @@ __device__ inline void init_deep(const double el[7], double n, double day, doubl
   const double mm = 4.7199672 + 0.22997150 * day - perigee_l;
   d[kDMb0] = ms - kTwoPi * floor(ms * kInvTwoPi);
   d[kDMb1] = mm - kTwoPi * floor(mm * kInvTwoPi);
+  init_resonance(el, rec, ke, day, d);
 }
 
 }  // namespace sgp4mi

@@ -380,9 +380,82 @@ __device__ __forceinline__ uint32_t sgp4_tail(const Grav& g, TP a, TP e, TS M, T
 }
 
 
-// Deep space (period of 225 min or more, non-resonant): the near-Earth
-// secular terms with the simplified drag, the lunar-solar secular rates, then
-// the Sun's and the Moon's long-period terms on the mean elements (each body's
+// Tesseral resonance of the 24 h and 12 h classes: the mean motion and the
+// resonant mean longitude integrated from epoch in steps of 720 minutes
+// toward t while a whole step remains (second-order Taylor steps), then the
+// Taylor polynomial over the remainder; double precision in every path.
+// Rates at (lambda, n, w): dn/dt = sum of a sin A - b cos A over the terms,
+// A = j w + k lambda and (a, b) the term's coefficient times the cosine and
+// sine of its phase; d2n/dt2 = dlambda/dt times the sum of k (a cos A +
+// b sin A); dlambda/dt = n + the rest of the argument's secular rate.
+__device__ __forceinline__ void res_rates(bool sync24, const double* d, double xli, double w, double xni,
+                                          double* ndot, double* nddot, double* ldot) {
+  const double* r = d + kDRc0;
+  double s1, c1;
+  sincos_rr(xli, &s1, &c1);
+  const double s2 = 2.0 * s1 * c1, c2 = 1.0 - 2.0 * s1 * s1;
+  double sn, cs;
+  if (sync24) {
+    // 24 h: A = lambda, 2 lambda, 3 lambda
+    const double s3 = s1 * (3.0 - 4.0 * s1 * s1), c3 = c1 * (4.0 * c1 * c1 - 3.0);
+    sn = (r[0] * s1 - r[1] * c1) + (r[2] * s2 - r[3] * c2) + (r[4] * s3 - r[5] * c3);
+    cs = (r[0] * c1 + r[1] * s1) + 2.0 * (r[2] * c2 + r[3] * s2) + 3.0 * (r[4] * c3 + r[5] * s3);
+  } else {
+    // 12 h: (j, k) = (2,1) (0,1) (1,1) (-1,1) (2,2) (0,2) (1,1) (-1,1) (1,2)
+    // (-1,2); the third and seventh terms, and the fourth and eighth, share
+    // their angle
+    double sw, cw;
+    sincos_rr(w, &sw, &cw);
+    const double sw2 = 2.0 * sw * cw, cw2 = 1.0 - 2.0 * sw * sw;
+    double s1x = 0.0, c1x = 0.0, s2x = 0.0, c2x = 0.0;  // k = 1 and k = 2 sums
+    auto term = [&](double a, double b, double sA, double cA, double* sk, double* ck) {
+      *sk += a * sA - b * cA;
+      *ck += a * cA + b * sA;
+    };
+    term(r[0], r[1], sw2 * c1 + cw2 * s1, cw2 * c1 - sw2 * s1, &s1x, &c1x);
+    term(r[2], r[3], s1, c1, &s1x, &c1x);
+    term(r[4] + r[12], r[5] + r[13], sw * c1 + cw * s1, cw * c1 - sw * s1, &s1x, &c1x);
+    term(r[6] + r[14], r[7] + r[15], s1 * cw - c1 * sw, c1 * cw + s1 * sw, &s1x, &c1x);
+    term(r[8], r[9], sw2 * c2 + cw2 * s2, cw2 * c2 - sw2 * s2, &s2x, &c2x);
+    term(r[10], r[11], s2, c2, &s2x, &c2x);
+    term(r[16], r[17], sw * c2 + cw * s2, cw * c2 - sw * s2, &s2x, &c2x);
+    term(r[18], r[19], s2 * cw - c2 * sw, c2 * cw + s2 * sw, &s2x, &c2x);
+    sn = s1x + s2x;
+    cs = c1x + 2.0 * c2x;
+  }
+  *ldot = xni + d[kDXfact];
+  *ndot = sn;
+  *nddot = cs * *ldot;
+}
+
+// Integrated (lambda, n) at t minutes after epoch; NaN beyond 10 years from
+// epoch or for t not finite (every lane's loop is bounded by that reach).
+__device__ __forceinline__ void res_integrate(bool sync24, const double* d, double t, double n0, double argp0,
+                                              double argpdot, double* xl, double* nm) {
+  if (!(fabs(t) <= kResMaxMin)) {
+    *xl = *nm = __builtin_nan("");
+    return;
+  }
+  double xli = d[kDXlamo], xni = n0, atime = 0.0, ndot, nddot, ldot;
+  const double h = t > 0.0 ? kResStepMin : -kResStepMin;
+  const double hh = 0.5 * h * h;
+  for (;;) {
+    res_rates(sync24, d, xli, argp0 + argpdot * atime, xni, &ndot, &nddot, &ldot);
+    if (!(fabs(t - atime) >= kResStepMin)) break;
+    xli = xli + ldot * h + ndot * hh;
+    xni = xni + ndot * h + nddot * hh;
+    atime += h;
+  }
+  const double ft = t - atime;
+  *nm = xni + ndot * ft + nddot * (0.5 * ft * ft);
+  *xl = xli + ldot * ft + ndot * (0.5 * ft * ft);
+}
+
+// Deep space (period of 225 min or more): the near-Earth
+// secular terms with the simplified drag, the lunar-solar secular rates, for
+// the resonant classes the integrated mean motion and the mean anomaly from
+// the resonant longitude, then the Sun's and the Moon's long-period terms on
+// the mean elements (each body's
 // mean anomaly advanced by its mean motion, its true anomaly to first order in
 // its eccentricity); below 0.2 rad of perturbed inclination the node and
 // inclination changes are applied to (sin i sin node, sin i cos node) and the
@@ -394,7 +467,7 @@ template <class TS, class TP>
 __device__ __forceinline__ uint32_t deep_point(const SatC<TS, TP>& c, const Grav& g, double t_abs,
                                             PointState<TP>& out) {
   out.ok = false;
-  const uint32_t scode = c.info & kInfoCodeMask;  // codes 1, 2 at epoch; 7: resonant
+  const uint32_t scode = c.info & kInfoCodeMask;  // codes 1, 2 at epoch
   if (scode) return scode;
   const double* d = c.deep;
   const TS t = TS(t_abs - c.epoch_min);
@@ -404,7 +477,25 @@ __device__ __forceinline__ uint32_t deep_point(const SatC<TS, TP>& c, const Grav
   TS node = lin(c.node0, c.nodedot, t) + c.nodecf * t2 + TS(d[kDNodeDt]) * t;
   const TS incl = TS(c.i0) + TS(d[kDiDt]) * t;
   const TS A = TS(1) - c.C1 * t;
-  const TS a_s = c.a0pp * A * A;
+  TS a0 = c.a0pp;
+  const double rcls = d[kDRes];
+  if (rcls != 0.0) {
+    // resonance: M from the resonant longitude and the sidereal angle at t,
+    // a from the integrated mean motion (code 2 if it is not positive)
+    const double td = t_abs - c.epoch_min;
+    double xl, nm;
+    res_integrate(rcls == 1.0, d, td, double(c.n0pp), double(c.argp0), double(c.argpdot), &xl, &nm);
+    const double th = d[kDGsto] + td * kEarthRot;
+    const double theta = th - kTwoPi * floor(th * kInvTwoPi);
+    if (rcls == 1.0)
+      M = TS(xl) - node - argp + TS(theta);
+    else
+      M = TS(xl) - TS(2) * node + TS(2) * TS(theta);
+    if (!(nm > 0.0)) return 2;
+    const double cr = cbrt(g.ke / nm);
+    a0 = TS(cr * cr);
+  }
+  const TS a_s = a0 * A * A;
   TS e = c.e0 + TS(d[kDeDt]) * t - c.bC4 * t;
   if (!(e >= TS(-0.001) && e < TS(1))) return 1;
   e = vmax(e, TS(1.0e-6));
@@ -477,7 +568,7 @@ __device__ __forceinline__ uint32_t deep_point(const SatC<TS, TP>& c, const Grav
   return sgp4_tail<TS, TP>(g, TP(a_s), TP(e), M, argp, node, q, out);
 }
 
-// Returns the point's code (0, 1, 2, 3, 4, 6 or 7).  r and v are written, and ok
+// Returns the point's code (0, 1, 2, 3, 4 or 6).  r and v are written, and ok
 // set, for codes 0 and 6 only.
 //
 // Secular part: sin M from sin/cos of the drag-free M by a small rotation

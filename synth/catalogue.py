@@ -224,8 +224,8 @@ DEEP_CLASSES = (
     (0.10, 25510.0, (0.0, 0.01), (64.0, 65.6)),      # GLONASS-like
     (0.20, 24400.0, (0.70, 0.72), (0.5, 28.5)),      # transfer orbits, perigee 450-1050 km
     (0.15, 12500.0, (0.0, 0.3), (10.0, 120.0)),      # 232-min and longer periods
-    (0.10, 42164.0, (0.0, 0.001), (0.0, 3.0)),       # near-geosynchronous: resonant, code 7
-    (0.05, 26600.0, (0.68, 0.74), (62.0, 64.0)),     # Molniya-type: resonant, code 7
+    (0.10, 42164.0, (0.0, 0.001), (0.0, 3.0)),       # near-geosynchronous: 24 h resonance
+    (0.05, 26600.0, (0.68, 0.74), (62.0, 64.0)),     # Molniya-type: 12 h resonance
 )
 
 

@@ -1,6 +1,7 @@
 """GPU parity of the deep-space path (periods of 225 min or more: the Sun's
-and the Moon's secular and long-period terms; resonant classes flagged) against
-the CPU oracle, element by element.
+and the Moon's secular and long-period terms; for the 12 h and 24 h resonant
+classes the tesseral resonance integrator) against the CPU oracle, element by
+element.
 
 Bars: FP64 |dr| <= 1e-6 km and |dv| <= 1e-9 km/s with codes bit-exact (the
 hot path's FP64 bar); FP32-mixed within 10 m and 1e-2 m/s times (|r| / 7,000
@@ -85,11 +86,14 @@ def test_deep_catalogue_dense_fp64_and_mixed():
     ro, vo, eo = oracle_dense(cat.elem, cat.t)
     kinds = {int(k): int((eo == k).sum()) for k in np.unique(eo)}
     say(f"  oracle codes {kinds}")
-    assert 0 in kinds and 7 in kinds
+    assert 0 in kinds and 7 not in kinds
+    with oracle.reference_jd(REF):
+        irez = oracle.init_constants(cat.elem)["irez"]
+    assert (irez == 1).sum() > 100 and (irez == 2).sum() > 100
     rec = sg.init(dev(cat.elem), ref_jd=REF)
     flags, = host(rec.flags)
     assert np.all(flags & 1)                        # every set is deep space
-    assert np.array_equal((flags & 8) != 0, np.all(eo == 7, axis=1))
+    assert np.array_equal((flags & 8) != 0, irez != 0)
     dt = dev(cat.t)
     r, v, err = host(*sg.propagate(rec, dt, "fp64"))
     check_fp64(r, v, err, ro, vo, eo)
@@ -200,12 +204,22 @@ def test_deep_code_3_near_parabolic():
     assert (eo == 3).sum() > 50
     rec = sg.init(dev(el), ref_jd=REF)
     r, v, err = host(*sg.propagate(rec, dev(t), "fp64"))
-    # codes decided by the lunar-solar eccentricity change (3) and by the
-    # resonance flags (7) are exact; these sets lie outside the model's domain
-    # (near-parabolic), so only codes are compared
-    same = (eo == 3) | (eo == 7)
+    # these sets lie outside the model's domain (near-parabolic), so only codes
+    # are compared.  Codes decided by the lunar-solar eccentricity change (3)
+    # are exact for the non-resonant sets.  In the resonant ones the
+    # integration diverges (n reaches +-1 rad/min within a day, the resonant
+    # longitude 1e8 rad) and rounding decides the later codes on either side:
+    # there, codes need only be valid, with NaN states.
+    with oracle.reference_jd(REF):
+        res = oracle.init_constants(el)["irez"] != 0
+    assert res.sum() >= 5
+    res = np.repeat(res[:, None], t.size, axis=1)
+    same = (eo == 3) & ~res
+    assert same.sum() > 50
     assert np.array_equal(err[same], eo[same])
-    assert np.all(np.isnan(r[:, err == 3]))
+    assert set(np.unique(err[res]).tolist()) <= {0, 1, 2, 3, 4, 6}
+    bad = (err != 0) & (err != 6)
+    assert np.all(np.isnan(r[:, bad]))
 
 
 def test_near_earth_plan_after_reinitialisation_with_deep_sets():

@@ -120,7 +120,7 @@ def crafted_elements():
     add(bstar=float("nan"))
     add(inc=math.pi)                                              # retrograde equatorial (1 + cos i guard)
     add(inc=0.0)
-    add(n0=2 * math.pi / 1436.0, e0=2e-4, inc=0.01)                # resonant deep space (24 h): code 7
+    add(n0=2 * math.pi / 1436.0, e0=2e-4, inc=0.01)                # resonant deep space (24 h)
     add(n0=2 * math.pi / 718.0, e0=0.7, inc=1.1)                   # resonant deep space (12 h, e >= 0.5)
     return np.array(cols, dtype=np.float64).T.copy()
 
@@ -190,7 +190,7 @@ def test_edge_cases_and_error_codes_fp64():
     assert np.all(well[[5, 6, 7, 9, 10, 15]] | ~((eo[[5, 6, 7, 9, 10, 15]] == 0) | (eo[[5, 6, 7, 9, 10, 15]] == 6)))
     assert np.max(np.abs(r[:, well] - ro[:, well])) <= 1e-6
     assert np.max(np.abs(v[:, well] - vo[:, well])) <= 1e-9
-    assert {0, 1, 2, 6, 7} <= set(np.unique(eo).tolist())
+    assert {0, 1, 2, 6} <= set(np.unique(eo).tolist())
 
 
 def test_negative_semilatus_rectum_code4():
