@@ -270,3 +270,40 @@ def test_near_earth_plan_after_reinitialisation_with_deep_sets():
             check_mixed(r[:, keep], v[:, keep], err[keep], ro2[:, keep], vo2[:, keep], eo2[keep],
                         np.repeat(mix[1], lens)[keep])
         plan.close()
+
+
+def test_resonance_long_times_and_reach():
+    """Resonant sets (24 h and 12 h classes) from a minute to ten years from
+    epoch, across integrator steps, and beyond the integrator's reach of ten
+    Julian years: codes bit-exact (2 with a NaN state beyond the reach, as for
+    a NaN time), FP64 states within 1e-6 km and 1e-9 km/s plus ten times the
+    oracle's own spread under 1e-15 relative perturbations of the elements
+    (7,305 steps amplify rounding: up to ~1e-5 km for a Molniya orbit at ten
+    years)."""
+    from test_gpu_parity import conditioning
+    ke = oracle.ke()
+    cols = []
+    for a, e, inc, node, argp, mo, ep in ((42164.2, 1e-4, 0.0, 0.0, 0.0, 1.2, 0.0), (42150.0, 5e-4, 0.02, 1.0, 2.0, 3.0, 1.5),
+                                          (26600.0, 0.72, 1.107, 0.7, 1.3, 0.2, 0.0), (26560.0, 0.6, 1.1, 2.0, 4.0, 1.0, -2.25)):
+        n = math.sqrt(398600.8 / a ** 3) * 60.0
+        cols.append([n, e, inc, node, argp, mo, 0.0, ep])
+    el = np.array(cols, dtype=np.float64).T.copy()
+    assert list(oracle.init_constants(el)["irez"]) == [1, 1, 2, 2]
+    Y = 525960.0
+    t = np.array([-10 * Y - 1440.0, -10 * Y + 1.0, -Y, -3000.0, -1.0, 0.0, 1.0, 719.999, 720.0, 720.001, 7 * 1440.0,
+                  Y, 5 * Y, 10 * Y - 1.0, 10 * Y + 1440.0, float("nan")])
+    say(f"[gpu] resonant sets over +-10 years, n={el.shape[1]} T={t.size}")
+    rec = sg.init(dev(el))
+    r, v, err = host(*sg.propagate(rec, dev(t), "fp64"))
+    ro, vo, eo, codes, stable, move = conditioning(el, t)
+    assert np.array_equal(err, eo)
+    tsince = t[None, :] - 1440.0 * el[7][:, None]
+    beyond = ~(np.abs(tsince) <= 10 * Y)
+    assert np.all(eo[beyond] == 2) and np.all(eo[~beyond] == 0)
+    assert np.all(np.isnan(r[:, beyond])) and np.all(np.isnan(v[:, beyond]))
+    ok = ~beyond
+    dr = np.max(np.abs(r - ro), axis=0)[ok]
+    dv = np.max(np.abs(v - vo), axis=0)[ok]
+    mv = move[ok]
+    say(f"  max |dr| {dr.max():.2e} km, |dv| {dv.max():.2e} km/s; oracle spread up to {mv.max():.2e}")
+    assert np.all(dr <= 1e-6 + 10 * mv) and np.all(dv <= 1e-9 + 10e-3 * mv)
