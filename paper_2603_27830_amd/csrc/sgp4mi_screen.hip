@@ -388,21 +388,30 @@ __global__ void __launch_bounds__(256)
   const int32_t end = b + 1 < h.nb ? c[b + 1] : c[b];
   const double xi = vi.x, yi = vi.y;
   const int64_t pi = int64_t(i) * T + k;
-  for (int32_t q2 = int32_t(q) + 1; q2 < end; ++q2) {
-    const float2 vj = sxy[q2];
-    const double xj = vj.x, yj = vj.y;
-    if (!(fabs(xj - xi) < D + 1.2e-7 * (fabs(xi) + fabs(xj)))) continue;
-    if (!(fabs(yj - yi) < D + 1.2e-7 * (fabs(yi) + fabs(yj)))) continue;
-    const int32_t j = sidx[q2];
-    const int64_t pj = int64_t(j) * T + k;
-    const double d2 = dist2(r, P, pi, pj);
-    if (d2 < D2) {
-      const unsigned long long e = atomicAdd(count, 1ull);
-      if (int64_t(e) < cap) {
-        pairs[3 * e] = i < j ? i : j;
-        pairs[3 * e + 1] = i < j ? j : i;
-        pairs[3 * e + 2] = int32_t(k);
-        dist[e] = sqrt(d2);
+  // candidates in groups of eight: the group's loads are issued together (a
+  // position past the bucket's end reads as NaN and fails the tests)
+  constexpr int kU = 8;
+  for (int32_t q0 = int32_t(q) + 1; q0 < end; q0 += kU) {
+    float2 vj[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      vj[u] = q0 + u < end ? sxy[q0 + u] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const double xj = vj[u].x, yj = vj[u].y;
+      if (!(fabs(xj - xi) < D + 1.2e-7 * (fabs(xi) + fabs(xj)))) continue;
+      if (!(fabs(yj - yi) < D + 1.2e-7 * (fabs(yi) + fabs(yj)))) continue;
+      const int32_t j = sidx[q0 + u];
+      const int64_t pj = int64_t(j) * T + k;
+      const double d2 = dist2(r, P, pi, pj);
+      if (d2 < D2) {
+        const unsigned long long e = atomicAdd(count, 1ull);
+        if (int64_t(e) < cap) {
+          pairs[3 * e] = i < j ? i : j;
+          pairs[3 * e + 1] = i < j ? j : i;
+          pairs[3 * e + 2] = int32_t(k);
+          dist[e] = sqrt(d2);
+        }
       }
     }
   }

@@ -154,3 +154,21 @@ def test_mega_constellation_snapshot_sound_and_complete_on_a_subset():
     eo, _ = osc.screen(r[:, :sub, :], D)
     mine = ev[(i < sub) & (j < sub)]
     assert np.array_equal(mine, eo)
+
+
+def test_device_memory_path_many_times():
+    """12,000 satellites x 1,000 times (the on-chip path's largest n, and a
+    device-memory layout of 1,000 time rows): the device-memory path's events
+    equal the on-chip path's over all times, and the oracle's at sampled
+    times."""
+    n, T, D = 12_000, 1000, 12.0
+    r = shell_points(n, T, seed=123, planted=600).astype(np.float32)
+    say(f"[gpu] screen n={n} T={T}: device-memory path against the on-chip path")
+    ev2, d2, tot2 = gpu_events(r, D, mode=2)
+    ev1, d1, tot1 = gpu_events(r, D, mode=1)
+    say(f"  events {tot2} (device memory), {tot1} (on chip)")
+    assert tot1 == tot2 == len(ev1) and tot1 > 600
+    assert np.array_equal(ev1, ev2) and np.array_equal(d1, d2)
+    times = [0, 1, 429, 430, 431, 859, 860, 861, 999]
+    m = check(r, D, times=set(times), mode=2)
+    assert m > 0
