@@ -216,8 +216,8 @@ DEEP_REF_JD = 2461053.5
 # (fraction, semi-major axis km, eccentricity range, inclination deg range):
 # navigation-constellation MEO, transfer orbits (low inclinations included, so
 # that the deep-space model's low-inclination form is met), other non-resonant
-# high orbits, and the two resonant classes the library flags (24 h: near-
-# geosynchronous; 12 h with e >= 0.5: Molniya-type).
+# high orbits, and the two resonant classes of the deep-space model (24 h:
+# near-geosynchronous; 12 h with e >= 0.5: Molniya-type).
 DEEP_CLASSES = (
     (0.25, 26560.0, (0.0, 0.02), (54.0, 56.0)),      # GPS-like 12 h, e < 0.5: not resonant
     (0.15, 29600.0, (0.0, 0.01), (55.0, 57.0)),      # Galileo-like
