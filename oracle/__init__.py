@@ -64,6 +64,8 @@ def lib():
         L.oracle_init.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
         L.oracle_jacobian_points.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp, _u8p]
         L.oracle_vjp.argtypes = [_dp, ctypes.c_int64, _dp, _dp, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_int]
+        L.oracle_vjp_ragged.argtypes = [_dp, ctypes.c_int64, _dp, _i64p, _dp, ctypes.c_int64, _dp, _dp, _dp,
+                                        ctypes.c_int]
         L.oracle_count_ops.argtypes = [_dp, _dp, ctypes.c_double, _u64p]
         L.oracle_set_reference_jd.argtypes = [ctypes.c_double, ctypes.c_double]
         L.oracle_reference_jd.restype = ctypes.c_double
@@ -171,6 +173,19 @@ def vjp(elem, t, gr, gv=None, grav=None, nthreads=1):
     gv = None if gv is None else _f64(gv).reshape(3, n * T)
     out = np.empty((7, n))
     _check(lib().oracle_vjp(_p(g), n, _p(elem), _p(t), T, _p(gr), _p(gv), _p(out), int(nthreads)))
+    return out
+
+
+def vjp_ragged(elem, offsets, t, gr, gv=None, grav=None, nthreads=1):
+    """Dual-number VJP over CSR time lists: gelem[7, n]; gr, gv [3, nnz]."""
+    elem = _f64(elem); t = _f64(t); g = _grav(grav)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n, nnz = elem.shape[1], t.shape[0]
+    gr = _f64(gr).reshape(3, nnz)
+    gv = None if gv is None else _f64(gv).reshape(3, nnz)
+    out = np.empty((7, n))
+    _check(lib().oracle_vjp_ragged(_p(g), n, _p(elem), _p(offsets, _i64p), _p(t), nnz, _p(gr), _p(gv), _p(out),
+                                   int(nthreads)))
     return out
 
 

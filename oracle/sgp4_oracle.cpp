@@ -1227,6 +1227,39 @@ int oracle_vjp(const double* grav, int64_t n, const double* elem, const double* 
   return 0;
 }
 
+// Vector-Jacobian product over CSR time lists: satellite i's points are
+// offsets[i] .. offsets[i+1]-1, at times t[p]; gelem[7][n] as for oracle_vjp
+// with the cotangent rows gr[c][p], gv[c][p] (gv nullable).
+int oracle_vjp_ragged(const double* grav, int64_t n, const double* elem, const int64_t* offsets, const double* t,
+                      int64_t nnz, const double* gr, const double* gv, double* gelem, int nthreads) {
+  Gravity g;
+  if (int rc = make_gravity(grav, &g)) return rc;
+  if (n < 0 || nnz < 0 || offsets[0] != 0 || offsets[n] != nnz) return -3;
+  for (int64_t i = 0; i < n; ++i) if (offsets[i + 1] < offsets[i]) return -3;
+  parallel_for(n, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      Dual el[kNElem];
+      double epoch;
+      load_elements(elem, n, i, el, &epoch);
+      for (int q = 0; q < kNElem; ++q) el[q].d[q] = 1.0;
+      Sat<Dual> c = sgp4_init<Dual>(g, el, epoch);
+      double acc[kNElem] = {0};
+      for (int64_t p = offsets[i]; p < offsets[i + 1]; ++p) {
+        Dual rr[3], vv[3];
+        int code = sgp4_point(g, c, t[p] - 1440.0 * epoch, rr, vv, nullptr);
+        if (code != 0 && code != 6) continue;
+        for (int q = 0; q < 3; ++q)
+          for (int m = 0; m < kNElem; ++m) {
+            acc[m] += gr[q * nnz + p] * rr[q].d[m];
+            if (gv) acc[m] += gv[q * nnz + p] * vv[q].d[m];
+          }
+      }
+      for (int m = 0; m < kNElem; ++m) gelem[m * n + i] = acc[m];
+    }
+  });
+  return 0;
+}
+
 // Arithmetic the definition performs for one point (initialisation excluded):
 // out[8] = {add/sub, mul, div, sqrt, cbrt, sin/cos, atan2, floor}.
 int oracle_count_ops(const double* grav, const double* elem1 /*[8]*/, double tmin, uint64_t* out8) {

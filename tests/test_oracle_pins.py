@@ -952,3 +952,33 @@ def test_vjp_equals_contracted_jacobian():
                                                                                 gv.reshape(3, -1))
     want = want.reshape(7, 8, 6).sum(axis=2)
     assert np.allclose(g, want, rtol=1e-12, atol=0)
+
+
+def test_ragged_vjp_equals_per_satellite_contracted_jacobian():
+    """The VJP over CSR time lists (empty lists included) is, per satellite,
+    the cotangents contracted with the dual-number Jacobian at that
+    satellite's own points; on a dense-shaped CSR it equals the dense VJP."""
+    c = synth.config1(9, 1)
+    rng = np.random.default_rng(8)
+    lens = np.array([0, 3, 7, 1, 0, 12, 5, 2, 4])
+    offsets = np.zeros(10, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    nnz = int(offsets[-1])
+    t = rng.uniform(-500.0, 3000.0, nnz)
+    gr = rng.normal(size=(3, nnz))
+    gv = rng.normal(size=(3, nnz))
+    g = oracle.vjp_ragged(c.elem, offsets, t, gr, gv)
+    sat = np.repeat(np.arange(9), lens)
+    J, _, _, err = oracle.jacobian_points(c.elem, sat, t)
+    ok = (err == 0) | (err == 6)
+    per = np.einsum("kcm,ck->mk", J[:, :3, :], gr) + np.einsum("kcm,ck->mk", J[:, 3:, :], gv)
+    want = np.zeros((7, 9))
+    np.add.at(want.T, sat[ok], per[:, ok].T)
+    assert np.allclose(g, want, rtol=1e-12, atol=0)
+    assert np.all(g[:, lens == 0] == 0.0)
+    # dense-shaped lists: the dense VJP
+    d = synth.config1(5, 4)
+    gr2 = rng.normal(size=(3, 5, 4))
+    off2 = np.arange(6, dtype=np.int64) * 4
+    g2 = oracle.vjp_ragged(d.elem, off2, np.tile(d.t, 5), gr2.reshape(3, -1))
+    assert np.array_equal(g2, oracle.vjp(d.elem, d.t, gr2))
