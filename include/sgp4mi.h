@@ -334,6 +334,22 @@ void sgp4_plan_destroy(sgp4_plan* plan);
 int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
              const void* gr, const void* gv, double* gelem, void* stream);
 
+/* Vector-Jacobian product over per-satellite time lists (section 5, as
+ * sgp4_vjp; the lists are those of sgp4_propagate_ragged: satellite i's
+ * points are offsets[i] .. offsets[i+1]-1 at times t[p], an orbit
+ * determination's irregular observation times): gelem[m][i] = sum over
+ * satellite i's points p and components c of gr[c][p] * d r_c/d theta_m +
+ * gv[c][p] * d v_c/d theta_m.  offsets: device int64 [n + 1], non-decreasing
+ * from 0 to nnz; each satellite's two offsets are clamped to [0, nnz] (and its
+ * end to at least its start), so malformed offsets read nothing outside t, gr
+ * and gv (the gradient then covers the clamped lists).  t: device float64
+ * [nnz]; gr, gv device [3][nnz] of double (FP64) or float (FP32_MIXED), gv
+ * nullable.  Codes, deep space, precisions and limits as for sgp4_vjp; an
+ * empty list gives a zero column.  A dense grid given as lists (offsets[i] =
+ * i T, t repeated) gives sgp4_vjp's result bit for bit. */
+int sgp4_vjp_ragged(int64_t n, const double* elem, const void* consts, const int64_t* offsets, const double* t,
+                    int64_t nnz, int precision, const void* gr, const void* gv, double* gelem, void* stream);
+
 /* Jacobian of the dense propagation (section 5: the state's sensitivity to the
  * elements, as for state-transition matrices and covariance propagation):
  * jac[(c * 7 + m) * n*T + i*T + j] = d s_c / d theta_m at satellite i, time j,

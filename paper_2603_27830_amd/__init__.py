@@ -20,7 +20,7 @@ import torch
 from . import _native
 from ._native import SGP4Error, PLAN_AUTOTUNE, PLAN_GRAPH, REC_CHECKSUM, REC_MISMATCH, REC_FIELD
 
-__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "SGP4Function", "PRECISIONS",
+__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "vjp_ragged", "SGP4Function", "PRECISIONS",
            "SGP4Error", "consts_bytes"]
 
 PRECISIONS = {"fp64": _native.SGP4_FP64, "fp32": _native.SGP4_FP32, "mixed": _native.SGP4_FP32_MIXED}
@@ -354,6 +354,34 @@ def vjp(rec: Record, t: torch.Tensor, gr: torch.Tensor, gv: Optional[torch.Tenso
     with torch.cuda.device(rec.device):
         _native.check(_native.lib().sgp4_vjp(n, _ptr(rec.elem), _ptr(rec.consts), _ptr(t), T, p, _ptr(gr), _ptr(gv),
                                              _ptr(out), _stream(rec.device)), "sgp4_vjp")
+    return out
+
+
+def vjp_ragged(rec: Record, offsets: torch.Tensor, t: torch.Tensor, gr: torch.Tensor,
+               gv: Optional[torch.Tensor] = None, precision="fp64"):
+    """Vector-Jacobian product over per-satellite time lists (CSR offsets
+    int64 [n + 1], times float64 [nnz], cotangents [3, nnz]): float64 [7, n]."""
+    p = _prec(precision)
+    _need(offsets, torch.int64, "offsets", rec.device)
+    _need(t, torch.float64, "t", rec.device)
+    if offsets.numel() != rec.n + 1:
+        raise ValueError("offsets must hold n + 1 entries")
+    dt = _out_dtype(p)
+    n, nnz = rec.n, int(t.numel())
+    gr = gr.contiguous()
+    _need(gr, dt, "gr", rec.device)
+    if gr.numel() != 3 * nnz:
+        raise ValueError("gr must have 3*nnz elements")
+    if gv is not None:
+        gv = gv.contiguous()
+        _need(gv, dt, "gv", rec.device)
+        if gv.numel() != 3 * nnz:
+            raise ValueError("gv must have 3*nnz elements")
+    out = torch.empty((7, n), dtype=torch.float64, device=rec.device)
+    with torch.cuda.device(rec.device):
+        _native.check(_native.lib().sgp4_vjp_ragged(n, _ptr(rec.elem), _ptr(rec.consts), _ptr(offsets), _ptr(t), nnz,
+                                                    p, _ptr(gr), _ptr(gv), _ptr(out), _stream(rec.device)),
+                      "sgp4_vjp_ragged")
     return out
 
 

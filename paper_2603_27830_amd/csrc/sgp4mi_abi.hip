@@ -43,6 +43,9 @@ hipError_t launch_ragged(int precision, int mode, bool deep, const void* consts,
 hipError_t launch_any_deep(const void* consts, int64_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* consts, const double* t, int64_t T,
                       const void* gr, const void* gv, double* gelem, hipStream_t s);
+hipError_t launch_vjp_ragged(int precision, int64_t n, const double* elem, const void* consts, const int64_t* offsets,
+                             const double* t, int64_t nnz, const void* gr, const void* gv, double* gelem,
+                             hipStream_t s);
 hipError_t launch_jacobian(int precision, int64_t n, const double* elem, const void* consts, const double* t,
                            int64_t T, double* jac, hipStream_t s);
 }  // namespace sgp4mi
@@ -596,6 +599,17 @@ int sgp4_vjp(int64_t n, const double* elem, const void* consts, const double* t,
   if (n == 0) return SGP4_OK;
   if (!elem || !consts || !gelem || (T > 0 && (!t || !gr))) return SGP4_E_ARG;
   return hip_status(launch_vjp(precision, n, elem, consts, t, T, gr, gv, gelem, static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_vjp_ragged(int64_t n, const double* elem, const void* consts, const int64_t* offsets, const double* t,
+                    int64_t nnz, int precision, const void* gr, const void* gv, double* gelem, void* stream) {
+  if (n < 0 || nnz < 0 || n > kMaxSats || mul_overflows(nnz, 3)) return SGP4_E_SIZE;
+  if (precision != SGP4_FP64 && precision != SGP4_FP32_MIXED) return SGP4_E_PRECISION;
+  if (!grid_fits(uint64_t(n), kVjpLanes)) return SGP4_E_SIZE;  // one workgroup per satellite
+  if (n == 0) return SGP4_OK;
+  if (!elem || !consts || !offsets || !gelem || (nnz > 0 && (!t || !gr))) return SGP4_E_ARG;
+  return hip_status(launch_vjp_ragged(precision, n, elem, consts, offsets, t, nnz, gr, gv, gelem,
+                                      static_cast<hipStream_t>(stream)));
 }
 
 int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,

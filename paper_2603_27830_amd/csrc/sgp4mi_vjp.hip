@@ -306,23 +306,26 @@ __device__ __forceinline__ uint32_t point_vjp(const SatC<TS, TP>& c, const Grav&
   return mrt < TP(1) ? 6u : 0u;
 }
 
+// One workgroup's satellite i: its points p0 + j for j < cnt, at times tt[j],
+// with cotangent rows of P entries (dense: p0 = i T, tt = t; CSR: p0 =
+// offsets[i], tt = t + p0).
 template <class TS, class TP>
-__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
-    vjp_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t, int64_t T,
-               const TP* __restrict__ gr, const TP* __restrict__ gv, double* __restrict__ gelem) {
+__device__ __forceinline__ void vjp_sat(const RecordView& rv, int64_t n, const double* __restrict__ elem, int64_t i,
+                                        int64_t p0, int64_t cnt, int64_t P, const double* __restrict__ tt,
+                                        const TP* __restrict__ gr, const TP* __restrict__ gv,
+                                        double* __restrict__ gelem) {
   constexpr int kWaves = kVjpBlock / 64;
   __shared__ double part[kWaves][kNRec];
   __shared__ double cbar[kNRec];
-  const int64_t i = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, i);
   const Grav g = load_grav(rv);
   double acc[kNRec];
 #pragma unroll
   for (int k = 0; k < kNRec; ++k) acc[k] = 0.0;
-  const int64_t P = n * T;
-  for (int64_t j = threadIdx.x; j < T; j += kVjpBlock) {
-    const int64_t p = i * T + j;
+  const double* t = tt;
+  for (int64_t j = threadIdx.x; j < cnt; j += kVjpBlock) {
+    const int64_t p = p0 + j;
     const TP grp[3] = {gr[p], gr[P + p], gr[2 * P + p]};
     TP gvp[3] = {TP(0), TP(0), TP(0)};
     if (gv) {
@@ -364,6 +367,29 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
     }
     gelem[m * n + i] = out;
   }
+}
+
+template <class TS, class TP>
+__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
+    vjp_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t, int64_t T,
+               const TP* __restrict__ gr, const TP* __restrict__ gv, double* __restrict__ gelem) {
+  const int64_t i = blockIdx.x;
+  vjp_sat<TS, TP>(rv, n, elem, i, i * T, T, n * T, t, gr, gv, gelem);
+}
+
+// CSR time lists: satellite i's points offsets[i] .. offsets[i+1]-1.  Each
+// workgroup clamps its two offsets to [0, nnz] (and the end to at least the
+// start), so malformed offsets never read outside t, gr or gv.
+template <class TS, class TP>
+__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
+    vjp_ragged_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const int64_t* __restrict__ offsets,
+                      const double* __restrict__ t, int64_t nnz, const TP* __restrict__ gr,
+                      const TP* __restrict__ gv, double* __restrict__ gelem) {
+  const int64_t i = blockIdx.x;
+  int64_t lo = offsets[i], hi = offsets[i + 1];
+  lo = lo < 0 ? 0 : (lo > nnz ? nnz : lo);
+  hi = hi < lo ? lo : (hi > nnz ? nnz : hi);
+  vjp_sat<TS, TP>(rv, n, elem, i, lo, hi - lo, nnz, t + lo, gr, gv, gelem);
 }
 
 // Jacobian of the dense propagation (paper section 5: the state's sensitivity
@@ -796,6 +822,22 @@ hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* 
   } else if (precision == 2) {
     hipLaunchKernelGGL((vjp_kernel<double, float>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n, elem, t, T,
                        static_cast<const float*>(gr), static_cast<const float*>(gv), gelem);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_ragged(int precision, int64_t n, const double* elem, const void* consts, const int64_t* offsets,
+                             const double* t, int64_t nnz, const void* gr, const void* gv, double* gelem,
+                             hipStream_t s) {
+  const RecordView rv = view_of(consts, n);
+  if (precision == 0) {
+    hipLaunchKernelGGL((vjp_ragged_kernel<double, double>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n, elem,
+                       offsets, t, nnz, static_cast<const double*>(gr), static_cast<const double*>(gv), gelem);
+  } else if (precision == 2) {
+    hipLaunchKernelGGL((vjp_ragged_kernel<double, float>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n, elem,
+                       offsets, t, nnz, static_cast<const float*>(gr), static_cast<const float*>(gv), gelem);
   } else {
     return hipErrorInvalidValue;
   }

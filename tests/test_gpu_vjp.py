@@ -233,3 +233,69 @@ def test_vjp_full_size_differentiation_workload():
     err_same = rel_err_per_sat(g32s, g64s)
     say(f"  mixed vs fp64 (same cotangent) on all satellites: {err_same:.3e}")
     assert err_same <= 1e-4
+
+
+def test_vjp_ragged_matches_dual_oracle_dense_and_clamped_offsets():
+    """VJP over per-satellite time lists (empty lists, a deep-space satellite
+    and a simplified-drag set among them): FP64 against the oracle's ragged
+    dual-number VJP to 1e-8 relative per satellite, FP32-mixed against FP64
+    for the same cotangent to 1e-4; empty lists give zero columns, the
+    deep-space satellite NaN; a dense grid given as lists equals sgp4_vjp bit
+    for bit; malformed offsets give the gradient of the clamped lists."""
+    cat = synth.config1(80, 1)
+    el = cat.elem.copy()
+    el[:, 7] = synth.config5(8, 1).elem[:, 3]
+    el[7, 7] = 0.0
+    ke = oracle.ke()
+    el[0, 11] = ke * ((6378.135 + 200.0) / 6378.135) ** -1.5     # perigee below 220 km: simplified drag
+    rng = np.random.default_rng(31)
+    lens = rng.integers(0, 60, el.shape[1])
+    lens[[0, 5, 40]] = 0
+    offsets = np.zeros(el.shape[1] + 1, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    nnz = int(offsets[-1])
+    t = np.concatenate([np.sort(rng.uniform(-500.0, 4000.0, L)) for L in lens])
+    gr = rng.normal(size=(3, nnz))
+    gv = rng.normal(size=(3, nnz)) * 1e3
+    say(f"[gpu] vjp ragged n={el.shape[1]} nnz={nnz}")
+    rec = sg.init(dev(el))
+    g64 = sg.vjp_ragged(rec, dev(offsets), dev(t), dev(gr), dev(gv), "fp64").cpu().numpy()
+    g32 = sg.vjp_ragged(rec, dev(offsets), dev(t), dev(gr).float(), dev(gv).float(), "mixed").cpu().numpy()
+    want = oracle.vjp_ragged(el, offsets, t, gr, gv)
+    deep = np.zeros(el.shape[1], bool)
+    deep[7] = True
+    assert np.all(np.isnan(g64[:, deep])) and np.all(np.isnan(g32[:, deep]))
+    empty = lens == 0
+    assert np.all(g64[:, empty] == 0.0) and np.all(g32[:, empty] == 0.0)
+    use = ~deep & ~empty
+    e64 = rel_err_per_sat(g64[:, use], want[:, use])
+    e32 = rel_err_per_sat(g32[:, use], g64[:, use])
+    say(f"  fp64 vs oracle {e64:.2e}, mixed vs fp64 {e32:.2e}")
+    assert e64 <= 1e-8 and e32 <= 1e-4
+    # a dense grid given as lists: the dense kernel's result, bit for bit
+    d = synth.config1(32, 20)
+    gd = rng.normal(size=(3, d.n, d.T))
+    recd = sg.init(dev(d.elem))
+    dense = sg.vjp(recd, dev(d.t), dev(gd), None, "fp64")
+    lists = sg.vjp_ragged(recd, dev(np.arange(d.n + 1, dtype=np.int64) * d.T), dev(np.tile(d.t, d.n)),
+                          dev(gd.reshape(3, -1)), None, "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(dense, lists)
+    # malformed offsets (decreasing, negative, past nnz): each satellite's
+    # clamped range, never an out-of-range read
+    bad = offsets.copy()
+    bad[3] = bad[5] + 7          # decreasing afterwards
+    bad[10] = -40
+    bad[50] = nnz + 100
+    gb = sg.vjp_ragged(rec, dev(bad), dev(t), dev(gr), dev(gv), "fp64").cpu().numpy()
+    for i in range(el.shape[1]):
+        lo = min(max(int(bad[i]), 0), nnz)
+        hi = min(max(int(bad[i + 1]), lo), nnz)
+        if deep[i]:
+            assert np.all(np.isnan(gb[:, i]))
+            continue
+        wi = oracle.vjp_ragged(el[:, i:i + 1], np.array([0, hi - lo]), t[lo:hi], gr[:, lo:hi], gv[:, lo:hi])[:, 0]
+        if hi == lo:
+            assert np.all(gb[:, i] == 0.0)
+        else:
+            assert rel_err_per_sat(gb[:, i:i + 1], wi[:, None]) <= 1e-8, i
