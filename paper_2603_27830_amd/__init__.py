@@ -20,8 +20,8 @@ import torch
 from . import _native
 from ._native import SGP4Error, PLAN_AUTOTUNE, PLAN_GRAPH, REC_CHECKSUM, REC_MISMATCH, REC_FIELD
 
-__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "vjp_ragged", "SGP4Function", "PRECISIONS",
-           "SGP4Error", "consts_bytes"]
+__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "vjp_ragged", "SGP4Function",
+           "SGP4RaggedFunction", "PRECISIONS", "SGP4Error", "consts_bytes"]
 
 PRECISIONS = {"fp64": _native.SGP4_FP64, "fp32": _native.SGP4_FP32, "mixed": _native.SGP4_FP32_MIXED}
 
@@ -423,3 +423,28 @@ class SGP4Function(torch.autograd.Function):
         g = torch.zeros((8, ctx.rec.n), dtype=torch.float64, device=ctx.rec.device)
         g[:7] = g7
         return g, None, None, None
+
+
+class SGP4RaggedFunction(torch.autograd.Function):
+    """(elem [8, n], offsets [n + 1], t [nnz]) -> (r [3, nnz], v [3, nnz], err
+    [nnz]) over per-satellite time lists; backward through the ragged VJP
+    kernel (no gradient for the epoch row, the offsets or the times)."""
+
+    @staticmethod
+    def forward(ctx, elem, offsets, t, precision="fp64", grav=None):
+        rec = init(elem.detach().contiguous(), grav)
+        r, v, err = propagate_ragged(rec, offsets, t, precision)
+        ctx.rec, ctx.offsets, ctx.t, ctx.precision = rec, offsets, t, precision
+        ctx.mark_non_differentiable(err)
+        return r, v, err
+
+    @staticmethod
+    def backward(ctx, gr, gv, _gerr):
+        p = ctx.precision
+        dt = _out_dtype(_prec(p))
+        if gr is None:
+            gr = torch.zeros((3, ctx.t.numel()), dtype=dt, device=ctx.rec.device)
+        g7 = vjp_ragged(ctx.rec, ctx.offsets, ctx.t, gr.to(dt), None if gv is None else gv.to(dt), p)
+        g = torch.zeros((8, ctx.rec.n), dtype=torch.float64, device=ctx.rec.device)
+        g[:7] = g7
+        return g, None, None, None, None

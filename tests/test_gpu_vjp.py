@@ -299,3 +299,24 @@ def test_vjp_ragged_matches_dual_oracle_dense_and_clamped_offsets():
             assert np.all(gb[:, i] == 0.0)
         else:
             assert rel_err_per_sat(gb[:, i:i + 1], wi[:, None]) <= 1e-8, i
+
+
+def test_ragged_autograd_gradient_equals_direct_vjp_call():
+    """SGP4RaggedFunction: a loss on the ragged states, backward through the
+    ragged VJP, equals the direct sgp4_vjp_ragged call for the same cotangent,
+    bit for bit, in both precisions."""
+    cat = synth.config1(40, 1)
+    rng = np.random.default_rng(13)
+    lens = rng.integers(0, 30, cat.n)
+    offsets = np.zeros(cat.n + 1, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    t = np.concatenate([np.sort(rng.uniform(0.0, 2880.0, L)) for L in lens])
+    for prec in ("fp64", "mixed"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        w = dev(rng.normal(size=(3, t.size))).to(dt)
+        elem = dev(cat.elem).requires_grad_(True)
+        r, v, _ = sg.SGP4RaggedFunction.apply(elem, dev(offsets), dev(t), prec)
+        (r * w).sum().backward()
+        g = sg.vjp_ragged(sg.init(dev(cat.elem)), dev(offsets), dev(t), w, None, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(elem.grad[:7], g) and torch.all(elem.grad[7] == 0), prec
