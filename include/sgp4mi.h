@@ -364,6 +364,17 @@ int sgp4_vjp_ragged(int64_t n, const double* elem, const void* consts, const int
 int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const double* t, int64_t T, int precision,
                   double* jac, void* stream);
 
+/* Jacobian over per-satellite time lists (section 5, as sgp4_jacobian; the
+ * lists as for sgp4_vjp_ragged): jac[(c * 7 + m) * nnz + p] = d s_c /
+ * d theta_m at CSR point p of satellite i (offsets[i] <= p < offsets[i+1]),
+ * time t[p].  jac: device float64 [6][7][nnz], NaN as for sgp4_jacobian;
+ * every point is written when the offsets are valid (non-decreasing from 0 to
+ * nnz); each satellite's offsets are clamped as for sgp4_vjp_ragged, so
+ * malformed ones never write outside jac (positions no clamped list covers
+ * are then left as they were).  Precisions and limits as for sgp4_jacobian. */
+int sgp4_jacobian_ragged(int64_t n, const double* elem, const void* consts, const int64_t* offsets, const double* t,
+                         int64_t nnz, int precision, double* jac, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ import torch
 from . import _native
 from ._native import SGP4Error, PLAN_AUTOTUNE, PLAN_GRAPH, REC_CHECKSUM, REC_MISMATCH, REC_FIELD
 
-__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "vjp_ragged", "SGP4Function",
+__all__ = ["Record", "init", "propagate", "propagate_ragged", "RaggedPlan", "vjp", "vjp_ragged", "jacobian_ragged", "SGP4Function",
            "SGP4RaggedFunction", "PRECISIONS", "SGP4Error", "consts_bytes"]
 
 PRECISIONS = {"fp64": _native.SGP4_FP64, "fp32": _native.SGP4_FP32, "mixed": _native.SGP4_FP32_MIXED}
@@ -398,6 +398,27 @@ def jacobian(rec: Record, t: torch.Tensor, precision="fp64", out: Optional[torch
     with torch.cuda.device(rec.device):
         _native.check(_native.lib().sgp4_jacobian(n, _ptr(rec.elem), _ptr(rec.consts), _ptr(t), T, p, _ptr(out),
                                                   _stream(rec.device)), "sgp4_jacobian")
+    return out
+
+
+def jacobian_ragged(rec: Record, offsets: torch.Tensor, t: torch.Tensor, precision="fp64",
+                    out: Optional[torch.Tensor] = None):
+    """Jacobian over per-satellite time lists (CSR offsets int64 [n + 1], times
+    float64 [nnz]): float64 [6, 7, nnz], NaN at points whose code is 1, 2, 4 or 7."""
+    p = _prec(precision)
+    _need(offsets, torch.int64, "offsets", rec.device)
+    _need(t, torch.float64, "t", rec.device)
+    if offsets.numel() != rec.n + 1:
+        raise ValueError("offsets must hold n + 1 entries")
+    nnz = int(t.numel())
+    if out is None:
+        out = torch.empty((6, 7, nnz), dtype=torch.float64, device=rec.device)
+    elif out.dtype != torch.float64 or out.numel() != 42 * nnz or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of 42*nnz elements")
+    with torch.cuda.device(rec.device):
+        _native.check(_native.lib().sgp4_jacobian_ragged(rec.n, _ptr(rec.elem), _ptr(rec.consts), _ptr(offsets),
+                                                         _ptr(t), nnz, p, _ptr(out), _stream(rec.device)),
+                      "sgp4_jacobian_ragged")
     return out
 
 

@@ -51,6 +51,7 @@ SIGNATURES = [
     ("sgp4_plan_destroy", None, [_vp]),
     ("sgp4_vjp", _int, [_i64, _vp, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp]),
     ("sgp4_vjp_ragged", _int, [_i64, _vp, _vp, _vp, _vp, _i64, _int, _vp, _vp, _vp, _vp]),
+    ("sgp4_jacobian_ragged", _int, [_i64, _vp, _vp, _vp, _vp, _i64, _int, _vp, _vp]),
     ("sgp4_jacobian", _int, [_i64, _vp, _vp, _vp, _i64, _int, _vp, _vp]),
 ]
 

@@ -46,6 +46,8 @@ hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* 
 hipError_t launch_vjp_ragged(int precision, int64_t n, const double* elem, const void* consts, const int64_t* offsets,
                              const double* t, int64_t nnz, const void* gr, const void* gv, double* gelem,
                              hipStream_t s);
+hipError_t launch_jacobian_ragged(int precision, int64_t n, const double* elem, const void* consts,
+                                  const int64_t* offsets, const double* t, int64_t nnz, double* jac, hipStream_t s);
 hipError_t launch_jacobian(int precision, int64_t n, const double* elem, const void* consts, const double* t,
                            int64_t T, double* jac, hipStream_t s);
 }  // namespace sgp4mi
@@ -620,6 +622,17 @@ int sgp4_jacobian(int64_t n, const double* elem, const void* consts, const doubl
   if (n == 0 || T == 0) return SGP4_OK;
   if (!elem || !consts || !t || !jac) return SGP4_E_ARG;
   return hip_status(launch_jacobian(precision, n, elem, consts, t, T, jac, static_cast<hipStream_t>(stream)));
+}
+
+int sgp4_jacobian_ragged(int64_t n, const double* elem, const void* consts, const int64_t* offsets, const double* t,
+                         int64_t nnz, int precision, double* jac, void* stream) {
+  if (n < 0 || nnz < 0 || n > kMaxSats || mul_overflows(nnz, 42)) return SGP4_E_SIZE;
+  if (precision != SGP4_FP64 && precision != SGP4_FP32_MIXED) return SGP4_E_PRECISION;
+  if (!grid_fits(uint64_t(n), kVjpLanes)) return SGP4_E_SIZE;  // one workgroup per satellite
+  if (n == 0 || nnz == 0) return SGP4_OK;
+  if (!elem || !consts || !offsets || !t || !jac) return SGP4_E_ARG;
+  return hip_status(launch_jacobian_ragged(precision, n, elem, consts, offsets, t, nnz, jac,
+                                           static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -758,12 +758,14 @@ __device__ __forceinline__ void jacobian_pass(const SatC<TS, TP>& c, const Grav&
     }
 }
 
+// One workgroup's satellite i: its points p0 + j for j < cnt at times tt[j],
+// columns of P entries (dense: p0 = i T, tt = t; CSR: p0 = offsets[i], tt =
+// t + p0).
 template <class TS, class TP>
-__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
-    jacobian_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t,
-                    int64_t T, double* __restrict__ jac) {
+__device__ __forceinline__ void jac_sat(const RecordView& rv, int64_t n, const double* __restrict__ elem, int64_t i,
+                                        int64_t p0, int64_t cnt, int64_t P, const double* __restrict__ tt,
+                                        double* __restrict__ jac) {
   __shared__ double dc[7][kNRec];
-  const int64_t i = blockIdx.x;
   const uint32_t scode = rv.slots[i].info & kInfoCodeMask;
   if (threadIdx.x < 7) {
     const int m = threadIdx.x;
@@ -786,9 +788,9 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
   // the constants are read after the duals' registers are free again
   const SatC<TS, TP> c = load_sat<TS, TP, false>(rv, i);
   const Grav g = load_grav(rv);
-  const int64_t P = n * T;
-  for (int64_t j = threadIdx.x; j < T; j += kVjpBlock) {
-    const int64_t p = i * T + j;
+  const double* t = tt;
+  for (int64_t j = threadIdx.x; j < cnt; j += kVjpBlock) {
+    const int64_t p = p0 + j;
     // the sensitivities are read from LDS where each step uses them: without
     // this fence the compiler would hoist all 238 loop-invariant loads into
     // registers ahead of the loop
@@ -797,6 +799,27 @@ __global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
     asm volatile("" ::: "memory");
     jacobian_pass<TS, TP, Dirs<4, 3>>(c, g, t[j], dc, jac, P, p);
   }
+}
+
+template <class TS, class TP>
+__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
+    jacobian_kernel(RecordView rv, int64_t n, const double* __restrict__ elem, const double* __restrict__ t,
+                    int64_t T, double* __restrict__ jac) {
+  const int64_t i = blockIdx.x;
+  jac_sat<TS, TP>(rv, n, elem, i, i * T, T, n * T, t, jac);
+}
+
+// CSR time lists, offsets clamped per workgroup as for the ragged VJP.
+template <class TS, class TP>
+__global__ void __launch_bounds__(kVjpBlock, kVjpBlocksPerCU<TP>)
+    jacobian_ragged_kernel(RecordView rv, int64_t n, const double* __restrict__ elem,
+                           const int64_t* __restrict__ offsets, const double* __restrict__ t, int64_t nnz,
+                           double* __restrict__ jac) {
+  const int64_t i = blockIdx.x;
+  int64_t lo = offsets[i], hi = offsets[i + 1];
+  lo = lo < 0 ? 0 : (lo > nnz ? nnz : lo);
+  hi = hi < lo ? lo : (hi > nnz ? nnz : hi);
+  jac_sat<TS, TP>(rv, n, elem, i, lo, hi - lo, nnz, t + lo, jac);
 }
 
 hipError_t launch_jacobian(int precision, int64_t n, const double* elem, const void* consts, const double* t,
@@ -822,6 +845,21 @@ hipError_t launch_vjp(int precision, int64_t n, const double* elem, const void* 
   } else if (precision == 2) {
     hipLaunchKernelGGL((vjp_kernel<double, float>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n, elem, t, T,
                        static_cast<const float*>(gr), static_cast<const float*>(gv), gelem);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobian_ragged(int precision, int64_t n, const double* elem, const void* consts,
+                                  const int64_t* offsets, const double* t, int64_t nnz, double* jac, hipStream_t s) {
+  const RecordView rv = view_of(consts, n);
+  if (precision == 0) {
+    hipLaunchKernelGGL((jacobian_ragged_kernel<double, double>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n,
+                       elem, offsets, t, nnz, jac);
+  } else if (precision == 2) {
+    hipLaunchKernelGGL((jacobian_ragged_kernel<double, float>), dim3(unsigned(n)), dim3(kVjpBlock), 0, s, rv, n,
+                       elem, offsets, t, nnz, jac);
   } else {
     return hipErrorInvalidValue;
   }

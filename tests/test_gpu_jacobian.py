@@ -112,3 +112,56 @@ def test_jacobian_rejects_plain_fp32():
     rec = sg.init(dev(synth.config0().elem))
     with pytest.raises(Exception):
         sg.jacobian(rec, dev(synth.config0().t), "fp32")
+
+
+def test_jacobian_ragged_oracle_dense_and_vjp():
+    """Jacobian over per-satellite time lists (empty lists and a deep-space
+    satellite among them): FP64 against the oracle's dual-number Jacobian at
+    the same points to 1e-8 of each column's scale, mixed against FP64 to
+    1e-4, NaN at every point of the deep-space satellite; contracted with a
+    cotangent it equals sgp4_vjp_ragged to 1e-10; a dense grid given as lists
+    equals sgp4_jacobian bit for bit."""
+    cat = synth.config1(50, 1)
+    el = cat.elem.copy()
+    el[:, 9] = synth.config5(12, 1).elem[:, 2]
+    el[7, 9] = 0.0
+    rng = np.random.default_rng(41)
+    lens = rng.integers(0, 40, el.shape[1])
+    lens[[0, 20]] = 0
+    offsets = np.zeros(el.shape[1] + 1, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    nnz = int(offsets[-1])
+    t = np.concatenate([np.sort(rng.uniform(-300.0, 3000.0, L)) for L in lens])
+    say(f"[gpu] jacobian ragged n={el.shape[1]} nnz={nnz}")
+    rec = sg.init(dev(el))
+    J64 = sg.jacobian_ragged(rec, dev(offsets), dev(t), "fp64").cpu().numpy()
+    J32 = sg.jacobian_ragged(rec, dev(offsets), dev(t), "mixed").cpu().numpy()
+    sat = np.repeat(np.arange(el.shape[1]), lens)
+    ref, _, _, err = oracle.jacobian_points(el, sat, t)
+    ref = np.transpose(ref, (1, 2, 0))  # [6, 7, nnz]
+    deep = sat == 9
+    assert deep.sum() > 0 and np.all(np.isnan(J64[:, :, deep])) and np.all(np.isnan(J32[:, :, deep]))
+    valid = ((err == 0) | (err == 6)) & ~deep
+    e64 = column_error(J64, ref, valid)
+    e32 = column_error(J32, J64, valid)
+    say(f"  fp64 vs oracle {e64:.2e}, mixed vs fp64 {e32:.2e}")
+    assert e64 <= 1e-8 and e32 <= 1e-4
+    # the contraction with a cotangent is the ragged VJP
+    gr = rng.normal(size=(3, nnz))
+    gv = rng.normal(size=(3, nnz)) * 1e3
+    g = sg.vjp_ragged(rec, dev(offsets), dev(t), dev(gr), dev(gv), "fp64").cpu().numpy()
+    Jv = np.where(np.isnan(J64), 0.0, J64)
+    contr = np.einsum("cmp,cp->mp", Jv[:3], gr) + np.einsum("cmp,cp->mp", Jv[3:], gv)
+    want = np.zeros((7, el.shape[1]))
+    np.add.at(want.T, sat, contr.T)
+    keep = np.ones(el.shape[1], bool)
+    keep[9] = False
+    scale = np.abs(want[:, keep]).max(axis=1, keepdims=True) + 1e-300
+    assert np.max(np.abs(g[:, keep] - want[:, keep]) / scale) <= 1e-10
+    # a dense grid given as lists
+    d = synth.config1(20, 33)
+    recd = sg.init(dev(d.elem))
+    dense = sg.jacobian(recd, dev(d.t), "fp64")
+    lists = sg.jacobian_ragged(recd, dev(np.arange(d.n + 1, dtype=np.int64) * d.T), dev(np.tile(d.t, d.n)), "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(dense.reshape(6, 7, -1), lists)
