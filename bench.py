@@ -687,6 +687,16 @@ def main():
             log(f"[bench] c3 {name}: {c3.nnz / k3:.3e} pts/s ({plan.describe()})")
             plan.close()
             torch.cuda.empty_cache()
+        # Gradient over the same lists: the ragged VJP for a unit cotangent on r
+        # (every point's forward pass recomputed and swept in reverse).
+        for name in ("fp64", "mixed"):
+            gdt = torch.float64 if name == "fp64" else torch.float32
+            gr3 = torch.ones((3, c3.nnz), dtype=gdt, device=dev)
+            kv = kernel_time(lambda: sg.vjp_ragged(rec3, off3, t3, gr3, None, name), torch, reps=3)
+            paths["c3_ragged_1M"][f"vjp_{name}"] = {"points_per_s": c3.nnz / kv, "kernel_ms": kv * 1e3}
+            log(f"[bench] c3 vjp {name}: {c3.nnz / kv:.3e} pts/s, {kv * 1e3:.2f} ms")
+            del gr3
+            torch.cuda.empty_cache()
 
     head = paths.get("mixed") or paths[names[0]]
     head_name = "mixed" if "mixed" in paths else names[0]
