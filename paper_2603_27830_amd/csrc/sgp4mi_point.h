@@ -383,34 +383,46 @@ __device__ __forceinline__ uint32_t sgp4_tail(const Grav& g, TP a, TP e, TS M, T
 // Tesseral resonance of the 24 h and 12 h classes: the mean motion and the
 // resonant mean longitude integrated from epoch in steps of 720 minutes
 // toward t while a whole step remains (second-order Taylor steps), then the
-// Taylor polynomial over the remainder; double precision in every path.
-// Rates at (lambda, n, w): dn/dt = sum of a sin A - b cos A over the terms,
-// A = j w + k lambda and (a, b) the term's coefficient times the cosine and
-// sine of its phase; d2n/dt2 = dlambda/dt times the sum of k (a cos A +
-// b sin A); dlambda/dt = n + the rest of the argument's secular rate.
+// Taylor polynomial over the remainder; the integrator's state in double in
+// every path.  Rates at (lambda, n, w): dn/dt = sum of a sin A - b cos A over
+// the terms, A = j w + k lambda and (a, b) the term's coefficient times the
+// cosine and sine of its phase; d2n/dt2 = dlambda/dt times the sum of k (a cos
+// A + b sin A); dlambda/dt = n + the rest of the argument's secular rate.
+// TR: the type the rates are evaluated in.  The float paths take them in
+// float (hardware sine and cosine of the angle reduced in double): a relative
+// error of ~1e-7 in dn/dt, ~1e-11 rad/min^2, moves lambda by ~1e-9 rad over a
+// week, far below the float state's own rounding.
+template <class TR>
 __device__ __forceinline__ void res_rates(bool sync24, const double* d, double xli, double w, double xni,
                                           double* ndot, double* nddot, double* ldot) {
   const double* r = d + kDRc0;
-  double s1, c1;
-  sincos_rr(xli, &s1, &c1);
-  const double s2 = 2.0 * s1 * c1, c2 = 1.0 - 2.0 * s1 * s1;
-  double sn, cs;
+  TR s1, c1;
+  if constexpr (sizeof(TR) == 8)
+    sincos_rr(xli, &s1, &c1);
+  else
+    sincos_hw(xli, &s1, &c1);
+  const TR s2 = TR(2) * s1 * c1, c2 = TR(1) - TR(2) * s1 * s1;
+  TR sn, cs;
   if (sync24) {
     // 24 h: A = lambda, 2 lambda, 3 lambda
-    const double s3 = s1 * (3.0 - 4.0 * s1 * s1), c3 = c1 * (4.0 * c1 * c1 - 3.0);
-    sn = (r[0] * s1 - r[1] * c1) + (r[2] * s2 - r[3] * c2) + (r[4] * s3 - r[5] * c3);
-    cs = (r[0] * c1 + r[1] * s1) + 2.0 * (r[2] * c2 + r[3] * s2) + 3.0 * (r[4] * c3 + r[5] * s3);
+    const TR s3 = s1 * (TR(3) - TR(4) * s1 * s1), c3 = c1 * (TR(4) * c1 * c1 - TR(3));
+    sn = (TR(r[0]) * s1 - TR(r[1]) * c1) + (TR(r[2]) * s2 - TR(r[3]) * c2) + (TR(r[4]) * s3 - TR(r[5]) * c3);
+    cs = (TR(r[0]) * c1 + TR(r[1]) * s1) + TR(2) * (TR(r[2]) * c2 + TR(r[3]) * s2) +
+         TR(3) * (TR(r[4]) * c3 + TR(r[5]) * s3);
   } else {
     // 12 h: (j, k) = (2,1) (0,1) (1,1) (-1,1) (2,2) (0,2) (1,1) (-1,1) (1,2)
     // (-1,2); the third and seventh terms, and the fourth and eighth, share
     // their angle
-    double sw, cw;
-    sincos_rr(w, &sw, &cw);
-    const double sw2 = 2.0 * sw * cw, cw2 = 1.0 - 2.0 * sw * sw;
-    double s1x = 0.0, c1x = 0.0, s2x = 0.0, c2x = 0.0;  // k = 1 and k = 2 sums
-    auto term = [&](double a, double b, double sA, double cA, double* sk, double* ck) {
-      *sk += a * sA - b * cA;
-      *ck += a * cA + b * sA;
+    TR sw, cw;
+    if constexpr (sizeof(TR) == 8)
+      sincos_rr(w, &sw, &cw);
+    else
+      sincos_hw(w, &sw, &cw);
+    const TR sw2 = TR(2) * sw * cw, cw2 = TR(1) - TR(2) * sw * sw;
+    TR s1x = TR(0), c1x = TR(0), s2x = TR(0), c2x = TR(0);  // k = 1 and k = 2 sums
+    auto term = [&](double a, double b, TR sA, TR cA, TR* sk, TR* ck) {
+      *sk += TR(a) * sA - TR(b) * cA;
+      *ck += TR(a) * cA + TR(b) * sA;
     };
     term(r[0], r[1], sw2 * c1 + cw2 * s1, cw2 * c1 - sw2 * s1, &s1x, &c1x);
     term(r[2], r[3], s1, c1, &s1x, &c1x);
@@ -421,15 +433,16 @@ __device__ __forceinline__ void res_rates(bool sync24, const double* d, double x
     term(r[16], r[17], sw * c2 + cw * s2, cw * c2 - sw * s2, &s2x, &c2x);
     term(r[18], r[19], s2 * cw - c2 * sw, c2 * cw + s2 * sw, &s2x, &c2x);
     sn = s1x + s2x;
-    cs = c1x + 2.0 * c2x;
+    cs = c1x + TR(2) * c2x;
   }
   *ldot = xni + d[kDXfact];
-  *ndot = sn;
-  *nddot = cs * *ldot;
+  *ndot = double(sn);
+  *nddot = double(cs) * *ldot;
 }
 
 // Integrated (lambda, n) at t minutes after epoch; NaN beyond 10 years from
 // epoch or for t not finite (every lane's loop is bounded by that reach).
+template <class TR>
 __device__ __forceinline__ void res_integrate(bool sync24, const double* d, double t, double n0, double argp0,
                                               double argpdot, double* xl, double* nm) {
   if (!(fabs(t) <= kResMaxMin)) {
@@ -440,7 +453,7 @@ __device__ __forceinline__ void res_integrate(bool sync24, const double* d, doub
   const double h = t > 0.0 ? kResStepMin : -kResStepMin;
   const double hh = 0.5 * h * h;
   for (;;) {
-    res_rates(sync24, d, xli, argp0 + argpdot * atime, xni, &ndot, &nddot, &ldot);
+    res_rates<TR>(sync24, d, xli, argp0 + argpdot * atime, xni, &ndot, &nddot, &ldot);
     if (!(fabs(t - atime) >= kResStepMin)) break;
     xli = xli + ldot * h + ndot * hh;
     xni = xni + ndot * h + nddot * hh;
@@ -484,7 +497,7 @@ __device__ __forceinline__ uint32_t deep_point(const SatC<TS, TP>& c, const Grav
     // a from the integrated mean motion (code 2 if it is not positive)
     const double td = t_abs - c.epoch_min;
     double xl, nm;
-    res_integrate(rcls == 1.0, d, td, double(c.n0pp), double(c.argp0), double(c.argpdot), &xl, &nm);
+    res_integrate<TP>(rcls == 1.0, d, td, double(c.n0pp), double(c.argp0), double(c.argpdot), &xl, &nm);
     const double th = d[kDGsto] + td * kEarthRot;
     const double theta = th - kTwoPi * floor(th * kInvTwoPi);
     if (rcls == 1.0)
