@@ -53,6 +53,18 @@ def test_argument_errors_need_no_gpu():
     assert L.sgp4_jacobian(-1, fake, fake, fake, 10, 0, fake, None) == E["SGP4_E_SIZE"]
     assert L.sgp4_jacobian(10, None, fake, fake, 10, 0, fake, None) == E["SGP4_E_ARG"]
     assert L.sgp4_jacobian(2**31 - 1, fake, fake, fake, 2**30, 0, fake, None) == E["SGP4_E_SIZE"]
+    # the per-satellite list forms of the VJP and the Jacobian
+    vr, jr = L.sgp4_vjp_ragged, L.sgp4_jacobian_ragged
+    assert vr(10, fake, fake, fake, fake, 100, 1, fake, None, fake, None) == E["SGP4_E_PRECISION"]
+    assert vr(-1, fake, fake, fake, fake, 100, 0, fake, None, fake, None) == E["SGP4_E_SIZE"]
+    assert vr(10, fake, fake, fake, fake, -1, 0, fake, None, fake, None) == E["SGP4_E_SIZE"]
+    assert vr(10, fake, fake, None, fake, 100, 0, fake, None, fake, None) == E["SGP4_E_ARG"]
+    assert vr(10, fake, fake, fake, fake, 100, 0, None, None, fake, None) == E["SGP4_E_ARG"]
+    assert vr(0, None, None, None, None, 0, 0, None, None, None, None) == 0
+    assert jr(10, fake, fake, fake, fake, 100, 1, fake, None) == E["SGP4_E_PRECISION"]
+    assert jr(10, fake, fake, fake, fake, 2**60, 0, fake, None) == E["SGP4_E_SIZE"]
+    assert jr(10, fake, fake, fake, None, 100, 0, fake, None) == E["SGP4_E_ARG"]
+    assert jr(10, fake, fake, fake, fake, 0, 0, None, None) == 0
     # null pointers
     assert L.sgp4_propagate(None, 10, fake, 10, 0, fake, fake, fake, None) == E["SGP4_E_ARG"]
     assert L.sgp4_propagate(fake, 10, fake, 10, 0, fake, None, fake, None) == E["SGP4_E_ARG"]
@@ -142,6 +154,8 @@ def test_launch_extent_limits_are_checked_on_the_host():
     # one 256-lane workgroup per satellite: n < 2^24
     assert L.sgp4_vjp(2**24, fake, fake, fake, 1, 0, fake, None, fake, None) == E["SGP4_E_SIZE"]
     assert L.sgp4_jacobian(2**24, fake, fake, fake, 1, 0, fake, None) == E["SGP4_E_SIZE"]
+    assert L.sgp4_vjp_ragged(2**24, fake, fake, fake, fake, 1, 0, fake, None, fake, None) == E["SGP4_E_SIZE"]
+    assert L.sgp4_jacobian_ragged(2**24, fake, fake, fake, fake, 1, 0, fake, None) == E["SGP4_E_SIZE"]
     # 2^26 tiles of 64 lanes = 2^32 lanes
     assert px(fake, 2**26, fake, 64, 0, fake, fake, fake, 256 | SCALAR | TILES, None) == E["SGP4_E_SIZE"]
     # satellite-by-time grid: n workgroups of 256 lanes
